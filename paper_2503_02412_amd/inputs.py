@@ -1,0 +1,270 @@
+"""Seeded synthetic inputs shared by the oracle side and the GPU side.
+
+This module holds workload definitions (map sizes, footprints, constants) and
+terrain / trajectory generators.  It contains none of the assessment method's
+arithmetic: no footprint tables, no fitting, no pose or risk maths.  Both the
+CPU oracle (``oracle/``) and the HIP library (``paper_2503_02412_amd``) are fed
+from here so that they see bit-identical inputs.
+
+All draws come from ``numpy.random.Generator(PCG64(seed))`` in a fixed order.
+The paper evaluates on an external procedural terrain generator and on real
+terrain (Sec. VII-A); neither is available, so these generators stand in for
+them, with the sizes and value ranges of the workloads listed below.
+
+Map convention: ``H[iy, ix]`` row-major, float32, NaN = unknown; cell
+``(ix, iy)`` has its centre at map-local metres ``((ix + 0.5) res, (iy + 0.5) res)``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, asdict, replace
+
+import numpy as np
+
+# --------------------------------------------------------------------------
+# Workload presets.  Constants follow the paper where it gives them
+# (phi_x_max = phi_y_max = 0.52 rad, Sec. VII-B); the others (kappa_max,
+# weights, r_max, min_valid) are not given by the paper and are parameters.
+# --------------------------------------------------------------------------
+
+
+@dataclass(frozen=True)
+class Params:
+    width: int
+    height: int
+    resolution: float
+    n_yaw: int
+    fp_length: float
+    fp_width: float
+    fp_nl: int
+    fp_nw: int
+    fp_shape: int = 0          # 0 = rectangle, 1 = inscribed ellipse mask
+    kappa_max: float = 0.03
+    phi_x_max: float = 0.52
+    phi_y_max: float = 0.52
+    w_kappa: float = 1.0 / 3.0
+    w_phi_x: float = 1.0 / 3.0
+    w_phi_y: float = 1.0 / 3.0
+    risk_max: float = 0.5
+    min_valid: int = 3
+    precision: int = 0         # 0 = FP32, 1 = FP32 + FP64 for near-degenerate states
+    fit: int = 0               # 0 = least-squares plane, 1 = principal-component plane
+
+    def as_dict(self) -> dict:
+        return asdict(self)
+
+    def with_(self, **kw) -> "Params":
+        return replace(self, **kw)
+
+    @property
+    def n_states(self) -> int:
+        return self.width * self.height * self.n_yaw
+
+
+# 64x64 @ 0.1 m, 16 yaw bins, 0.6 x 0.4 m footprint on a 6 x 4 sample grid.
+CONFIG1 = Params(64, 64, 0.1, 16, 0.6, 0.4, 6, 4)
+# 200x200 @ 0.1 m, 36 yaw bins, 1.0 x 0.6 m footprint on a 20 x 12 grid.
+CONFIG2 = Params(200, 200, 0.1, 36, 1.0, 0.6, 20, 12)
+# Rolling window: 400x400 @ 0.05 m, 72 yaw bins, 1.0 x 0.6 m on 20 x 12.
+CONFIG3 = Params(400, 400, 0.05, 72, 1.0, 0.6, 20, 12)
+# Large map: 800x800 @ 0.05 m, 72 yaw bins, 2.0 x 1.2 m on 40 x 24.
+CONFIG5 = Params(800, 800, 0.05, 72, 2.0, 1.2, 40, 24)
+
+PRESETS = {"config1": CONFIG1, "config2": CONFIG2, "config3": CONFIG3, "config5": CONFIG5}
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# --------------------------------------------------------------------------
+# G1: sum of 8 random-direction sinusoids plus Gaussian noise.
+# --------------------------------------------------------------------------
+
+def sinusoid_terrain(width: int, height: int, res: float, seed: int, *,
+                     n_waves: int = 8, amp_max: float = 0.3,
+                     wl_min: float = 1.0, wl_max: float = 6.0,
+                     noise_sigma: float = 0.02) -> np.ndarray:
+    rng = _rng(seed)
+    alpha = rng.uniform(0.0, 2.0 * math.pi, n_waves)
+    amp = rng.uniform(0.0, amp_max, n_waves)
+    lam = rng.uniform(wl_min, wl_max, n_waves)
+    psi = rng.uniform(0.0, 2.0 * math.pi, n_waves)
+    noise = rng.normal(0.0, noise_sigma, (height, width))
+    xs = (np.arange(width) + 0.5) * res
+    ys = (np.arange(height) + 0.5) * res
+    X, Y = np.meshgrid(xs, ys)
+    h = np.zeros((height, width))
+    for a, A, l, p in zip(alpha, amp, lam, psi):
+        h += A * np.sin(2.0 * math.pi * (X * math.cos(a) + Y * math.sin(a)) / l + p)
+    return (h + noise).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# G2 / G3 / G5: fractal value noise + steps + NaN blobs.
+# --------------------------------------------------------------------------
+
+def _fade(t: np.ndarray) -> np.ndarray:
+    return t * t * t * (t * (t * 6.0 - 15.0) + 10.0)
+
+
+def value_noise(width: int, height: int, res: float, rng: np.random.Generator, *,
+                octaves: int = 4, base: float = 3.2, lacunarity: float = 2.0,
+                gain: float = 0.5) -> np.ndarray:
+    xs = (np.arange(width) + 0.5) * res
+    ys = (np.arange(height) + 0.5) * res
+    out = np.zeros((height, width))
+    spacing, amp = base, 1.0
+    for _ in range(octaves):
+        nxl = int(math.ceil(width * res / spacing)) + 2
+        nyl = int(math.ceil(height * res / spacing)) + 2
+        lat = rng.uniform(-1.0, 1.0, (nyl, nxl))
+        gx = xs / spacing
+        gy = ys / spacing
+        ix = np.floor(gx).astype(np.int64)
+        iy = np.floor(gy).astype(np.int64)
+        tx = _fade(gx - ix)[None, :]
+        ty = _fade(gy - iy)[:, None]
+        v00 = lat[iy[:, None], ix[None, :]]
+        v01 = lat[iy[:, None], ix[None, :] + 1]
+        v10 = lat[iy[:, None] + 1, ix[None, :]]
+        v11 = lat[iy[:, None] + 1, ix[None, :] + 1]
+        top = v00 + (v01 - v00) * tx
+        bot = v10 + (v11 - v10) * tx
+        out += amp * (top + (bot - top) * ty)
+        spacing /= lacunarity
+        amp *= gain
+    return out
+
+
+def _max_slope(h: np.ndarray, res: float) -> float:
+    gx = (h[1:-1, 2:] - h[1:-1, :-2]) / (2.0 * res)
+    gy = (h[2:, 1:-1] - h[:-2, 1:-1]) / (2.0 * res)
+    return float(np.sqrt(gx * gx + gy * gy).max())
+
+
+def add_steps(h: np.ndarray, res: float, rng: np.random.Generator, n_steps: int = 4,
+              lo: float = 0.1, hi: float = 0.3) -> np.ndarray:
+    height, width = h.shape
+    xs = (np.arange(width) + 0.5) * res
+    ys = (np.arange(height) + 0.5) * res
+    X, Y = np.meshgrid(xs, ys)
+    for _ in range(n_steps):
+        px = rng.uniform(0.0, width * res)
+        py = rng.uniform(0.0, height * res)
+        ang = rng.uniform(0.0, 2.0 * math.pi)
+        dh = rng.uniform(lo, hi)
+        side = (X - px) * math.cos(ang) + (Y - py) * math.sin(ang) > 0.0
+        h = h + dh * side
+    return h
+
+
+def add_holes(h: np.ndarray, rng: np.random.Generator, frac: float, blob: int = 10) -> np.ndarray:
+    """Punch NaN blobs of ``blob`` four-connected cells until >= frac is NaN."""
+    height, width = h.shape
+    mask = np.zeros((height, width), dtype=bool)
+    target = int(math.ceil(frac * height * width))
+    steps = ((1, 0), (-1, 0), (0, 1), (0, -1))
+    count = 0
+    while count < target:
+        y0 = int(rng.integers(0, height))
+        x0 = int(rng.integers(0, width))
+        cells = [(y0, x0)]
+        seen = {(y0, x0)}
+        guard = 0
+        while len(cells) < blob and guard < 1000:
+            guard += 1
+            cy, cx = cells[int(rng.integers(0, len(cells)))]
+            dy, dx = steps[int(rng.integers(0, 4))]
+            ny, nx = cy + dy, cx + dx
+            if 0 <= ny < height and 0 <= nx < width and (ny, nx) not in seen:
+                seen.add((ny, nx))
+                cells.append((ny, nx))
+        for cy, cx in cells:
+            if not mask[cy, cx]:
+                mask[cy, cx] = True
+                count += 1
+    out = h.copy()
+    out[mask] = np.nan
+    return out
+
+
+def fractal_terrain(width: int, height: int, res: float, seed: int, *,
+                    hole_frac: float = 0.05, max_slope_deg: float = 30.0,
+                    n_steps: int = 4) -> np.ndarray:
+    rng = _rng(seed)
+    h = value_noise(width, height, res, rng)
+    s = _max_slope(h, res)
+    if s > 0:
+        h = h * (math.tan(math.radians(max_slope_deg)) / s)
+    h = add_steps(h, res, rng, n_steps=n_steps)
+    if hole_frac > 0:
+        h = add_holes(h, rng, hole_frac)
+    return h.astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# Workload maps.
+# --------------------------------------------------------------------------
+
+def config1_map(seed: int = 1) -> np.ndarray:
+    return sinusoid_terrain(64, 64, 0.1, seed)
+
+
+def config2_map(seed: int = 2) -> np.ndarray:
+    return fractal_terrain(200, 200, 0.1, seed, hole_frac=0.05)
+
+
+def config5_map(seed: int = 5) -> np.ndarray:
+    return fractal_terrain(800, 800, 0.05, seed, hole_frac=0.15)
+
+
+def trajectory(seed: int = 3, n_steps: int = 100, step_m: float = 0.5) -> np.ndarray:
+    """Robot (x, y) positions in metres: start at 0, then n_steps moves of
+    step_m in a uniformly random heading.  Returns (n_steps + 1, 2) float64."""
+    rng = _rng(seed)
+    heading = rng.uniform(0.0, 2.0 * math.pi, n_steps)
+    pos = np.zeros((n_steps + 1, 2))
+    pos[1:, 0] = np.cumsum(step_m * np.cos(heading))
+    pos[1:, 1] = np.cumsum(step_m * np.sin(heading))
+    return pos
+
+
+@dataclass
+class World:
+    """A large world height grid in which a rolling window moves.
+
+    World cell (gx, gy) has its centre at ((gx + 0.5) res, (gy + 0.5) res)
+    metres, and is stored at ``heights[gy - gy0, gx - gx0]``."""
+    heights: np.ndarray
+    gx0: int
+    gy0: int
+    res: float
+
+    def window(self, ox: int, oy: int, w: int, h: int) -> np.ndarray:
+        """Heights of world cells [ox, ox+w) x [oy, oy+h); NaN outside the grid."""
+        out = np.full((h, w), np.nan, dtype=np.float32)
+        ys0, xs0 = oy - self.gy0, ox - self.gx0
+        H, W = self.heights.shape
+        y_lo, y_hi = max(0, ys0), min(H, ys0 + h)
+        x_lo, x_hi = max(0, xs0), min(W, xs0 + w)
+        if y_lo < y_hi and x_lo < x_hi:
+            out[y_lo - ys0:y_hi - ys0, x_lo - xs0:x_hi - xs0] = self.heights[y_lo:y_hi, x_lo:x_hi]
+        return out
+
+
+def rolling_world(params: Params = CONFIG3, seed: int = 3, n_steps: int = 100,
+                  hole_frac: float = 0.05) -> tuple[World, np.ndarray]:
+    """World grid covering the whole seeded trajectory plus one window of margin
+    on every side, built with the fractal generator at the window's resolution."""
+    traj = trajectory(seed, n_steps)
+    res = params.resolution
+    margin = max(params.width, params.height)
+    gx_lo = int(math.floor(traj[:, 0].min() / res)) - margin
+    gx_hi = int(math.floor(traj[:, 0].max() / res)) + margin
+    gy_lo = int(math.floor(traj[:, 1].min() / res)) - margin
+    gy_hi = int(math.floor(traj[:, 1].max() / res)) + margin
+    w, h = gx_hi - gx_lo + 1, gy_hi - gy_lo + 1
+    heights = fractal_terrain(w, h, res, seed + 1000, hole_frac=hole_frac,
+                              n_steps=4 * max(1, (w * h) // (400 * 400)))
+    return World(heights, gx_lo, gy_lo, res), traj

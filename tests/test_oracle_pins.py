@@ -1,0 +1,433 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+The paper prints no worked numeric example of Algorithm 1, so every pin here
+is derived: closed forms of Eq. 1-3 on planes, invariants of the method under
+yaw + pi, 90-degree map rotation, integer translation, height offset and
+mirroring, and brute force through library routines (scipy bilinear sampling,
+numpy least squares / symmetric eigensolver) on tiny maps with holes.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+from paper_2503_02412_amd import inputs as I
+
+ST_VALID, ST_CURV, ST_TILT, ST_DEGEN, ST_TRAV = 1, 2, 4, 8, 16
+
+
+def _golden_constants():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.txt")
+    vals = {}
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        name, value = line.split()[:2]
+        vals[name] = float(value)
+    return vals
+
+
+PAPER = _golden_constants()
+
+
+def closed_form(gx, gy, theta):
+    """Pose and tilt of a robot at yaw theta on the plane h = h0 + gx x + gy y.
+
+    The slope along the heading is b, across it (to the left) c.  The terrain
+    normal in the yaw frame is (-b, -c, 1)/s; y_b is orthogonal to the heading,
+    so sin(roll) = c / sqrt(1 + c^2); x_b is orthogonal to y_b and z_b, giving
+    sin(phi_x) = b / (sqrt(1 + c^2) s) and the Z-X-Y pitch below."""
+    b = gx * math.cos(theta) + gy * math.sin(theta)
+    c = -gx * math.sin(theta) + gy * math.cos(theta)
+    roll = math.atan(c)
+    pitch = -math.atan2(b, math.sqrt(1.0 + c * c))
+    phi_x = math.atan2(abs(b), math.sqrt((1.0 + c * c) ** 2 + b * b * c * c))
+    phi_y = math.atan(abs(c))
+    return b, c, roll, pitch, phi_x, phi_y
+
+
+def interior_mask(orc, p, margin=0):
+    dx0, dx1, dy0, dy1 = orc.reach(p)
+    m = np.zeros((p.height, p.width), bool)
+    m[-dy0 + margin:p.height - dy1 - margin, -dx0 + margin:p.width - dx1 - margin] = True
+    return m
+
+
+# --------------------------------------------------------------------------
+# Flat terrain and planes (Eq. 1-3 closed forms).
+# --------------------------------------------------------------------------
+
+def test_flat_map_is_level_and_riskless(orc):
+    p = I.CONFIG1
+    h = np.full((p.height, p.width), 1.5, np.float32)
+    r = orc.assess_rect(p, h)
+    assert np.all(r.status & ST_VALID)
+    assert np.max(np.abs(r.roll)) < 1e-12 and np.max(np.abs(r.pitch)) < 1e-12
+    assert np.max(np.abs(r.z - 1.5)) < 1e-12
+    assert np.max(r.risk) < 1e-12
+    assert np.all(r.status & ST_TRAV)
+
+
+def test_flat_map_with_holes_is_flat(orc):
+    p = I.CONFIG1
+    rng = np.random.default_rng(7)
+    h = np.full((p.height, p.width), 0.25, np.float32)
+    h[rng.random(h.shape) < 0.2] = np.nan
+    r = orc.assess_rect(p, h)
+    v = (r.status & ST_VALID) > 0
+    assert v.sum() > 0.5 * v.size
+    # Bilinear weights sum to 1 only up to FP64 rounding, hence the 1e-13 bound.
+    assert np.max(np.abs(r.roll[v])) < 1e-13 and np.max(np.abs(r.pitch[v])) < 1e-13
+    assert np.max(r.risk[v]) < 1e-13 and np.max(np.abs(r.z[v] - 0.25)) < 1e-13
+    assert np.all(np.isnan(r.z[~v])) and np.all(r.risk[~v] == 1.0)
+
+
+@pytest.mark.parametrize("a,b", [(3, 0), (0, -5), (2, 7), (-9, 4)])
+def test_quantised_plane_matches_closed_form_over_all_yaws(orc, a, b):
+    # h = (a ix + b iy) / 256 is exact in float32, so the fit is exact in FP64.
+    p = I.CONFIG1
+    iy, ix = np.mgrid[0:p.height, 0:p.width]
+    h = ((a * ix + b * iy) / 256.0).astype(np.float32)
+    gx, gy = a / (256.0 * p.resolution), b / (256.0 * p.resolution)
+    r = orc.assess_rect(p, h)
+    m = interior_mask(orc, p)
+    for k in range(p.n_yaw):
+        th = 2 * math.pi * k / p.n_yaw
+        _, _, roll, pitch, phx, phy = closed_form(gx, gy, th)
+        assert np.max(np.abs(r.roll[k][m] - roll)) < 1e-12
+        assert np.max(np.abs(r.pitch[k][m] - pitch)) < 1e-12
+        assert np.max(np.abs(r.phi_x[k][m] - phx)) < 1e-12
+        assert np.max(np.abs(r.phi_y[k][m] - phy)) < 1e-12
+        assert np.max(np.abs(r.z[k][m] - h[m])) < 1e-12
+        assert np.max(np.abs(r.kappa[k][m])) < 1e-12
+
+
+def test_worked_slopes_risk():
+    """Risk values of Algorithm 1 on 10 and 35 degree planes (w = 1/3, phi_max = 0.52
+    rad from Sec. VII-B), derived from the closed forms and checked on the oracle."""
+    import oracle
+    assert PAPER["phi_x_max"] == 0.52 and PAPER["phi_y_max"] == 0.52
+    p = I.CONFIG1
+    iy, ix = np.mgrid[0:p.height, 0:p.width]
+    m = interior_mask(oracle, p)
+    expect = {
+        10: {0: 0.111880080, 4: 0.111880080, 8: 0.111880080, 12: 0.111880080,
+             2: 0.157813961, 6: 0.157813961, 10: 0.157813961, 14: 0.157813961},
+        35: {0: 1.0, 4: 1.0, 8: 1.0, 12: 1.0, 2: 0.533157113, 6: 0.533157113},
+    }
+    for deg, table in expect.items():
+        g = math.tan(math.radians(deg))
+        h = (g * (ix + 0.5) * p.resolution).astype(np.float32)
+        r = oracle.assess_rect(p, h)
+        for k, risk in table.items():
+            assert np.max(np.abs(r.risk[k][m] - risk)) < 2e-6, (deg, k)
+        if deg == 10:
+            assert np.max(np.abs(r.pitch[0][m] + 0.174532925)) < 2e-6
+        else:
+            assert np.all(r.status[0][m] & ST_TILT)
+            assert np.max(np.abs(r.phi_x[2][m] - 0.371987899)) < 2e-6
+            assert np.max(np.abs(r.phi_y[2][m] - 0.459737197)) < 2e-6
+            assert np.max(np.abs(np.abs(r.pitch[2][m]) - 0.417613041)) < 2e-6
+
+
+# --------------------------------------------------------------------------
+# Invariants of the method.
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def g1():
+    return I.config1_map(1)
+
+
+def test_yaw_plus_pi_negates_roll_and_pitch(orc, g1):
+    p = I.CONFIG1
+    r = orc.assess_rect(p, g1)
+    K = p.n_yaw
+    for k in range(K // 2):
+        a, b = k, k + K // 2
+        v = (r.status[a] & ST_VALID) > 0
+        assert np.array_equal(v, (r.status[b] & ST_VALID) > 0)
+        assert np.max(np.abs(r.roll[a][v] + r.roll[b][v])) < 1e-12
+        assert np.max(np.abs(r.pitch[a][v] + r.pitch[b][v])) < 1e-12
+        assert np.max(np.abs(r.z[a][v] - r.z[b][v])) < 1e-12
+        assert np.max(np.abs(r.kappa[a][v] - r.kappa[b][v])) < 1e-12
+        assert np.max(np.abs(r.risk[a] - r.risk[b])) < 1e-12
+
+
+def test_rotation_by_90_degrees_shifts_yaw_by_quarter(orc, g1):
+    p = I.CONFIG1
+    N, K = p.width, p.n_yaw
+    a = np.arange(N)
+    hr = g1[(N - 1 - a)[None, :], a[:, None]]       # hr[y', x'] = h[N-1-x', y']
+    r0 = orc.assess_rect(p, g1)
+    r1 = orc.assess_rect(p, hr)
+    iy, ix = np.mgrid[0:N, 0:N]
+    for k in range(K):
+        k1 = (k + K // 4) % K
+        z1 = r1.z[k1][ix, N - 1 - iy]                # state (x, y) -> (N-1-y, x)
+        v = (r0.status[k] & ST_VALID) > 0
+        assert np.array_equal(v, (r1.status[k1][ix, N - 1 - iy] & ST_VALID) > 0)
+        assert np.max(np.abs(r0.z[k][v] - z1[v])) < 1e-12
+        assert np.max(np.abs(r0.roll[k][v] - r1.roll[k1][ix, N - 1 - iy][v])) < 1e-12
+        assert np.max(np.abs(r0.pitch[k][v] - r1.pitch[k1][ix, N - 1 - iy][v])) < 1e-12
+        assert np.max(np.abs(r0.risk[k] - r1.risk[k1][ix, N - 1 - iy])) < 1e-12
+
+
+def test_integer_translation_is_bitwise(orc, g1):
+    p = I.CONFIG1
+    tx, ty = 5, -3
+    h2 = np.full_like(g1, np.nan)
+    h2[max(0, ty):p.height + min(0, ty), max(0, tx):p.width + min(0, tx)] = \
+        g1[max(0, -ty):p.height - max(0, ty), max(0, -tx):p.width - max(0, tx)]
+    r0 = orc.assess_rect(p, g1, x0=10, y0=10, nx=40, ny=40)
+    r1 = orc.assess_rect(p, h2, x0=10 + tx, y0=10 + ty, nx=40, ny=40)
+    for f in ("z", "roll", "pitch", "risk", "kappa", "status"):
+        assert np.array_equal(getattr(r0, f), getattr(r1, f), equal_nan=(f != "status")), f
+
+
+def test_height_offset_shifts_z_only(orc, g1):
+    p = I.CONFIG1
+    hq = (np.round(g1.astype(np.float64) * 4096) / 4096).astype(np.float32)
+    r0 = orc.assess_rect(p, hq)
+    r1 = orc.assess_rect(p, hq + np.float32(1.0))
+    v = (r0.status & ST_VALID) > 0
+    assert np.max(np.abs(r1.z[v] - r0.z[v] - 1.0)) < 1e-12
+    for f in ("roll", "pitch", "risk", "kappa"):
+        assert np.max(np.abs(getattr(r1, f)[v] - getattr(r0, f)[v])) < 1e-11, f
+    assert np.array_equal(r0.status, r1.status)
+
+
+def test_y_mirror_negates_roll(orc, g1):
+    p = I.CONFIG1
+    N, K = p.height, p.n_yaw
+    hm = g1[::-1].copy()
+    r0 = orc.assess_rect(p, g1)
+    r1 = orc.assess_rect(p, hm)
+    for k in range(K):
+        km = (K - k) % K
+        v = (r0.status[k] & ST_VALID) > 0
+        assert np.max(np.abs(r0.roll[k][v] + r1.roll[km][::-1][v])) < 1e-12
+        assert np.max(np.abs(r0.pitch[k][v] - r1.pitch[km][::-1][v])) < 1e-12
+        assert np.max(np.abs(r0.z[k][v] - r1.z[km][::-1][v])) < 1e-12
+        assert np.max(np.abs(r0.risk[k] - r1.risk[km][::-1])) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Brute force through library routines on tiny maps.
+# --------------------------------------------------------------------------
+
+def brute_state(p, h, ix, iy, k):
+    """Samples by scipy bilinear interpolation, fit by numpy lstsq / eigh."""
+    th = 2 * math.pi * k / p.n_yaw
+    h0 = np.nan_to_num(h.astype(np.float64), nan=0.0)
+    bad = np.isnan(h).astype(np.float64)
+    pts, pq = [], []
+    for i in range(p.fp_nl):
+        for j in range(p.fp_nw):
+            u = (i + 0.5) * p.fp_length / p.fp_nl - p.fp_length / 2
+            v = (j + 0.5) * p.fp_width / p.fp_nw - p.fp_width / 2
+            if p.fp_shape == 1 and (2 * i + 1 - p.fp_nl) ** 2 * p.fp_nw ** 2 + \
+                    (2 * j + 1 - p.fp_nw) ** 2 * p.fp_nl ** 2 > (p.fp_nl * p.fp_nw) ** 2:
+                continue
+            o = np.array([(u * math.cos(th) - v * math.sin(th)) / p.resolution,
+                          (u * math.sin(th) + v * math.cos(th)) / p.resolution])
+            r = np.round(o)
+            o = np.where(np.abs(o - r) < 1e-6, r, o)
+            crd = [[iy + o[1]], [ix + o[0]]]
+            if ndi.map_coordinates(bad, crd, order=1, mode="constant", cval=1.0)[0] > 0:
+                continue
+            z = ndi.map_coordinates(h0, crd, order=1, mode="constant", cval=0.0)[0]
+            pts.append((u, v, z))
+            pq.append((i, j))
+    pts = np.array(pts).reshape(-1, 3)
+    n = len(pts)
+    if n < p.min_valid or np.linalg.matrix_rank(
+            np.c_[np.ones(n), pts[:, :2]], tol=1e-9) < 3:
+        return dict(valid=False, n=n)
+    A = np.c_[np.ones(n), pts[:, 0], pts[:, 1]]
+    sol, res, *_ = np.linalg.lstsq(A, pts[:, 2], rcond=None)
+    a, b, c = sol
+    tr = pts.var(axis=0).sum()
+    if p.fit == 0:
+        sse = float(np.sum((A @ sol - pts[:, 2]) ** 2))
+        kappa = sse / (n * (1 + b * b + c * c) * tr)
+        z = a
+    else:
+        w, V = np.linalg.eigh(np.cov(pts.T, bias=True))
+        nv = V[:, 0] * np.sign(V[2, 0])
+        kappa = w[0] / tr
+        b, c = -nv[0] / nv[2], -nv[1] / nv[2]
+        mu = pts.mean(axis=0)
+        z = mu[2] + (nv[0] * mu[0] + nv[1] * mu[1]) / nv[2]
+    phi_x = math.atan2(abs(b), math.sqrt((1 + c * c) ** 2 + b * b * c * c))
+    phi_y = math.atan(abs(c))
+    # Algorithm 1: curvature early-out, tilt early-out, then the weighted sum.
+    if kappa > p.kappa_max:
+        risk, bits = 1.0, ST_CURV
+    elif phi_x > p.phi_x_max or phi_y > p.phi_y_max:
+        risk, bits = 1.0, ST_TILT
+    else:
+        risk = (p.w_kappa * kappa / p.kappa_max + p.w_phi_x * phi_x / p.phi_x_max
+                + p.w_phi_y * phi_y / p.phi_y_max)
+        bits = 0
+    bits |= ST_VALID | (ST_TRAV if risk <= p.risk_max else 0)
+    near = (abs(kappa / p.kappa_max - 1) < 1e-9 or abs(phi_x - p.phi_x_max) < 1e-9
+            or abs(phi_y - p.phi_y_max) < 1e-9 or abs(risk - p.risk_max) < 1e-9)
+    return dict(valid=True, n=n, z=z, roll=math.atan(c),
+                pitch=-math.atan2(b, math.sqrt(1 + c * c)), kappa=kappa, risk=risk,
+                bits=bits, near=near)
+
+
+TINY = [
+    I.Params(12, 12, 0.1, 8, 0.6, 0.4, 6, 4),
+    I.Params(11, 13, 0.1, 8, 0.5, 0.3, 7, 5),
+    I.Params(12, 12, 0.1, 8, 0.6, 0.4, 6, 4, fp_shape=1),
+    I.Params(12, 12, 0.1, 8, 0.6, 0.4, 6, 4, fit=1),
+    I.Params(10, 12, 0.05, 12, 0.4, 0.3, 8, 6, fit=1, fp_shape=1),
+]
+
+
+def tiny_map(p, rng, rough):
+    if rough:
+        h = rng.uniform(-0.2, 0.2, (p.height, p.width))
+    else:
+        iy, ix = np.mgrid[0:p.height, 0:p.width] * p.resolution
+        g = rng.uniform(-0.4, 0.4, 2)
+        h = g[0] * ix + g[1] * iy + 0.03 * np.sin(3 * ix + 2 * iy) \
+            + rng.normal(0, 0.004, (p.height, p.width))
+    h = h.astype(np.float32)
+    h[rng.random(h.shape) < 0.12] = np.nan
+    return h
+
+
+@pytest.mark.parametrize("rough", [True, False])
+@pytest.mark.parametrize("pi", range(len(TINY)))
+def test_brute_force_tiny_maps(orc, pi, rough):
+    _check_brute(orc, pi, rough)
+
+
+def _check_brute(orc, pi, rough):
+    p = TINY[pi]
+    rng = np.random.default_rng(100 + pi + 50 * rough)
+    h = tiny_map(p, rng, rough)
+    r = orc.assess_rect(p, h)
+    n_checked = 0
+    kinds = set()
+    for k in range(p.n_yaw):
+        for iy in range(p.height):
+            for ix in range(p.width):
+                bf = brute_state(p, h, ix, iy, k)
+                assert r.n_valid[k, iy, ix] == bf["n"], (k, iy, ix)
+                assert bool(r.status[k, iy, ix] & ST_VALID) == bf["valid"], (k, iy, ix)
+                if not bf["valid"]:
+                    assert np.isnan(r.z[k, iy, ix]) and r.risk[k, iy, ix] == 1.0
+                    continue
+                n_checked += 1
+                assert abs(r.z[k, iy, ix] - bf["z"]) < 1e-9
+                assert abs(r.roll[k, iy, ix] - bf["roll"]) < 1e-9
+                assert abs(r.pitch[k, iy, ix] - bf["pitch"]) < 1e-9
+                assert abs(r.kappa[k, iy, ix] - bf["kappa"]) < 1e-9
+                if not bf["near"]:
+                    assert abs(r.risk[k, iy, ix] - bf["risk"]) < 1e-9
+                    assert (int(r.status[k, iy, ix]) & ~ST_DEGEN) == bf["bits"], (k, iy, ix)
+                kinds.add(bf["bits"])
+    assert n_checked > 100
+    # Both early-outs and the weighted-risk branch are exercised by some case.
+    return kinds
+
+
+def test_brute_force_covers_every_branch(orc):
+    # The brute-force cases above reach both early-outs and the weighted risk.
+    kinds = set()
+    for pi in range(len(TINY)):
+        for rough in (True, False):
+            p = TINY[pi]
+            h = tiny_map(p, np.random.default_rng(100 + pi + 50 * rough), rough)
+            st = orc.assess_rect(p, h).status
+            kinds |= set(int(b) & ~ST_DEGEN for b in np.unique(st))
+    assert any(b & ST_CURV for b in kinds) and any(b & ST_TILT for b in kinds)
+    assert any(b & ST_TRAV for b in kinds)
+    assert any((b & (ST_CURV | ST_TILT | ST_TRAV)) == 0 for b in kinds)
+
+
+def test_least_squares_curvature_bounds_principal_component(orc, g1):
+    p = I.CONFIG1
+    r0 = orc.assess_rect(p, g1)
+    r1 = orc.assess_rect(p.with_(fit=1), g1)
+    v = (r0.status & ST_VALID) > 0
+    assert np.all(r0.kappa[v] >= r1.kappa[v] - 1e-15)
+    # On a plane both fits coincide.
+    iy, ix = np.mgrid[0:p.height, 0:p.width]
+    h = ((3 * ix - 2 * iy) / 256.0).astype(np.float32)
+    a = orc.assess_rect(p, h)
+    b = orc.assess_rect(p.with_(fit=1), h)
+    for f in ("z", "roll", "pitch"):
+        assert np.max(np.abs(getattr(a, f) - getattr(b, f))) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# The exact gate and its hand-built cases.
+# --------------------------------------------------------------------------
+
+def _gate_map(finite_cells, val=0.1):
+    h = np.full((16, 16), np.nan, np.float32)
+    for (x, y) in finite_cells:
+        h[y, x] = val + 0.01 * x - 0.02 * y
+    return h
+
+
+def test_gate_single_valid_row_is_unknown(orc):
+    p = I.Params(16, 16, 0.1, 4, 0.6, 0.4, 6, 4)
+    cx = cy = 8
+    # Samples at theta = 0 sit at half-integer offsets (+-0.5, +-1.5, +-2.5) x (+-0.5, +-1.5).
+    # Cells of rows cy-1 and cy only: the six samples with v offset -0.5 are valid.
+    cells = [(x, y) for x in range(16) for y in (cy - 1, cy)]
+    r = orc.assess_list(p, _gate_map(cells), [cx], [cy], [0])
+    assert r.n_valid[0] == 6 and r.status[0] == 0 and np.isnan(r.z[0]) and r.risk[0] == 1.0
+
+
+def test_gate_three_noncollinear_samples_solve_exactly(orc):
+    p = I.Params(16, 16, 0.1, 4, 0.6, 0.4, 6, 4)
+    cx = cy = 8
+    blocks = [(-3, -2), (2, -2), (-3, 1)]          # lower-left corners of 2x2 cell blocks
+    cells = [(cx + bx + a, cy + by + b) for bx, by in blocks for a in (0, 1) for b in (0, 1)]
+    h = _gate_map(cells)
+    r = orc.assess_list(p, h, [cx], [cy], [0])
+    assert r.n_valid[0] == 3 and (r.status[0] & ST_VALID)
+    # The cells lie on h = 0.1 + 0.01 x - 0.02 y (grid units): exact plane through 3 points.
+    gx, gy = 0.01 / p.resolution, -0.02 / p.resolution
+    _, _, roll, pitch, _, _ = closed_form(gx, gy, 0.0)
+    assert abs(r.roll[0] - roll) < 1e-6 and abs(r.pitch[0] - pitch) < 1e-6
+    assert abs(r.z[0] - (0.1 + 0.01 * cx - 0.02 * cy)) < 1e-6
+    assert r.status[0] & ST_DEGEN
+
+
+def test_gate_two_samples_below_min_valid(orc):
+    p = I.Params(16, 16, 0.1, 4, 0.6, 0.4, 6, 4)
+    cx = cy = 8
+    blocks = [(-3, -2), (2, -2)]
+    cells = [(cx + bx + a, cy + by + b) for bx, by in blocks for a in (0, 1) for b in (0, 1)]
+    r = orc.assess_list(p, _gate_map(cells), [cx], [cy], [0])
+    assert r.n_valid[0] == 2 and r.status[0] == 0
+
+
+def test_out_of_map_samples_are_dropped(orc):
+    p = I.CONFIG1
+    h = np.zeros((p.height, p.width), np.float32)
+    r = orc.assess_list(p, h, [0, 63, 0, 32], [0, 63, 32, 32], [0, 0, 4, 0])
+    n_full = p.fp_nl * p.fp_nw
+    assert r.n_valid[3] == n_full
+    assert r.n_valid[0] < n_full and r.n_valid[1] < n_full and r.n_valid[2] < n_full
+    assert np.all(r.status & ST_VALID)
+
+
+def test_ellipse_mask_counts(orc):
+    p = I.Params(32, 32, 0.1, 4, 1.0, 0.6, 10, 6, fp_shape=1)
+    h = np.zeros((32, 32), np.float32)
+    r = orc.assess_list(p, h, [16], [16], [0])
+    expect = sum(1 for i in range(10) for j in range(6)
+                 if ((2 * i + 1 - 10) / 10) ** 2 + ((2 * j + 1 - 6) / 6) ** 2 <= 1.0)
+    assert r.n_valid[0] == expect < 60
