@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of the SE(2) traversability hot path on one MI355X.
+
+One step = one full-map assessment (every (x, y, yaw) state: footprint gather,
+plane fit, pose, risk) of the 200 x 200 @ 0.1 m map with 36 yaw bins and a
+1.0 x 0.6 m footprint sampled on 20 x 12 points (fractal terrain with steps and
+5% unknown blobs).  The map and the outputs stay resident in HBM; each step is
+one launch of the assessment kernel on the current stream, timed with HIP
+events on that stream.
+
+Prints ONE JSON line.  Extra fields report the rolling-window update of the
+400 x 400 @ 0.05 m, 72-bin window along a 100-move trajectory, the 800 x 800
+x 72 map with a 2.0 x 1.2 m footprint, and the FP64 CPU oracle on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2503_02412_amd import inputs as I  # noqa: E402
+
+METRIC = ("SE(2) cells/s and ms per 200×200×36 map; surrogate vs plain at matched error")
+VENDOR_FP32_PEAK_TFLOPS = 157.3       # 256 CU x 2.4 GHz x 64 lanes x 2 (FMA) x 2 (dual/packed)
+HBM_PEAK_GBS = 8000.0
+
+
+def flops_per_state(params) -> int:
+    """Algorithmic work: 16 flop per footprint sample (bilinear 9, moments 7)
+    plus 80 flop per state for the fit, pose and risk."""
+    n_s = params.fp_nl * params.fp_nw
+    return 16 * n_s + 80
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("seb_assess.hip", "seb_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2503_02412_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(workload)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_launches(torch, fn, steps: int, warmup: int):
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    stop.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps          # ms per launch
+
+
+def bench_rolling(torch, seb, n_moves: int = 100):
+    p = I.CONFIG3
+    W, H = p.width, p.height
+    world, traj = I.rolling_world(p, seed=3, n_steps=n_moves)
+    ctx = seb.Context(p)
+    win = seb.Window(ctx, traj[0, 0], traj[0, 1])
+    ox, oy, _, _ = win.origin()
+    win.reset(traj[0, 0], traj[0, 1], torch.from_numpy(world.window(ox, oy, W, H)).cuda())
+    # Stage every move's exposed cells in HBM before timing.
+    staged, origin = [], (ox, oy)
+    for s in range(1, n_moves + 1):
+        plan = seb.plan_window_move(p, origin[0], origin[1], *traj[s])
+        win_h = world.window(plan.new_origin_x, plan.new_origin_y, W, H)
+        dy = plan.new_origin_y - plan.old_origin_y
+        dx = plan.new_origin_x - plan.old_origin_x
+        if plan.full_reset:
+            cells = win_h.reshape(-1)
+        else:
+            rows = list(range(H - dy, H)) if dy > 0 else list(range(0, -dy))
+            cols = list(range(W - dx, W)) if dx > 0 else list(range(0, -dx))
+            rest = [y for y in range(H) if y not in set(rows)]
+            parts = [win_h[rows, :].reshape(-1)]
+            if cols:
+                parts.append(win_h[np.ix_(rest, cols)].reshape(-1))
+            cells = np.concatenate(parts)
+        staged.append(torch.from_numpy(np.ascontiguousarray(cells, np.float32)).cuda()
+                      if cells.size else None)
+        origin = (plan.new_origin_x, plan.new_origin_y)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_moves + 1)]
+    ev[0].record(stream)
+    states = 0
+    t0 = time.perf_counter()
+    for s in range(1, n_moves + 1):
+        states += win.update(*traj[s], staged[s - 1])
+        ev[s].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / n_moves
+    per = np.array([ev[s - 1].elapsed_time(ev[s]) for s in range(1, n_moves + 1)])
+    full_ms = time_launches(torch, lambda: ctx.assess(win.ring, win.out), 20, 3)
+    return {
+        "workload": "400x400 @0.05 m, 72 yaw bins, 1.0x0.6 m footprint on 20x12; "
+                    "100 moves of 0.5 m in random headings",
+        "update_ms_mean": float(per.mean()), "update_ms_median": float(np.median(per)),
+        "update_ms_max": float(per.max()), "update_wall_ms_mean": wall,
+        "full_recompute_ms": full_ms,
+        "states_recomputed_per_move": states / n_moves,
+        "fraction_of_full_map": states / n_moves / p.n_states,
+    }
+
+
+def bench_large(torch, seb):
+    p = I.CONFIG5
+    ctx = seb.Context(p)
+    h = torch.from_numpy(I.config5_map(5)).cuda()
+    out = seb.alloc_outputs(p)
+    ms = time_launches(torch, lambda: ctx.assess(h, out), 10, 2)
+    f = flops_per_state(p) * p.n_states
+    return {"workload": "800x800 @0.05 m, 72 yaw bins, 2.0x1.2 m footprint on 40x24, 15% holes",
+            "ms_per_map": ms, "cells_per_s": p.n_states / (ms * 1e-3),
+            "achieved_tflops": f / (ms * 1e-3) / 1e12,
+            "frac_of_vendor_fp32": f / (ms * 1e-3) / 1e12 / VENDOR_FP32_PEAK_TFLOPS}
+
+
+def cpu_baseline(params, hmap):
+    import oracle
+    threads = oracle.max_threads()
+    t0 = time.perf_counter()
+    oracle.assess_rect(params, hmap, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": params.n_states / dt, "unit": "SE(2) cells/s", "cores": threads,
+            "kind": "oracle", "seconds": dt,
+            "sample": "one full 200x200x36 map (1,440,000 states), FP64 oracle, OpenMP"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the assessment has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2503_02412_amd import seb
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    p = I.CONFIG2
+    hmap = I.config2_map(2)
+    ctx = seb.Context(p)
+    h = torch.from_numpy(hmap).cuda()
+    out = seb.alloc_outputs(p)
+    ms = time_launches(torch, lambda: ctx.assess(h, out), args.steps, args.warmup)
+
+    flops = flops_per_state(p) * p.n_states
+    achieved = flops / (ms * 1e-3) / 1e12
+    traffic = measured_traffic("config2")
+    result = {
+        "metric": METRIC,
+        "value": p.n_states / (ms * 1e-3),
+        "unit": "SE(2) cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "full-map SE(2) assessment, 200x200 @0.1 m, 36 yaw bins, "
+                               "1.0x0.6 m footprint on 20x12 samples, seeded fractal terrain "
+                               "with steps and 5% unknown blobs",
+                   "states_per_step": p.n_states, "precision": "fp32"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VENDOR_FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / VENDOR_FP32_PEAK_TFLOPS,
+                     "traffic": traffic},
+    }
+    if not args.no_extras:
+        result["rolling"] = bench_rolling(torch, seb)
+        result["large_map"] = bench_large(torch, seb)
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(p, hmap)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

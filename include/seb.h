@@ -1,0 +1,187 @@
+/*
+ * seb.h -- C ABI of the MI355X (gfx950) SE(2)-grid traversability library.
+ *
+ * Method: SEB-Naver (arXiv 2503.02412).  For every state (x, y, yaw) of a
+ * robot-centric height map the library gathers the terrain under the
+ * yaw-rotated vehicle footprint, fits the terrain plane, recovers the pose the
+ * terrain imposes (Sec. III, Eq. 1-3: height z, and the body axes from the
+ * plane normal z_b, reported as Z-X-Y roll and pitch) and scores the risk of
+ * Algorithm 1 (Sec. V-B: curvature early-out, tilt early-out, weighted sum).
+ * The map is robot-centric and moves with the robot (Sec. V-A, Eq. 4).
+ *
+ * Conventions shared by every entry point:
+ *   - Heights: float32, row-major [H][W] with row stride `ld` (elements),
+ *     NaN or +-Inf = unknown cell.  Finite heights must satisfy |h| < 2^60.
+ *     Cell (ix, iy) is centred at map-local metres ((ix+0.5) res, (iy+0.5) res).
+ *   - Yaw bins: theta_k = 2 pi k / K, k = 0 .. K-1.
+ *   - Outputs (seb_out): five device arrays laid out [K][H][W] (yaw-major
+ *     planes of H rows of W cells, dense).  Units: metres / radians.
+ *   - All array pointers are DEVICE pointers owned by the caller; they must
+ *     stay valid until the work queued on `stream` has completed.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls only enqueue work: they never synchronise, never print, and
+ *     allocate device memory only in the *_create functions.
+ *   - Return value: SEB_OK (0) or a negative seb_status.  Argument errors are
+ *     detected on the host before anything is launched; seb_last_error()
+ *     returns a thread-local message describing the most recent failure.
+ *     Asynchronous device faults surface at the caller's next synchronisation.
+ *   - A seb_ctx / seb_window may be used by one stream at a time.
+ */
+#ifndef SEB_H
+#define SEB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SEB_OK = 0,
+    SEB_ERR_INVALID = -1,      /* bad argument or configuration             */
+    SEB_ERR_HIP = -2,          /* a HIP runtime call or launch failed       */
+    SEB_ERR_ALLOC = -3,        /* device or host allocation failed          */
+    SEB_ERR_UNSUPPORTED = -4,  /* valid, but outside what the kernels cover */
+    SEB_ERR_IO = -5            /* file could not be read or written         */
+} seb_status;
+
+/* Status byte of each state. */
+enum {
+    SEB_ST_VALID = 1,       /* plane fitted; 0 = UNKNOWN (too few / collinear samples) */
+    SEB_ST_CURV = 2,        /* Alg. 1 curvature early-out: kappa > kappa_max           */
+    SEB_ST_TILT = 4,        /* Alg. 1 tilt early-out: phi_x > phi_x_max or phi_y > ... */
+    SEB_ST_DEGEN = 8,       /* near-degenerate footprint (few or nearly collinear)     */
+    SEB_ST_TRAV = 16,       /* traversable: valid and risk <= risk_max                 */
+    SEB_ST_SURROGATE = 32   /* produced by the learned surrogate, not the plain fit    */
+};
+
+/* Assessment parameters.  Lengths in metres, angles in radians.  The names
+ * follow Algorithm 1 (Sec. V-B): kappa_max, phi_x_max, phi_y_max and the risk
+ * weights w_r = (w_kappa, w_phi_x, w_phi_y); risk_max is r_max of the safety
+ * constraint (Sec. VI-B).  The paper gives phi_x_max = phi_y_max = 0.52 rad
+ * (Sec. VII-B) and leaves the others open. */
+typedef struct seb_config {
+    int32_t width, height;       /* W (x, columns) and H (y, rows) cells          */
+    double resolution;           /* metres per cell                               */
+    int32_t n_yaw;               /* K                                             */
+    double fp_length, fp_width;  /* footprint extent along body x / body y        */
+    int32_t fp_nl, fp_nw;        /* body-frame midpoint sample grid               */
+    int32_t fp_shape;            /* 0 rectangle, 1 inscribed ellipse              */
+    double kappa_max, phi_x_max, phi_y_max;
+    double w_kappa, w_phi_x, w_phi_y, risk_max;
+    int32_t min_valid;           /* >= 3 samples needed for a fit                 */
+    int32_t precision;           /* 0 FP32; 1 FP32 + FP64 for near-degenerate    */
+    int32_t fit;                 /* 0 least-squares plane (1: principal-component,
+                                    not provided by the kernels)                   */
+} seb_config;
+
+/* Output arrays, each [K][H][W] on the device.  z and the angles are NaN for
+ * UNKNOWN states, whose risk is 1. */
+typedef struct seb_out {
+    float* z;       /* terrain-imposed height at the state (plane at the cell centre) */
+    float* roll;    /* Z-X-Y roll, > 0 left side up                                 */
+    float* pitch;   /* Z-X-Y pitch, > 0 nose down                                   */
+    float* risk;    /* Algorithm 1 risk in [0, 1]; 1 = explicit obstacle            */
+    uint8_t* status;/* SEB_ST_* bits                                                */
+} seb_out;
+
+typedef struct seb_ctx seb_ctx;
+typedef struct seb_window seb_window;
+
+/* ---------------------------------------------------------------- context */
+
+/* Check a configuration on the host only (no device use).  Returns SEB_OK,
+ * SEB_ERR_INVALID (malformed) or SEB_ERR_UNSUPPORTED (footprint reach or
+ * sample grid beyond the kernels' limits). */
+int seb_validate_config(const seb_config* cfg);
+
+/* Build the FP64 footprint/yaw table for `cfg` on the host and upload it to
+ * the current HIP device.  *out receives the new context (library-owned;
+ * release with seb_destroy).  Errors: SEB_ERR_INVALID, SEB_ERR_UNSUPPORTED,
+ * SEB_ERR_ALLOC, SEB_ERR_HIP. */
+int seb_create(const seb_config* cfg, seb_ctx** out);
+
+/* Release a context and its device table.  NULL is ignored.  The caller must
+ * ensure no queued work still uses it. */
+void seb_destroy(seb_ctx* ctx);
+
+/* ------------------------------------------------------ full assessment */
+
+/* Assess every yaw bin of the states in the rectangle [x0, x0+nx) x
+ * [y0, y0+ny) of the map `height` (device, [H][W] with row stride ld >= W),
+ * writing out->*[k][iy][ix] for those states only.  Footprint samples that
+ * fall outside the map or on unknown cells are dropped (Alg. 1 runs on the
+ * valid ones).  nx == 0 or ny == 0 is a no-op.  The rectangle must lie inside
+ * the map.  Defined by Sec. V-B, Algorithm 1 with Eq. 1-3 of Sec. III. */
+int seb_assess_se2(seb_ctx* ctx, const float* height, int64_t ld, int32_t x0, int32_t y0,
+                   int32_t nx, int32_t ny, const seb_out* out, void* stream);
+
+/* ------------------------------------------------- rolling maintenance */
+
+/* Geometry of one window move (host only, pure integer arithmetic). */
+typedef struct seb_window_plan {
+    int64_t old_origin_x, old_origin_y;   /* world cell of logical cell (0, 0)       */
+    int64_t new_origin_x, new_origin_y;   /* Eq. 4: floor(p / res) - (W/2, H/2)      */
+    int32_t full_reset;                   /* shift >= window size: everything new    */
+    int32_t exposed_rows;                 /* |dy| whole rows (W cells each)          */
+    int32_t exposed_cols;                 /* |dx| columns over the other H-|dy| rows */
+    int64_t n_cells_exposed;              /* cells new_cells must provide            */
+    int32_t n_rects;                      /* disjoint state rectangles recomputed    */
+    int32_t rects[8][4];                  /* x0, y0, nx, ny in new logical coords    */
+    int64_t n_states;                     /* states recomputed (all yaw bins)        */
+} seb_window_plan;
+
+/* Create a rolling window over caller-owned ring storage: `height_ring`
+ * ([H][W], row stride ld) and `out_ring` (seb_out, [K][H][W]).  World cell
+ * (gx, gy) of the window lives at ring position (gx mod W, gy mod H) in both.
+ * The window starts at the robot position (x, y) metres with every cell
+ * unknown; call seb_window_reset to load heights.  Errors: SEB_ERR_INVALID,
+ * SEB_ERR_ALLOC. */
+int seb_window_create(seb_ctx* ctx, float* height_ring, int64_t ld, const seb_out* out_ring,
+                      double x, double y, seb_window** out);
+void seb_window_destroy(seb_window* w);
+
+/* Origin (world cell of logical (0, 0)) and ring offset (origin mod size). */
+int seb_window_origin(const seb_window* w, int64_t* origin_x, int64_t* origin_y,
+                      int32_t* ring_x, int32_t* ring_y);
+
+/* Place the window at robot position (x, y) (Eq. 4), copy the logical map
+ * `heights` (device [H][W], row stride ld; NULL = all unknown) into the ring
+ * and assess every state. */
+int seb_window_reset(seb_window* w, double x, double y, const float* heights, int64_t ld,
+                     void* stream);
+
+/* Host-only geometry of moving the window to robot position (x, y): the new
+ * origin by Eq. 4, the exposed strips and the rectangles of states whose
+ * footprint reaches a changed cell (new cells, or cells that left the window
+ * and are unknown from now on).  Does not modify the window. */
+int seb_window_plan_move(const seb_window* w, double x, double y, seb_window_plan* plan);
+
+/* The same geometry without a window or a device: for a window of `cfg`
+ * whose logical cell (0, 0) is world cell (origin_x, origin_y), moving the
+ * robot to (x, y).  Host only. */
+int seb_plan_window_move(const seb_config* cfg, int64_t origin_x, int64_t origin_y, double x,
+                         double y, seb_window_plan* plan);
+
+/* Move the window to robot position (x, y) (Sec. V-A: Eq. 4, then cells no
+ * longer in the map become unknown).  `new_cells` (device, may be NULL = all
+ * unknown) holds the heights of the newly exposed cells in the order of
+ * seb_window_plan: first the exposed rows (increasing logical y, each W cells
+ * of increasing x), then the exposed columns (for each remaining row in
+ * increasing y, the |dx| cells in increasing x).  Then re-assesses exactly the
+ * plan's rectangles; the result equals a full seb_assess_se2 of the new window
+ * bit for bit.  *n_states_recomputed (host, may be NULL) receives the plan's
+ * n_states without synchronising. */
+int seb_update_window(seb_window* w, double x, double y, const float* new_cells, void* stream,
+                      int64_t* n_states_recomputed);
+
+/* --------------------------------------------------------------- misc */
+
+const char* seb_strerror(int status);
+const char* seb_last_error(void);
+const char* seb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEB_H */

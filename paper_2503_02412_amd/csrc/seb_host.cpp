@@ -1,0 +1,677 @@
+// Host side of the SE(2) traversability library: configuration checks, the
+// FP64 footprint/yaw table, rolling-window geometry and the C ABI (seb.h).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/seb.h"
+#include "seb_internal.hpp"
+
+using namespace seb;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return SEB_ERR_HIP;
+}
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSnap = 1e-6;
+
+int bits_for(int64_t v) {
+    int b = 0;
+    while ((int64_t(1) << b) <= v) ++b;
+    return b;
+}
+
+// Footprint sample geometry of one body-frame sample (i, j).
+struct BodySample {
+    int i, j, p, q;
+    double u, v;
+};
+
+bool footprint_sample(const seb_config& c, int i, int j, BodySample* s) {
+    s->i = i;
+    s->j = j;
+    s->p = 2 * i - (c.fp_nl - 1);
+    s->q = 2 * j - (c.fp_nw - 1);
+    s->u = (i + 0.5) * c.fp_length / c.fp_nl - 0.5 * c.fp_length;
+    s->v = (j + 0.5) * c.fp_width / c.fp_nw - 0.5 * c.fp_width;
+    if (c.fp_shape == 1) {
+        // inside the inscribed ellipse, decided in exact integers
+        const int64_t nl = c.fp_nl, nw = c.fp_nw;
+        const int64_t lhs = (int64_t)s->p * s->p * nw * nw + (int64_t)s->q * s->q * nl * nl;
+        if (lhs > nl * nl * nw * nw) return false;
+    }
+    return true;
+}
+
+double snap_int(double o) {
+    const double r = std::nearbyint(o);
+    return std::fabs(o - r) < kSnap ? r : o;
+}
+
+// Grid offset of a body sample at yaw theta: o = R(theta) (u, v) / res.
+void grid_offset(const seb_config& c, double cth, double sth, const BodySample& s, double* ox,
+                 double* oy) {
+    *ox = snap_int((s.u * cth - s.v * sth) / c.resolution);
+    *oy = snap_int((s.u * sth + s.v * cth) / c.resolution);
+}
+
+struct Geometry {
+    std::vector<BodySample> samples;      // footprint samples in table order
+    std::vector<Segment> segs;
+    int n_units = 0, mirror = 0;
+    int R = 0;                            // LDS halo (covers the unconditional +1 corner reads)
+    int dx_min = 0, dx_max = 0, dy_min = 0, dy_max = 0;   // required-corner reach
+    int qoff = 0, w1 = 0, sh2 = 0;
+    double rho_full = 0.0;
+};
+
+int build_geometry(const seb_config& c, Geometry* g, std::string* why) {
+    // Table order: rows of constant body-x index i, samples of increasing j.
+    std::vector<std::vector<BodySample>> rows(c.fp_nl);
+    for (int i = 0; i < c.fp_nl; ++i)
+        for (int j = 0; j < c.fp_nw; ++j) {
+            BodySample s;
+            if (footprint_sample(c, i, j, &s)) rows[i].push_back(s);
+        }
+    // Packed integer moments: choose the longest segment whose fields fit 32 bits.
+    g->qoff = c.fp_nw - 1;
+    const int64_t qmax = g->qoff;
+    int seg_len = 0;
+    for (int m = std::min(63, c.fp_nw); m >= 1; --m) {
+        const int w1 = bits_for((int64_t)m * 2 * qmax);
+        const int w2 = bits_for((int64_t)m * qmax * qmax);
+        if (6 + w1 + w2 <= 32) {
+            seg_len = m;
+            g->w1 = w1;
+            g->sh2 = 6 + w1;
+            break;
+        }
+    }
+    if (seg_len == 0) {
+        *why = "footprint sample grid too wide for the packed moments";
+        return SEB_ERR_UNSUPPORTED;
+    }
+    g->samples.clear();
+    g->segs.clear();
+    for (int i = 0; i < c.fp_nl; ++i) {
+        const auto& r = rows[i];
+        for (size_t s0 = 0; s0 < r.size(); s0 += seg_len) {
+            Segment sg;
+            sg.p = 2 * i - (c.fp_nl - 1);
+            sg.first = (int)g->samples.size();
+            sg.count = (int)std::min<size_t>(seg_len, r.size() - s0);
+            sg.pad = 0;
+            for (int t = 0; t < sg.count; ++t) g->samples.push_back(r[s0 + t]);
+            g->segs.push_back(sg);
+        }
+    }
+    if (g->samples.empty()) {
+        *why = "footprint has no samples";
+        return SEB_ERR_INVALID;
+    }
+    // Yaw bins k and k + K/2 share sample positions: compute half, mirror the rest.
+    g->mirror = (c.n_yaw % 2 == 0) ? c.n_yaw / 2 : 0;
+    g->n_units = g->mirror ? c.n_yaw / 2 : c.n_yaw;
+
+    // Reach over all yaw bins (both halves, to be safe).
+    int R = 0, dx0 = 0, dx1 = 0, dy0 = 0, dy1 = 0;
+    for (int k = 0; k < c.n_yaw; ++k) {
+        const double th = 2.0 * kPi * (double)k / (double)c.n_yaw;
+        const double cth = std::cos(th), sth = std::sin(th);
+        for (const auto& s : g->samples) {
+            double ox, oy;
+            grid_offset(c, cth, sth, s, &ox, &oy);
+            const double fx = std::floor(ox), fy = std::floor(oy);
+            const int ax = (int)fx, ay = (int)fy;
+            const int bx = ax + (ox - fx > 0.0 ? 1 : 0), by = ay + (oy - fy > 0.0 ? 1 : 0);
+            dx0 = std::min(dx0, ax);
+            dx1 = std::max(dx1, bx);
+            dy0 = std::min(dy0, ay);
+            dy1 = std::max(dy1, by);
+            R = std::max({R, -ax, ax + 1, -ay, ay + 1});
+        }
+    }
+    g->R = R;
+    g->dx_min = dx0;
+    g->dx_max = dx1;
+    g->dy_min = dy0;
+    g->dy_max = dy1;
+
+    // Scale of the near-degenerate test: 4 det / (D + E)^2 of the full footprint.
+    int64_t N = 0, Sp = 0, Sq = 0, Spp = 0, Spq = 0, Sqq = 0;
+    for (const auto& s : g->samples) {
+        N += 1;
+        Sp += s.p;
+        Sq += s.q;
+        Spp += (int64_t)s.p * s.p;
+        Spq += (int64_t)s.p * s.q;
+        Sqq += (int64_t)s.q * s.q;
+    }
+    const int64_t D = N * Spp - Sp * Sp, E = N * Sqq - Sq * Sq, F = N * Spq - Sp * Sq;
+    const int64_t det = D * E - F * F;
+    const double de = (double)(D + E);
+    g->rho_full = (de > 0) ? (4.0 * (double)det) / (de * de) : 0.0;
+    return SEB_OK;
+}
+
+int validate(const seb_config* c, std::string* why) {
+    if (!c) {
+        *why = "config is NULL";
+        return SEB_ERR_INVALID;
+    }
+    if (c->width < 1 || c->height < 1 || c->width > (1 << 20) || c->height > (1 << 20)) {
+        *why = "width/height must be in [1, 2^20]";
+        return SEB_ERR_INVALID;
+    }
+    if ((int64_t)c->width * c->height * std::max(c->n_yaw, 1) > (int64_t(1) << 40)) {
+        *why = "too many states";
+        return SEB_ERR_INVALID;
+    }
+    if (!(c->resolution > 0.0) || !std::isfinite(c->resolution)) {
+        *why = "resolution must be positive";
+        return SEB_ERR_INVALID;
+    }
+    if (c->n_yaw < 1 || c->n_yaw > 4096) {
+        *why = "n_yaw must be in [1, 4096]";
+        return SEB_ERR_INVALID;
+    }
+    if (!(c->fp_length > 0.0) || !(c->fp_width > 0.0) || !std::isfinite(c->fp_length) ||
+        !std::isfinite(c->fp_width)) {
+        *why = "footprint extents must be positive";
+        return SEB_ERR_INVALID;
+    }
+    if (c->fp_nl < 1 || c->fp_nw < 1 || c->fp_nl > 4096 || c->fp_nw > 4096) {
+        *why = "footprint sample grid must be in [1, 4096]^2";
+        return SEB_ERR_INVALID;
+    }
+    if (c->fp_shape != 0 && c->fp_shape != 1) {
+        *why = "fp_shape must be 0 (rectangle) or 1 (ellipse)";
+        return SEB_ERR_INVALID;
+    }
+    if (!(c->kappa_max > 0.0) || !(c->phi_x_max > 0.0) || !(c->phi_y_max > 0.0)) {
+        *why = "kappa_max, phi_x_max and phi_y_max must be positive";
+        return SEB_ERR_INVALID;
+    }
+    if (!std::isfinite(c->w_kappa) || !std::isfinite(c->w_phi_x) || !std::isfinite(c->w_phi_y) ||
+        !std::isfinite(c->risk_max)) {
+        *why = "risk weights and risk_max must be finite";
+        return SEB_ERR_INVALID;
+    }
+    if (c->min_valid < 3) {
+        *why = "min_valid must be >= 3";
+        return SEB_ERR_INVALID;
+    }
+    if (c->precision != 0 && c->precision != 1) {
+        *why = "precision must be 0 or 1";
+        return SEB_ERR_INVALID;
+    }
+    if (c->fit != 0 && c->fit != 1) {
+        *why = "fit must be 0 or 1";
+        return SEB_ERR_INVALID;
+    }
+    if ((int64_t)c->fp_nl * c->fp_nw > 65536) {
+        *why = "at most 65536 footprint samples are supported";
+        return SEB_ERR_UNSUPPORTED;
+    }
+    if (c->fit == 1) {
+        *why = "the principal-component fit is not provided by the kernels";
+        return SEB_ERR_UNSUPPORTED;
+    }
+    return SEB_OK;
+}
+
+int64_t floor_div_cell(double x, double res) { return (int64_t)std::floor(x / res); }
+
+int64_t pos_mod(int64_t a, int64_t n) {
+    int64_t r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+}  // namespace
+
+struct seb_ctx {
+    seb_config cfg;
+    Geometry geo;
+    int pitch = 0;
+    TblEntry* d_tbl = nullptr;
+    double2* d_frac = nullptr;
+    Segment* d_segs = nullptr;
+    int device = 0;
+};
+
+struct seb_window {
+    seb_ctx* ctx;
+    float* ring;
+    int64_t ld;
+    seb_out out;
+    int64_t ox, oy;    // world cell of logical (0, 0)
+};
+
+namespace {
+
+// Fill the per-call part of the kernel arguments.
+void base_args(const seb_ctx* c, AssessArgs* a) {
+    std::memset(a, 0, sizeof(*a));
+    const seb_config& g = c->cfg;
+    a->W = g.width;
+    a->H = g.height;
+    a->tbl = c->d_tbl;
+    a->frac = c->d_frac;
+    a->segs = c->d_segs;
+    a->n_units = c->geo.n_units;
+    a->mirror = c->geo.mirror;
+    a->n_samples = (int)c->geo.samples.size();
+    a->n_segs = (int)c->geo.segs.size();
+    a->K = g.n_yaw;
+    a->R = c->geo.R;
+    a->qoff = c->geo.qoff;
+    a->mask1 = (uint32_t)((1u << c->geo.w1) - 1u);
+    a->sh2 = c->geo.sh2;
+    a->hu = (float)(0.5 * g.fp_length / g.fp_nl);
+    a->hv = (float)(0.5 * g.fp_width / g.fp_nw);
+    a->rho16 = c->geo.rho_full / 16.0;
+    a->n_total = (int)c->geo.samples.size();
+    a->kappa_max = (float)g.kappa_max;
+    a->phi_x_max = (float)g.phi_x_max;
+    a->phi_y_max = (float)g.phi_y_max;
+    a->w_kappa = (float)g.w_kappa;
+    a->w_phi_x = (float)g.w_phi_x;
+    a->w_phi_y = (float)g.w_phi_y;
+    a->risk_max = (float)g.risk_max;
+    a->min_valid = g.min_valid;
+    a->precision = g.precision;
+}
+
+// Tile decomposition of the state rectangles; chooses the yaw bins per workgroup.
+void set_rects(AssessArgs* a, int n, const int32_t (*rects)[4]) {
+    a->n_rects = 0;
+    int start = 0;
+    for (int r = 0; r < n; ++r) {
+        if (rects[r][2] <= 0 || rects[r][3] <= 0) continue;
+        const int i = a->n_rects++;
+        for (int t = 0; t < 4; ++t) a->rect[i][t] = rects[r][t];
+        a->tiles_x[i] = (rects[r][2] + TILE - 1) / TILE;
+        const int ty = (rects[r][3] + TILE - 1) / TILE;
+        a->tile_start[i] = start;
+        start += a->tiles_x[i] * ty;
+    }
+    a->tile_start[a->n_rects] = start;
+    // Aim for >= 2048 workgroups (8 per CU) so that 256 CUs stay busy.
+    const int64_t work = (int64_t)start * a->n_units;
+    int g = (int)std::max<int64_t>(1, work / 2048);
+    a->units_per_group = std::min(g, std::max(a->n_units, 1));
+}
+
+int check_out(const seb_out* o) {
+    if (!o || !o->z || !o->roll || !o->pitch || !o->risk || !o->status)
+        return fail(SEB_ERR_INVALID, "output arrays must all be non-NULL");
+    return SEB_OK;
+}
+
+int run_assess(seb_ctx* c, const float* height, int64_t ld, int rx, int ry, const seb_out* out,
+               int n_rects, const int32_t (*rects)[4], hipStream_t stream) {
+    AssessArgs a;
+    base_args(c, &a);
+    a.height = height;
+    a.ld = ld;
+    a.rx = rx;
+    a.ry = ry;
+    a.z = out->z;
+    a.roll = out->roll;
+    a.pitch = out->pitch;
+    a.risk = out->risk;
+    a.status = out->status;
+    set_rects(&a, n_rects, rects);
+    const hipError_t e = launch_assess(a, c->pitch, stream);
+    if (e != hipSuccess) return hip_fail(e, "assessment kernel launch");
+    return SEB_OK;
+}
+
+// Band of states whose footprint reaches a changed cell, as disjoint rects.
+void plan_geometry(const seb_config& cfg, const Geometry& g, int64_t ox, int64_t oy,
+                   int64_t nox, int64_t noy, seb_window_plan* p) {
+    const int W = cfg.width, H = cfg.height;
+    std::memset(p, 0, sizeof(*p));
+    p->old_origin_x = ox;
+    p->old_origin_y = oy;
+    p->new_origin_x = nox;
+    p->new_origin_y = noy;
+    const int64_t dx = nox - ox, dy = noy - oy;
+    if (std::llabs(dx) >= W || std::llabs(dy) >= H) {
+        p->full_reset = 1;
+        p->exposed_rows = H;
+        p->exposed_cols = 0;
+        p->n_cells_exposed = (int64_t)W * H;
+        p->n_rects = 1;
+        p->rects[0][0] = 0;
+        p->rects[0][1] = 0;
+        p->rects[0][2] = W;
+        p->rects[0][3] = H;
+        p->n_states = (int64_t)W * H * cfg.n_yaw;
+        return;
+    }
+    const int ady = (int)std::llabs(dy), adx = (int)std::llabs(dx);
+    p->exposed_rows = ady;
+    p->exposed_cols = adx;
+    p->n_cells_exposed = (int64_t)ady * W + (int64_t)adx * (H - ady);
+
+    // State intervals along one axis affected by a shift d of that axis.
+    auto intervals = [](int d, int n, int lo_reach, int hi_reach, std::vector<std::pair<int, int>>* iv) {
+        // lo_reach = -min offset (>= 0), hi_reach = max offset (>= 0)
+        if (d > 0) {
+            iv->push_back({n - d - hi_reach, n});      // reach the new cells [n-d, n)
+            iv->push_back({0, lo_reach});              // reach the cells that left (< 0)
+        } else if (d < 0) {
+            iv->push_back({0, -d + lo_reach});         // reach the new cells [0, -d)
+            iv->push_back({n - hi_reach, n});          // reach the cells that left (>= n)
+        }
+    };
+    auto merge = [](std::vector<std::pair<int, int>> iv, int n) {
+        std::vector<std::pair<int, int>> out;
+        for (auto& x : iv) {
+            x.first = std::max(0, x.first);
+            x.second = std::min(n, x.second);
+        }
+        std::sort(iv.begin(), iv.end());
+        for (auto& x : iv) {
+            if (x.first >= x.second) continue;
+            if (!out.empty() && x.first <= out.back().second)
+                out.back().second = std::max(out.back().second, x.second);
+            else
+                out.push_back(x);
+        }
+        return out;
+    };
+    std::vector<std::pair<int, int>> rv, cv;
+    intervals((int)dy, H, -g.dy_min, g.dy_max, &rv);
+    intervals((int)dx, W, -g.dx_min, g.dx_max, &cv);
+    rv = merge(rv, H);
+    cv = merge(cv, W);
+    int n = 0;
+    int64_t states = 0;
+    for (auto& r : rv) {
+        p->rects[n][0] = 0;
+        p->rects[n][1] = r.first;
+        p->rects[n][2] = W;
+        p->rects[n][3] = r.second - r.first;
+        states += (int64_t)W * (r.second - r.first);
+        ++n;
+    }
+    // Rows not covered by row bands, crossed with the column bands.
+    std::vector<std::pair<int, int>> rem;
+    int y = 0;
+    for (auto& r : rv) {
+        if (r.first > y) rem.push_back({y, r.first});
+        y = r.second;
+    }
+    if (y < H) rem.push_back({y, H});
+    for (auto& rr : rem)
+        for (auto& cc : cv) {
+            p->rects[n][0] = cc.first;
+            p->rects[n][1] = rr.first;
+            p->rects[n][2] = cc.second - cc.first;
+            p->rects[n][3] = rr.second - rr.first;
+            states += (int64_t)(cc.second - cc.first) * (rr.second - rr.first);
+            ++n;
+        }
+    p->n_rects = n;
+    p->n_states = states * cfg.n_yaw;
+}
+
+void origin_for(const seb_config& cfg, double x, double y, int64_t* ox, int64_t* oy) {
+    // Eq. 4: the map frame sits at the robot's cell; the window is centred on it.
+    *ox = floor_div_cell(x, cfg.resolution) - cfg.width / 2;
+    *oy = floor_div_cell(y, cfg.resolution) - cfg.height / 2;
+}
+
+}  // namespace
+
+extern "C" {
+
+int seb_validate_config(const seb_config* cfg) {
+    std::string why;
+    int rc = validate(cfg, &why);
+    if (rc != SEB_OK) return fail(rc, why);
+    Geometry g;
+    rc = build_geometry(*cfg, &g, &why);
+    if (rc != SEB_OK) return fail(rc, why);
+    if (pick_pitch(g.R) == 0) return fail(SEB_ERR_UNSUPPORTED, "footprint reach exceeds the widest LDS tile (64 cells)");
+    return SEB_OK;
+}
+
+int seb_create(const seb_config* cfg, seb_ctx** out) {
+    if (!out) return fail(SEB_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    int rc = seb_validate_config(cfg);
+    if (rc != SEB_OK) return rc;
+    seb_ctx* c = new (std::nothrow) seb_ctx();
+    if (!c) return fail(SEB_ERR_ALLOC, "host allocation failed");
+    c->cfg = *cfg;
+    std::string why;
+    build_geometry(*cfg, &c->geo, &why);
+    c->pitch = pick_pitch(c->geo.R);
+    hipGetDevice(&c->device);
+
+    // FP64 table: per yaw bin, per sample, the snapped grid offset split into
+    // an integer corner and bilinear fractions.
+    const Geometry& g = c->geo;
+    const int ns = (int)g.samples.size();
+    std::vector<TblEntry> tbl((size_t)g.n_units * ns);
+    std::vector<double2> frac((size_t)g.n_units * ns);
+    const int sh2 = g.sh2;
+    for (int u = 0; u < g.n_units; ++u) {
+        const double th = 2.0 * kPi * (double)u / (double)cfg->n_yaw;
+        const double cth = std::cos(th), sth = std::sin(th);
+        for (int s = 0; s < ns; ++s) {
+            const BodySample& b = g.samples[s];
+            double ox, oy;
+            grid_offset(*cfg, cth, sth, b, &ox, &oy);
+            const double flx = std::floor(ox), fly = std::floor(oy);
+            const double fx = ox - flx, fy = oy - fly;
+            TblEntry& t = tbl[(size_t)u * ns + s];
+            t.off = (int)fly * c->pitch + (int)flx;
+            t.w00 = (float)((1.0 - fx) * (1.0 - fy));
+            t.w01 = (float)(fx * (1.0 - fy));
+            t.w10 = (float)((1.0 - fx) * fy);
+            t.w11 = (float)(fx * fy);
+            t.q = (float)b.q;
+            t.pk = 1u | ((uint32_t)(b.q + g.qoff) << 6) | ((uint32_t)(b.q * b.q) << sh2);
+            t.pad = 0;
+            frac[(size_t)u * ns + s] = make_double2(fx, fy);
+        }
+    }
+    hipError_t e;
+    if ((e = hipMalloc(&c->d_tbl, tbl.size() * sizeof(TblEntry))) != hipSuccess ||
+        (e = hipMalloc(&c->d_frac, frac.size() * sizeof(double2))) != hipSuccess ||
+        (e = hipMalloc(&c->d_segs, g.segs.size() * sizeof(Segment))) != hipSuccess) {
+        seb_destroy(c);
+        g_last_error = std::string("hipMalloc: ") + hipGetErrorString(e);
+        return SEB_ERR_ALLOC;
+    }
+    if ((e = hipMemcpy(c->d_tbl, tbl.data(), tbl.size() * sizeof(TblEntry),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->d_frac, frac.data(), frac.size() * sizeof(double2),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->d_segs, g.segs.data(), g.segs.size() * sizeof(Segment),
+                       hipMemcpyHostToDevice)) != hipSuccess) {
+        seb_destroy(c);
+        return hip_fail(e, "table upload");
+    }
+    *out = c;
+    return SEB_OK;
+}
+
+void seb_destroy(seb_ctx* c) {
+    if (!c) return;
+    if (c->d_tbl) hipFree(c->d_tbl);
+    if (c->d_frac) hipFree(c->d_frac);
+    if (c->d_segs) hipFree(c->d_segs);
+    delete c;
+}
+
+int seb_assess_se2(seb_ctx* c, const float* height, int64_t ld, int32_t x0, int32_t y0,
+                   int32_t nx, int32_t ny, const seb_out* out, void* stream) {
+    if (!c) return fail(SEB_ERR_INVALID, "ctx is NULL");
+    if (nx < 0 || ny < 0) return fail(SEB_ERR_INVALID, "nx and ny must be >= 0");
+    if (nx == 0 || ny == 0) return SEB_OK;
+    if (!height) return fail(SEB_ERR_INVALID, "height is NULL");
+    int rc = check_out(out);
+    if (rc != SEB_OK) return rc;
+    if (ld < c->cfg.width) return fail(SEB_ERR_INVALID, "ld must be >= width");
+    if (x0 < 0 || y0 < 0 || (int64_t)x0 + nx > c->cfg.width || (int64_t)y0 + ny > c->cfg.height)
+        return fail(SEB_ERR_INVALID, "state rectangle outside the map");
+    const int32_t rect[1][4] = {{x0, y0, nx, ny}};
+    return run_assess(c, height, ld, 0, 0, out, 1, rect, (hipStream_t)stream);
+}
+
+int seb_window_create(seb_ctx* c, float* height_ring, int64_t ld, const seb_out* out_ring,
+                      double x, double y, seb_window** out) {
+    if (!out) return fail(SEB_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!c || !height_ring) return fail(SEB_ERR_INVALID, "ctx and height_ring must be non-NULL");
+    int rc = check_out(out_ring);
+    if (rc != SEB_OK) return rc;
+    if (ld < c->cfg.width) return fail(SEB_ERR_INVALID, "ld must be >= width");
+    if (!std::isfinite(x) || !std::isfinite(y)) return fail(SEB_ERR_INVALID, "position not finite");
+    seb_window* w = new (std::nothrow) seb_window();
+    if (!w) return fail(SEB_ERR_ALLOC, "host allocation failed");
+    w->ctx = c;
+    w->ring = height_ring;
+    w->ld = ld;
+    w->out = *out_ring;
+    origin_for(c->cfg, x, y, &w->ox, &w->oy);
+    *out = w;
+    return SEB_OK;
+}
+
+void seb_window_destroy(seb_window* w) { delete w; }
+
+int seb_window_origin(const seb_window* w, int64_t* origin_x, int64_t* origin_y, int32_t* ring_x,
+                      int32_t* ring_y) {
+    if (!w) return fail(SEB_ERR_INVALID, "window is NULL");
+    if (origin_x) *origin_x = w->ox;
+    if (origin_y) *origin_y = w->oy;
+    if (ring_x) *ring_x = (int32_t)pos_mod(w->ox, w->ctx->cfg.width);
+    if (ring_y) *ring_y = (int32_t)pos_mod(w->oy, w->ctx->cfg.height);
+    return SEB_OK;
+}
+
+int seb_window_reset(seb_window* w, double x, double y, const float* heights, int64_t ld,
+                     void* stream) {
+    if (!w) return fail(SEB_ERR_INVALID, "window is NULL");
+    if (!std::isfinite(x) || !std::isfinite(y)) return fail(SEB_ERR_INVALID, "position not finite");
+    seb_ctx* c = w->ctx;
+    if (heights && ld < c->cfg.width) return fail(SEB_ERR_INVALID, "ld must be >= width");
+    origin_for(c->cfg, x, y, &w->ox, &w->oy);
+    InsertArgs ia;
+    std::memset(&ia, 0, sizeof(ia));
+    ia.ring = w->ring;
+    ia.ld = w->ld;
+    ia.W = c->cfg.width;
+    ia.H = c->cfg.height;
+    ia.rx = (int)pos_mod(w->ox, ia.W);
+    ia.ry = (int)pos_mod(w->oy, ia.H);
+    ia.src = heights;
+    ia.src_ld = ld;
+    ia.full = 1;
+    hipError_t e = launch_insert(ia, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "ring insert launch");
+    const int32_t rect[1][4] = {{0, 0, c->cfg.width, c->cfg.height}};
+    return run_assess(c, w->ring, w->ld, ia.rx, ia.ry, &w->out, 1, rect, (hipStream_t)stream);
+}
+
+int seb_window_plan_move(const seb_window* w, double x, double y, seb_window_plan* plan) {
+    if (!w || !plan) return fail(SEB_ERR_INVALID, "window and plan must be non-NULL");
+    if (!std::isfinite(x) || !std::isfinite(y)) return fail(SEB_ERR_INVALID, "position not finite");
+    int64_t nox, noy;
+    origin_for(w->ctx->cfg, x, y, &nox, &noy);
+    plan_geometry(w->ctx->cfg, w->ctx->geo, w->ox, w->oy, nox, noy, plan);
+    return SEB_OK;
+}
+
+int seb_plan_window_move(const seb_config* cfg, int64_t origin_x, int64_t origin_y, double x,
+                         double y, seb_window_plan* plan) {
+    if (!plan) return fail(SEB_ERR_INVALID, "plan is NULL");
+    int rc = seb_validate_config(cfg);
+    if (rc != SEB_OK) return rc;
+    if (!std::isfinite(x) || !std::isfinite(y)) return fail(SEB_ERR_INVALID, "position not finite");
+    Geometry g;
+    std::string why;
+    build_geometry(*cfg, &g, &why);
+    int64_t nox, noy;
+    origin_for(*cfg, x, y, &nox, &noy);
+    plan_geometry(*cfg, g, origin_x, origin_y, nox, noy, plan);
+    return SEB_OK;
+}
+
+int seb_update_window(seb_window* w, double x, double y, const float* new_cells, void* stream,
+                      int64_t* n_states_recomputed) {
+    seb_window_plan p;
+    int rc = seb_window_plan_move(w, x, y, &p);
+    if (rc != SEB_OK) return rc;
+    seb_ctx* c = w->ctx;
+    const int W = c->cfg.width, H = c->cfg.height;
+    InsertArgs ia;
+    std::memset(&ia, 0, sizeof(ia));
+    ia.ring = w->ring;
+    ia.ld = w->ld;
+    ia.W = W;
+    ia.H = H;
+    ia.rx = (int)pos_mod(p.new_origin_x, W);
+    ia.ry = (int)pos_mod(p.new_origin_y, H);
+    ia.src = new_cells;
+    const int64_t dx = p.new_origin_x - p.old_origin_x, dy = p.new_origin_y - p.old_origin_y;
+    if (p.full_reset) {
+        ia.full = 1;
+        ia.src_ld = W;
+    } else {
+        ia.rows_n = p.exposed_rows;
+        ia.rows_lo = dy > 0 ? H - (int)dy : 0;
+        ia.cols_n = p.exposed_cols;
+        ia.cols_lo = dx > 0 ? W - (int)dx : 0;
+    }
+    hipError_t e = launch_insert(ia, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "ring insert launch");
+    w->ox = p.new_origin_x;
+    w->oy = p.new_origin_y;
+    if (n_states_recomputed) *n_states_recomputed = p.n_states;
+    if (p.n_rects == 0) return SEB_OK;
+    return run_assess(c, w->ring, w->ld, ia.rx, ia.ry, &w->out, p.n_rects, p.rects,
+                      (hipStream_t)stream);
+}
+
+const char* seb_strerror(int status) {
+    switch (status) {
+        case SEB_OK: return "success";
+        case SEB_ERR_INVALID: return "invalid argument";
+        case SEB_ERR_HIP: return "HIP runtime error";
+        case SEB_ERR_ALLOC: return "allocation failed";
+        case SEB_ERR_UNSUPPORTED: return "unsupported configuration";
+        case SEB_ERR_IO: return "I/O error";
+        default: return "unknown status";
+    }
+}
+
+const char* seb_last_error(void) { return g_last_error.c_str(); }
+
+const char* seb_version(void) { return "seb-mi355x 0.1.0 (gfx950)"; }
+
+}  // extern "C"

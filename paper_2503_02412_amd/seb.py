@@ -1,0 +1,273 @@
+"""Python binding of libseb.so (include/seb.h): argument marshalling only.
+
+Every step of the assessment runs in the library's HIP kernels; torch is used
+for device memory and streams.  Importing this module on a machine without
+the built library raises immediately -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libseb.so")
+
+SEB_OK, SEB_ERR_INVALID, SEB_ERR_HIP, SEB_ERR_ALLOC, SEB_ERR_UNSUPPORTED, SEB_ERR_IO = \
+    0, -1, -2, -3, -4, -5
+ST_VALID, ST_CURV, ST_TILT, ST_DEGEN, ST_TRAV, ST_SURROGATE = 1, 2, 4, 8, 16, 32
+
+
+class SebError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: status {code} ({detail})")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("width", C.c_int32), ("height", C.c_int32), ("resolution", C.c_double),
+        ("n_yaw", C.c_int32), ("fp_length", C.c_double), ("fp_width", C.c_double),
+        ("fp_nl", C.c_int32), ("fp_nw", C.c_int32), ("fp_shape", C.c_int32),
+        ("kappa_max", C.c_double), ("phi_x_max", C.c_double), ("phi_y_max", C.c_double),
+        ("w_kappa", C.c_double), ("w_phi_x", C.c_double), ("w_phi_y", C.c_double),
+        ("risk_max", C.c_double), ("min_valid", C.c_int32), ("precision", C.c_int32),
+        ("fit", C.c_int32),
+    ]
+
+
+class Out(C.Structure):
+    _fields_ = [("z", C.c_void_p), ("roll", C.c_void_p), ("pitch", C.c_void_p),
+                ("risk", C.c_void_p), ("status", C.c_void_p)]
+
+
+class WindowPlan(C.Structure):
+    _fields_ = [
+        ("old_origin_x", C.c_int64), ("old_origin_y", C.c_int64),
+        ("new_origin_x", C.c_int64), ("new_origin_y", C.c_int64),
+        ("full_reset", C.c_int32), ("exposed_rows", C.c_int32), ("exposed_cols", C.c_int32),
+        ("n_cells_exposed", C.c_int64), ("n_rects", C.c_int32),
+        ("rects", (C.c_int32 * 4) * 8), ("n_states", C.c_int64),
+    ]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "seb_validate_config": (C.c_int, [C.POINTER(Config)]),
+    "seb_create": (C.c_int, [C.POINTER(Config), C.POINTER(C.c_void_p)]),
+    "seb_destroy": (None, [C.c_void_p]),
+    "seb_assess_se2": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
+                                 C.c_int32, C.c_int32, C.POINTER(Out), C.c_void_p]),
+    "seb_window_create": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(Out),
+                                    C.c_double, C.c_double, C.POINTER(C.c_void_p)]),
+    "seb_window_destroy": (None, [C.c_void_p]),
+    "seb_window_origin": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "seb_window_reset": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_int64,
+                                   C.c_void_p]),
+    "seb_window_plan_move": (C.c_int, [C.c_void_p, C.c_double, C.c_double,
+                                       C.POINTER(WindowPlan)]),
+    "seb_plan_window_move": (C.c_int, [C.POINTER(Config), C.c_int64, C.c_int64, C.c_double,
+                                       C.c_double, C.POINTER(WindowPlan)]),
+    "seb_update_window": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                                    C.POINTER(C.c_int64)]),
+    "seb_strerror": (C.c_char_p, [C.c_int]),
+    "seb_last_error": (C.c_char_p, []),
+    "seb_version": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libseb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        # torch first: the library then binds to the HIP runtime torch already
+        # loaded (same SONAME), so device pointers and streams are shared.
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2503_02412_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != SEB_OK:
+        raise SebError(rc, where, lib().seb_last_error().decode())
+
+
+def config(params) -> Config:
+    p = params
+    return Config(int(p.width), int(p.height), float(p.resolution), int(p.n_yaw),
+                  float(p.fp_length), float(p.fp_width), int(p.fp_nl), int(p.fp_nw),
+                  int(p.fp_shape), float(p.kappa_max), float(p.phi_x_max), float(p.phi_y_max),
+                  float(p.w_kappa), float(p.w_phi_x), float(p.w_phi_y), float(p.risk_max),
+                  int(p.min_valid), int(p.precision), int(p.fit))
+
+
+def validate(params) -> int:
+    cfg = config(params)
+    return int(lib().seb_validate_config(C.byref(cfg)))
+
+
+def plan_window_move(params, origin_x: int, origin_y: int, x: float, y: float) -> WindowPlan:
+    """Host-only window-move geometry (seb_plan_window_move)."""
+    cfg = config(params)
+    p = WindowPlan()
+    _check(lib().seb_plan_window_move(C.byref(cfg), int(origin_x), int(origin_y), float(x),
+                                      float(y), C.byref(p)), "seb_plan_window_move")
+    return p
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def alloc_outputs(params, device="cuda"):
+    """Five torch tensors [K, H, W] on the device (float32 x4 + uint8 status)."""
+    import torch
+    shape = (params.n_yaw, params.height, params.width)
+    f = lambda: torch.empty(shape, dtype=torch.float32, device=device)
+    return {"z": f(), "roll": f(), "pitch": f(), "risk": f(),
+            "status": torch.empty(shape, dtype=torch.uint8, device=device)}
+
+
+def _out_struct(out, params) -> Out:
+    K, H, W = params.n_yaw, params.height, params.width
+    for name in ("z", "roll", "pitch", "risk", "status"):
+        t = out[name]
+        if not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (K, H, W):
+            raise ValueError(f"output '{name}' must be a contiguous CUDA tensor [K, H, W]")
+    return Out(out["z"].data_ptr(), out["roll"].data_ptr(), out["pitch"].data_ptr(),
+               out["risk"].data_ptr(), out["status"].data_ptr())
+
+
+def _check_map(height, params):
+    import torch
+    if not (height.is_cuda and height.dtype == torch.float32 and height.dim() == 2):
+        raise ValueError("height must be a float32 CUDA tensor [H, W]")
+    if tuple(height.shape) != (params.height, params.width) or height.stride(1) != 1:
+        raise ValueError("height must be [H, W] with unit column stride")
+
+
+class Context:
+    """Footprint table for one configuration (seb_create / seb_destroy)."""
+
+    def __init__(self, params):
+        self.params = params
+        self._cfg = config(params)
+        h = C.c_void_p()
+        _check(lib().seb_create(C.byref(self._cfg), C.byref(h)), "seb_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().seb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def assess(self, height, out=None, rect=None, stream=None):
+        """seb_assess_se2 over rect = (x0, y0, nx, ny) (default: the whole map)."""
+        _check_map(height, self.params)
+        if out is None:
+            out = alloc_outputs(self.params, height.device)
+        x0, y0, nx, ny = rect if rect is not None else (0, 0, self.params.width,
+                                                         self.params.height)
+        o = _out_struct(out, self.params)
+        _check(lib().seb_assess_se2(self._h, C.c_void_p(height.data_ptr()), height.stride(0),
+                                    x0, y0, nx, ny, C.byref(o), _stream_handle(stream)),
+               "seb_assess_se2")
+        return out
+
+
+class Window:
+    """Rolling window over ring storage (seb_window_*)."""
+
+    def __init__(self, ctx: Context, x: float, y: float, ring=None, out=None):
+        import torch
+        p = ctx.params
+        self.ctx = ctx
+        self.ring = ring if ring is not None else torch.full(
+            (p.height, p.width), float("nan"), dtype=torch.float32, device="cuda")
+        self.out = out if out is not None else alloc_outputs(p, self.ring.device)
+        o = _out_struct(self.out, p)
+        h = C.c_void_p()
+        _check(lib().seb_window_create(ctx._h, C.c_void_p(self.ring.data_ptr()),
+                                       self.ring.stride(0), C.byref(o), float(x), float(y),
+                                       C.byref(h)), "seb_window_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().seb_window_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def origin(self):
+        ox, oy, rx, ry = C.c_int64(), C.c_int64(), C.c_int32(), C.c_int32()
+        _check(lib().seb_window_origin(self._h, C.byref(ox), C.byref(oy), C.byref(rx),
+                                       C.byref(ry)), "seb_window_origin")
+        return ox.value, oy.value, rx.value, ry.value
+
+    def reset(self, x, y, heights=None, stream=None):
+        ptr, ld = (None, 0) if heights is None else (heights.data_ptr(), heights.stride(0))
+        if heights is not None:
+            _check_map(heights, self.ctx.params)
+        _check(lib().seb_window_reset(self._h, float(x), float(y), C.c_void_p(ptr), ld,
+                                      _stream_handle(stream)), "seb_window_reset")
+
+    def plan(self, x, y) -> WindowPlan:
+        p = WindowPlan()
+        _check(lib().seb_window_plan_move(self._h, float(x), float(y), C.byref(p)),
+               "seb_window_plan_move")
+        return p
+
+    def update(self, x, y, new_cells=None, stream=None) -> int:
+        if new_cells is not None:
+            import torch
+            need = self.plan(x, y).n_cells_exposed
+            if (not new_cells.is_cuda or new_cells.dtype != torch.float32
+                    or not new_cells.is_contiguous() or new_cells.numel() < need):
+                raise ValueError(f"new_cells must be a contiguous float32 CUDA tensor "
+                                 f"with >= {need} elements")
+        n = C.c_int64()
+        ptr = None if new_cells is None else new_cells.data_ptr()
+        _check(lib().seb_update_window(self._h, float(x), float(y), C.c_void_p(ptr),
+                                       _stream_handle(stream), C.byref(n)), "seb_update_window")
+        return n.value
+
+    def logical(self, name: str):
+        """An output (or 'height') un-rotated to logical window order (a copy)."""
+        import torch
+        _, _, rx, ry = self.origin()
+        t = self.ring if name == "height" else self.out[name]
+        return torch.roll(t, shifts=(-ry, -rx), dims=(-2, -1))
+
+
+def version() -> str:
+    return lib().seb_version().decode()
