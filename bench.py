@@ -142,15 +142,32 @@ def bench_large(torch, seb):
             "frac_of_vendor_fp32": f / (ms * 1e-3) / 1e12 / VENDOR_FP32_PEAK_TFLOPS}
 
 
-def cpu_baseline(params, hmap):
+def cpu_baseline(params, hmap, repeats: int = 3):
+    """The FP64 oracle, as it stands, on all host cores: `repeats` full maps
+    (about 10-30 s of CPU work), median time per map."""
     import oracle
     threads = oracle.max_threads()
-    t0 = time.perf_counter()
-    oracle.assess_rect(params, hmap, threads=threads)
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        oracle.assess_rect(params, hmap, threads=threads)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
     return {"value": params.n_states / dt, "unit": "SE(2) cells/s", "cores": threads,
-            "kind": "oracle", "seconds": dt,
-            "sample": "one full 200x200x36 map (1,440,000 states), FP64 oracle, OpenMP"}
+            "kind": "oracle", "seconds_per_map": dt,
+            "sample": f"{repeats} full 200x200x36 maps (1,440,000 states each), FP64 oracle, "
+                      f"OpenMP over rows, median per map"}
+
+
+def calibrate_copy(torch, mib: int = 256):
+    """A plain device copy of known size, so that HBM byte counters read in the
+    same profiling run can be scaled (FETCH_SIZE / WRITE_SIZE per copied byte)."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
 
 
 def main():
@@ -160,6 +177,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 256 MiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the assessment has no multi-GPU path "
@@ -170,6 +189,8 @@ def main():
     from paper_2503_02412_amd import seb
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.calibrate_copy:
+        calibrate_copy(torch)
     p = I.CONFIG2
     hmap = I.config2_map(2)
     ctx = seb.Context(p)

@@ -102,9 +102,11 @@ def test_unknown_and_flat_maps(torch_cuda):
     p = I.CONFIG1
     g = run(torch_cuda, p, np.full((64, 64), np.nan, np.float32))
     assert np.all(g["status"] == 0) and np.all(g["risk"] == 1.0) and np.all(np.isnan(g["z"]))
+    # FP32 bilinear sums round at about 1e-7 |h| per sample: a level map at
+    # 2.5 m comes out level and riskless to ~1e-6.
     g = run(torch_cuda, p, np.full((64, 64), 2.5, np.float32))
-    assert np.all(g["status"] & 1) and np.max(np.abs(g["z"] - 2.5)) < 1e-6
-    assert np.max(np.abs(g["roll"])) < 1e-6 and np.max(g["risk"]) < 1e-6
+    assert np.all(g["status"] & 1) and np.max(np.abs(g["z"] - 2.5)) < 1e-5
+    assert np.max(np.abs(g["roll"])) < 1e-5 and np.max(g["risk"]) < 1e-5
     g = run(torch_cuda, p, np.full((64, 64), np.inf, np.float32))
     assert np.all(g["status"] == 0)
 
@@ -153,14 +155,34 @@ def test_determinism_and_translation(torch_cuda):
         assert np.array_equal(a[f][sl], c[f][sl2], equal_nan=True), f
 
 
+def hardest_subregion(h, reach, size=64, stride=16):
+    """The size x size window (on a stride lattice) whose states see the most
+    unknown or out-of-map cells within footprint reach -- chosen from the input
+    map alone."""
+    dx0, dx1, dy0, dy1 = reach
+    pad = max(-dx0, dx1, -dy0, dy1)
+    Hh, Ww = h.shape
+    bad = np.ones((Hh + 2 * pad, Ww + 2 * pad))
+    bad[pad:pad + Hh, pad:pad + Ww] = np.isnan(h)
+    cs = np.zeros((bad.shape[0] + 1, bad.shape[1] + 1))
+    cs[1:, 1:] = bad.cumsum(0).cumsum(1)
+    best, arg = -1.0, (0, 0)
+    span = size + 2 * pad
+    for y0 in range(0, Hh - size + 1, stride):
+        for x0 in range(0, Ww - size + 1, stride):
+            v = cs[y0 + span, x0 + span] - cs[y0, x0 + span] - cs[y0 + span, x0] + cs[y0, x0]
+            if v > best:
+                best, arg = v, (x0, y0)
+    return arg
+
+
 def test_precision_mode_on_degenerate_states(torch_cuda, orc):
     """FP32 + FP64 (precision 1) on the large-footprint map with 15% holes:
     near-degenerate states are recomputed in FP64 and land much closer to
     the oracle."""
     p0 = I.CONFIG5
     h = I.config5_map(5)
-    # 64 x 64 subregion, all 72 yaw bins
-    x0 = y0 = 400
+    x0, y0 = hardest_subregion(h, orc.reach(p0))
     errs = {}
     for prec in (0, 1):
         p = p0.with_(precision=prec)
