@@ -181,8 +181,8 @@ def main():
                     help="also run a 256 MiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the assessment has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the assessment has no multi-GPU path; "
+              "run it without --gpus or with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

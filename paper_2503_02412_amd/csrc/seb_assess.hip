@@ -120,66 +120,119 @@ __device__ Result finish(const AssessArgs& a, const Moments<T>& m, T ref) {
     return r;
 }
 
-// FP32 moments of one yaw bin.  tp0 points at the lane's own cell in LDS.
+// Bilinear sample of the lane's state, centred on ref.  Corner weights are
+// wave-uniform scalars; the four heights come from two paired LDS reads.
 template <int P>
-__device__ __forceinline__ void accumulate32(const AssessArgs& a, const float* tp0,
-                                             cptr<TblEntry> T, float ref, Moments<float>& m) {
+__device__ __forceinline__ float sample(const float* tp0, int off, float4 w, float ref) {
+    const float* tp = tp0 + off;
+    float z = fmaf(w.x, tp[0], -ref);
+    z = fmaf(w.y, tp[1], z);
+    z = fmaf(w.z, tp[P], z);
+    return fmaf(w.w, tp[P + 1], z);
+}
+
+// Per-segment integer moments: (count, sum q, sum q^2) unpacked from pk and
+// combined with the segment's body-x index p.
+__device__ __forceinline__ void add_segment(Moments<float>& m, int p, uint32_t pk, int qoff,
+                                            uint32_t mask1, int sh2, float rz) {
+    const int c = (int)(pk & 63u);
+    const int Q = (int)((pk >> 6) & mask1) - qoff * c;
+    const int QQ = (int)(pk >> sh2);
+    m.N += c;
+    m.Sp += p * c;
+    m.Spp += p * p * c;
+    m.Sq += Q;
+    m.Spq += p * Q;
+    m.Sqq += QQ;
+    m.Sz += rz;
+    m.Spz = fmaf((float)p, rz, m.Spz);
+}
+
+constexpr int bits_for(int v) {
+    int b = 0;
+    while ((1 << b) <= v) ++b;
+    return b;
+}
+
+// FP32 moments of one yaw bin when every segment is a full row of NW samples:
+// the row loop is unrolled, so q and the packed integer constants of each
+// sample are literals and only the weights and offsets are loaded.
+template <int P, int NW>
+__device__ __forceinline__ void accumulate_rows(const AssessArgs& a, const float* tp0,
+                                                cptr<float4> W, cptr<int32_t> O, float ref,
+                                                Moments<float>& m) {
+    constexpr int kQoff = NW - 1;
+    constexpr int kSh2 = 6 + bits_for(NW * 2 * kQoff);
+    constexpr uint32_t kMask1 = (1u << (kSh2 - 6)) - 1u;
+    static_assert(kSh2 + bits_for(NW * kQoff * kQoff) <= 32, "packed moments overflow");
+    m.Sz = m.Spz = m.Sqz = m.Szz = 0.f;
+    m.N = m.Sp = m.Sq = m.Spp = m.Spq = m.Sqq = 0;
+    const int nrows = a.n_segs;
+    int p = 1 - nrows;
+    for (int i = 0; i < nrows; ++i, p += 2) {
+        float rz = 0.f;
+        uint32_t pk = 0u;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const float z = sample<P>(tp0, O[i * NW + j], W[i * NW + j], ref);
+            if (fabsf(z) < VALID_LIMIT) {
+                const int q = 2 * j - kQoff;
+                rz += z;
+                m.Sqz = fmaf((float)q, z, m.Sqz);
+                m.Szz = fmaf(z, z, m.Szz);
+                pk += 1u | ((uint32_t)(2 * j) << 6) | ((uint32_t)(q * q) << kSh2);
+            }
+        }
+        add_segment(m, p, pk, kQoff, kMask1, kSh2, rz);
+    }
+}
+
+// FP32 moments of one yaw bin, any footprint (segments of any length).
+template <int P>
+__device__ __forceinline__ void accumulate_segments(const AssessArgs& a, const float* tp0,
+                                                    cptr<float4> W, cptr<int32_t> O, float ref,
+                                                    Moments<float>& m) {
     m.Sz = m.Spz = m.Sqz = m.Szz = 0.f;
     m.N = m.Sp = m.Sq = m.Spp = m.Spq = m.Sqq = 0;
     const cptr<Segment> segs = as_const(a.segs);
+    const cptr<float> qs = as_const(a.qs);
+    const cptr<uint32_t> pks = as_const(a.pks);
     for (int g = 0; g < a.n_segs; ++g) {
         const Segment sg = segs[g];
-        const cptr<TblEntry> e = T + sg.first;
         float rz = 0.f;
         uint32_t pk = 0u;
-        for (int s = 0; s < sg.count; ++s) {
-            const TblEntry t = e[s];
-            const float* tp = tp0 + t.off;
-            float z = fmaf(t.w00, tp[0], -ref);
-            z = fmaf(t.w01, tp[1], z);
-            z = fmaf(t.w10, tp[P], z);
-            z = fmaf(t.w11, tp[P + 1], z);
+        for (int s = sg.first; s < sg.first + sg.count; ++s) {
+            const float z = sample<P>(tp0, O[s], W[s], ref);
             if (fabsf(z) < VALID_LIMIT) {
                 rz += z;
-                m.Sqz = fmaf(t.q, z, m.Sqz);
+                m.Sqz = fmaf(qs[s], z, m.Sqz);
                 m.Szz = fmaf(z, z, m.Szz);
-                pk += t.pk;
+                pk += pks[s];
             }
         }
-        const int c = (int)(pk & 63u);
-        const int s1 = (int)((pk >> 6) & a.mask1);
-        const int s2 = (int)(pk >> a.sh2);
-        const int Q = s1 - a.qoff * c;
-        m.N += c;
-        m.Sp += sg.p * c;
-        m.Spp += sg.p * sg.p * c;
-        m.Sq += Q;
-        m.Spq += sg.p * Q;
-        m.Sqq += s2;
-        m.Sz += rz;
-        m.Spz = fmaf((float)sg.p, rz, m.Spz);
+        add_segment(m, sg.p, pk, a.qoff, a.mask1, a.sh2, rz);
     }
 }
 
 // FP64 moments of one yaw bin, with FP64 bilinear weights (near-degenerate path).
 template <int P>
-__device__ void accumulate64(const AssessArgs& a, const float* tp0, cptr<TblEntry> T,
+__device__ void accumulate64(const AssessArgs& a, const float* tp0, cptr<int32_t> O,
                              cptr<double2> FR, double ref, Moments<double>& m) {
     m.Sz = m.Spz = m.Sqz = m.Szz = 0.0;
     m.N = m.Sp = m.Sq = m.Spp = m.Spq = m.Sqq = 0;
     const cptr<Segment> segs = as_const(a.segs);
+    const cptr<float> qs = as_const(a.qs);
     for (int g = 0; g < a.n_segs; ++g) {
         const Segment sg = segs[g];
         double rz = 0.0;
-        for (int s = 0; s < sg.count; ++s) {
-            const TblEntry t = T[sg.first + s];
-            const double2 f = FR[sg.first + s];
-            const float* tp = tp0 + t.off;
+        for (int s = sg.first; s < sg.first + sg.count; ++s) {
+            const double2 f = FR[s];
+            const float* tp = tp0 + O[s];
             const double gx = 1.0 - f.x, gy = 1.0 - f.y;
             const double z = gx * gy * (double)tp[0] + f.x * gy * (double)tp[1] +
                              gx * f.y * (double)tp[P] + f.x * f.y * (double)tp[P + 1] - ref;
             if (fabs(z) < (double)VALID_LIMIT) {
-                const int q = (int)t.q;
+                const int q = (int)qs[s];
                 rz += z;
                 m.Sqz += (double)q * z;
                 m.Szz += z * z;
@@ -206,7 +259,7 @@ __device__ __forceinline__ void store(const AssessArgs& a, int k, int64_t cell, 
     a.status[o] = r.st;
 }
 
-template <int P>
+template <int P, int NW>
 __global__ __launch_bounds__(BLOCK) void assess_kernel(const AssessArgs a) {
     extern __shared__ float tile[];
     const int tid = threadIdx.x;
@@ -252,7 +305,9 @@ __global__ __launch_bounds__(BLOCK) void assess_kernel(const AssessArgs a) {
     const int u0 = blockIdx.y * a.units_per_group;
     const int u1 = min(a.n_units, u0 + a.units_per_group);
     for (int u = u0; u < u1; ++u) {
-        const cptr<TblEntry> T = as_const(a.tbl) + (int64_t)u * a.n_samples;
+        const int64_t ub = (int64_t)u * a.n_samples;
+        const cptr<float4> W = as_const(a.wts) + ub;
+        const cptr<int32_t> O = as_const(a.offs) + ub;
 
         // Reference height: own cell, else the first valid sample in table order.
         // A state with no valid sample keeps ref = 0, so every sample stays invalid.
@@ -261,13 +316,10 @@ __global__ __launch_bounds__(BLOCK) void assess_kernel(const AssessArgs a) {
         if (__ballot(need)) {
             for (int s = 0; s < a.n_samples; ++s) {
                 if (!__ballot(need)) break;
-                const TblEntry t = T[s];
+                const float4 w = W[s];
+                const int off = O[s];
                 if (need) {
-                    const float* tp = tp0 + t.off;
-                    float h = t.w00 * tp[0];
-                    h = fmaf(t.w01, tp[1], h);
-                    h = fmaf(t.w10, tp[P], h);
-                    h = fmaf(t.w11, tp[P + 1], h);
+                    const float h = sample<P>(tp0, off, w, 0.f);
                     if (fabsf(h) < VALID_LIMIT) {
                         ref = h;
                         need = false;
@@ -277,15 +329,17 @@ __global__ __launch_bounds__(BLOCK) void assess_kernel(const AssessArgs a) {
         }
 
         Moments<float> m;
-        accumulate32<P>(a, tp0, T, ref, m);
+        if constexpr (NW > 0)
+            accumulate_rows<P, NW>(a, tp0, W, O, ref, m);
+        else
+            accumulate_segments<P>(a, tp0, W, O, ref, m);
         Result r = finish<float>(a, m, ref);
 
         if (a.precision == 1) {
             const bool redo = (r.st & SEB_ST_DEGEN) != 0;
             if (__ballot(redo) && redo) {
                 Moments<double> md;
-                accumulate64<P>(a, tp0, T, as_const(a.frac) + (int64_t)u * a.n_samples,
-                                (double)ref, md);
+                accumulate64<P>(a, tp0, O, as_const(a.frac) + ub, (double)ref, md);
                 r = finish<double>(a, md, (double)ref);
             }
         }
@@ -336,6 +390,19 @@ int pick_pitch(int R) {
     return 0;
 }
 
+bool has_row_kernel(int row_len) { return row_len == 4 || row_len == 12 || row_len == 24; }
+
+template <int P>
+static hipError_t launch_p(const AssessArgs& a, dim3 grid, size_t lds, hipStream_t stream) {
+    switch (a.row_len) {
+        case 4: hipLaunchKernelGGL((assess_kernel<P, 4>), grid, dim3(BLOCK), lds, stream, a); break;
+        case 12: hipLaunchKernelGGL((assess_kernel<P, 12>), grid, dim3(BLOCK), lds, stream, a); break;
+        case 24: hipLaunchKernelGGL((assess_kernel<P, 24>), grid, dim3(BLOCK), lds, stream, a); break;
+        default: hipLaunchKernelGGL((assess_kernel<P, 0>), grid, dim3(BLOCK), lds, stream, a); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_assess(const AssessArgs& a, int pitch, hipStream_t stream) {
     const int tiles = a.tile_start[a.n_rects];
     if (tiles == 0) return hipSuccess;
@@ -343,13 +410,12 @@ hipError_t launch_assess(const AssessArgs& a, int pitch, hipStream_t stream) {
     const dim3 grid(tiles, groups);
     const size_t lds = (size_t)(TILE + 2 * a.R) * pitch * sizeof(float);
     switch (pitch) {
-        case 48: hipLaunchKernelGGL(assess_kernel<48>, grid, dim3(BLOCK), lds, stream, a); break;
-        case 80: hipLaunchKernelGGL(assess_kernel<80>, grid, dim3(BLOCK), lds, stream, a); break;
-        case 112: hipLaunchKernelGGL(assess_kernel<112>, grid, dim3(BLOCK), lds, stream, a); break;
-        case 144: hipLaunchKernelGGL(assess_kernel<144>, grid, dim3(BLOCK), lds, stream, a); break;
+        case 48: return launch_p<48>(a, grid, lds, stream);
+        case 80: return launch_p<80>(a, grid, lds, stream);
+        case 112: return launch_p<112>(a, grid, lds, stream);
+        case 144: return launch_p<144>(a, grid, lds, stream);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_insert(const InsertArgs& a, hipStream_t stream) {

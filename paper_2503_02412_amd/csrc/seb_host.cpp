@@ -251,8 +251,12 @@ struct seb_ctx {
     seb_config cfg;
     Geometry geo;
     int pitch = 0;
-    TblEntry* d_tbl = nullptr;
+    int row_len = 0;
+    float4* d_wts = nullptr;
+    int32_t* d_offs = nullptr;
     double2* d_frac = nullptr;
+    float* d_qs = nullptr;
+    uint32_t* d_pks = nullptr;
     Segment* d_segs = nullptr;
     int device = 0;
 };
@@ -273,9 +277,13 @@ void base_args(const seb_ctx* c, AssessArgs* a) {
     const seb_config& g = c->cfg;
     a->W = g.width;
     a->H = g.height;
-    a->tbl = c->d_tbl;
+    a->wts = c->d_wts;
+    a->offs = c->d_offs;
     a->frac = c->d_frac;
+    a->qs = c->d_qs;
+    a->pks = c->d_pks;
     a->segs = c->d_segs;
+    a->row_len = c->row_len;
     a->n_units = c->geo.n_units;
     a->mirror = c->geo.mirror;
     a->n_samples = (int)c->geo.samples.size();
@@ -474,46 +482,54 @@ int seb_create(const seb_config* cfg, seb_ctx** out) {
     // an integer corner and bilinear fractions.
     const Geometry& g = c->geo;
     const int ns = (int)g.samples.size();
-    std::vector<TblEntry> tbl((size_t)g.n_units * ns);
+    std::vector<float4> wts((size_t)g.n_units * ns);
+    std::vector<int32_t> offs((size_t)g.n_units * ns);
     std::vector<double2> frac((size_t)g.n_units * ns);
-    const int sh2 = g.sh2;
+    std::vector<float> qs(ns);
+    std::vector<uint32_t> pks(ns);
+    for (int s = 0; s < ns; ++s) {
+        const BodySample& b = g.samples[s];
+        qs[s] = (float)b.q;
+        pks[s] = 1u | ((uint32_t)(b.q + g.qoff) << 6) | ((uint32_t)(b.q * b.q) << g.sh2);
+    }
     for (int u = 0; u < g.n_units; ++u) {
         const double th = 2.0 * kPi * (double)u / (double)cfg->n_yaw;
         const double cth = std::cos(th), sth = std::sin(th);
         for (int s = 0; s < ns; ++s) {
-            const BodySample& b = g.samples[s];
             double ox, oy;
-            grid_offset(*cfg, cth, sth, b, &ox, &oy);
+            grid_offset(*cfg, cth, sth, g.samples[s], &ox, &oy);
             const double flx = std::floor(ox), fly = std::floor(oy);
             const double fx = ox - flx, fy = oy - fly;
-            TblEntry& t = tbl[(size_t)u * ns + s];
-            t.off = (int)fly * c->pitch + (int)flx;
-            t.w00 = (float)((1.0 - fx) * (1.0 - fy));
-            t.w01 = (float)(fx * (1.0 - fy));
-            t.w10 = (float)((1.0 - fx) * fy);
-            t.w11 = (float)(fx * fy);
-            t.q = (float)b.q;
-            t.pk = 1u | ((uint32_t)(b.q + g.qoff) << 6) | ((uint32_t)(b.q * b.q) << sh2);
-            t.pad = 0;
-            frac[(size_t)u * ns + s] = make_double2(fx, fy);
+            const size_t e = (size_t)u * ns + s;
+            offs[e] = (int)fly * c->pitch + (int)flx;
+            wts[e] = make_float4((float)((1.0 - fx) * (1.0 - fy)), (float)(fx * (1.0 - fy)),
+                                 (float)((1.0 - fx) * fy), (float)(fx * fy));
+            frac[e] = make_double2(fx, fy);
         }
     }
-    hipError_t e;
-    if ((e = hipMalloc(&c->d_tbl, tbl.size() * sizeof(TblEntry))) != hipSuccess ||
-        (e = hipMalloc(&c->d_frac, frac.size() * sizeof(double2))) != hipSuccess ||
-        (e = hipMalloc(&c->d_segs, g.segs.size() * sizeof(Segment))) != hipSuccess) {
-        seb_destroy(c);
-        g_last_error = std::string("hipMalloc: ") + hipGetErrorString(e);
-        return SEB_ERR_ALLOC;
+    // The unrolled row kernels need every segment to be one full row.
+    c->row_len = 0;
+    if (has_row_kernel(cfg->fp_nw) && (int)g.segs.size() == cfg->fp_nl) {
+        bool rows = true;
+        for (size_t i = 0; i < g.segs.size(); ++i)
+            rows = rows && g.segs[i].count == cfg->fp_nw && g.segs[i].first == (int)i * cfg->fp_nw;
+        if (rows) c->row_len = cfg->fp_nw;
     }
-    if ((e = hipMemcpy(c->d_tbl, tbl.data(), tbl.size() * sizeof(TblEntry),
-                       hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(c->d_frac, frac.data(), frac.size() * sizeof(double2),
-                       hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(c->d_segs, g.segs.data(), g.segs.size() * sizeof(Segment),
-                       hipMemcpyHostToDevice)) != hipSuccess) {
+    hipError_t e;
+    auto upload = [&](void** dst, const void* src, size_t bytes) {
+        if ((e = hipMalloc(dst, bytes)) != hipSuccess) return false;
+        return (e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice)) == hipSuccess;
+    };
+    if (!upload((void**)&c->d_wts, wts.data(), wts.size() * sizeof(float4)) ||
+        !upload((void**)&c->d_offs, offs.data(), offs.size() * sizeof(int32_t)) ||
+        !upload((void**)&c->d_frac, frac.data(), frac.size() * sizeof(double2)) ||
+        !upload((void**)&c->d_qs, qs.data(), qs.size() * sizeof(float)) ||
+        !upload((void**)&c->d_pks, pks.data(), pks.size() * sizeof(uint32_t)) ||
+        !upload((void**)&c->d_segs, g.segs.data(), g.segs.size() * sizeof(Segment))) {
+        const int code = (e == hipErrorOutOfMemory) ? SEB_ERR_ALLOC : SEB_ERR_HIP;
+        g_last_error = std::string("table upload: ") + hipGetErrorString(e);
         seb_destroy(c);
-        return hip_fail(e, "table upload");
+        return code;
     }
     *out = c;
     return SEB_OK;
@@ -521,9 +537,9 @@ int seb_create(const seb_config* cfg, seb_ctx** out) {
 
 void seb_destroy(seb_ctx* c) {
     if (!c) return;
-    if (c->d_tbl) hipFree(c->d_tbl);
-    if (c->d_frac) hipFree(c->d_frac);
-    if (c->d_segs) hipFree(c->d_segs);
+    for (void* p : {(void*)c->d_wts, (void*)c->d_offs, (void*)c->d_frac, (void*)c->d_qs,
+                    (void*)c->d_pks, (void*)c->d_segs})
+        if (p) hipFree(p);
     delete c;
 }
 

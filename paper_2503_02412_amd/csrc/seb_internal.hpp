@@ -23,15 +23,15 @@ constexpr float SENTINEL = 0x1p110f;
 constexpr float VALID_LIMIT = 0x1p64f;
 constexpr float HEIGHT_LIMIT = 0x1p60f;
 
-// One footprint sample of one yaw bin.  32 bytes; read by the whole wave at
-// once through the scalar unit.
-struct TblEntry {
-    int32_t off;                 // LDS offset (dy * pitch + dx) of the lower-left corner
-    float w00, w01, w10, w11;    // bilinear weights of corners (0,0) (1,0) (0,1) (1,1)
-    float q;                     // body-y sample index q = 2j - (nw-1), as float
-    uint32_t pk;                 // packed (1, q + qoff, q^2) for exact integer moments
-    int32_t pad;
-};
+// The footprint table, structure of arrays, sample order = rows of constant
+// body-x index i, each row in increasing body-y index j:
+//   wts  [n_units][n_samples] float4  bilinear weights of corners (0,0) (1,0) (0,1) (1,1)
+//   offs [n_units][n_samples] int32   LDS offset dy * pitch + dx of corner (0,0)
+//   frac [n_units][n_samples] double2 FP64 fractions (fx, fy) for the FP64 path
+//   qs   [n_samples] float, pks [n_samples] uint32: body-y index q = 2j - (nw-1)
+//        and the packed (1, q + qoff, q^2) of the exact integer moments
+// All entries of one sample are the same for every lane of a wave, which
+// reads them with scalar loads.
 
 // A run of samples sharing the body-x index p (one row of the sample grid, or
 // a piece of it short enough for the packed integer moments not to overflow).
@@ -53,10 +53,15 @@ struct AssessArgs {
     float* pitch;
     float* risk;
     uint8_t* status;
-    // footprint table
-    const TblEntry* tbl;         // [n_units][n_samples]
-    const double2* frac;         // [n_units][n_samples] FP64 (fx, fy) for the FP64 path
+    // footprint table (see above)
+    const float4* wts;
+    const int32_t* offs;
+    const double2* frac;
+    const float* qs;
+    const uint32_t* pks;
     const Segment* segs;         // [n_segs]
+    int32_t row_len;             // samples per segment when every segment is a full
+                                 // row of the rectangle (fast path), else 0
     int32_t n_units;             // yaw bins computed directly
     int32_t mirror;              // K/2 when yaw bin k+K/2 is derived from bin k, else 0
     int32_t n_samples;
@@ -96,6 +101,8 @@ struct InsertArgs {
 
 // Launchers (seb_assess.hip).  Return hipSuccess or the launch error.
 hipError_t launch_assess(const AssessArgs& a, int pitch, hipStream_t stream);
+// Row lengths with a specialised (fully unrolled) inner loop.
+bool has_row_kernel(int row_len);
 hipError_t launch_insert(const InsertArgs& a, hipStream_t stream);
 // LDS pitches (floats) the assessment kernel is instantiated for.
 int pick_pitch(int R);
