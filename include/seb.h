@@ -175,6 +175,96 @@ int seb_plan_window_move(const seb_config* cfg, int64_t origin_x, int64_t origin
 int seb_update_window(seb_window* w, double x, double y, const float* new_cells, void* stream,
                       int64_t* n_states_recomputed);
 
+/* ------------------------------------------------- learned surrogate */
+
+/* A small network that maps the terrain around a cell plus the yaw to the
+ * assessment's outputs (Sec. III Eq. 1-3, Sec. V-B Alg. 1).  Learned
+ * traversability models are discussed in Sec. II, together with their model
+ * uncertainty -- hence the plain-method fallback of seb_surrogate_infer.
+ * Input of cell (cy, cx): three 24 x 24 channels over cells
+ * (cy-12+i, cx-12+j): x-slope and y-slope (height differences to the next
+ * cell / resolution, 0 unless both cells are known) and a known flag.
+ * Layers: conv 3->16 (4x4, stride 2), conv 16->32 (3x3, stride 2), fc
+ * 800 + (sin yaw, cos yaw) -> 128 -> 64 -> 4, ReLU between layers; bf16
+ * weights and activations, fp32 accumulation.  Outputs (dz/0.05 m,
+ * roll/0.5 rad, pitch/0.5 rad, risk) with dz = z - height of the cell.
+ * Parameters: float32 vector of seb_net_param_count() values, in the order
+ * W1[16][3][4][4] b1[16] W2[32][16][3][3] b2[32] W3[128][800] Wy[128][2]
+ * b3[128] W4[64][128] b4[64] W5[4][64] b5[4]; W3's 800 inputs are ordered
+ * (row a, column b, channel) of conv2's 5 x 5 x 32 output. */
+typedef struct seb_net seb_net;
+
+/* A batch of training (or forward) samples drawn from a set of maps. */
+typedef struct seb_train_batch {
+    const float* maps;           /* device [n_maps][map_h][map_w] heights, NaN = unknown */
+    int32_t n_maps, map_h, map_w;
+    double resolution;
+    int32_t n_yaw;               /* K of the labels; yaw k means theta = 2 pi k / K   */
+    const float* label_z;        /* device [n_maps][K][map_h][map_w] plain-method     */
+    const float* label_roll;     /* outputs for the maps (training only; may be NULL  */
+    const float* label_pitch;    /* for seb_net_forward)                               */
+    const float* label_risk;
+    const int32_t* samples;      /* device [batch][4]: map, cy, cx, k                  */
+    int32_t batch;               /* multiple of 32, <= the net's max_batch             */
+} seb_train_batch;
+
+int64_t seb_net_param_count(void);
+
+/* Create a network with counter-based random initial weights (He-uniform
+ * from splitmix64(seed, index)), zero biases and Adam state, and a training
+ * workspace for batches up to max_batch (multiple of 32, <= 65536).
+ * Synchronises the device.  Errors: SEB_ERR_INVALID, SEB_ERR_ALLOC, SEB_ERR_HIP. */
+int seb_net_create(uint64_t seed, int32_t max_batch, seb_net** out);
+void seb_net_destroy(seb_net* net);
+
+/* Copy the float32 parameter vector to / from host memory (synchronous).
+ * Setting parameters resets the Adam state. */
+int seb_net_get_params(const seb_net* net, float* host_params);
+int seb_net_set_params(seb_net* net, const float* host_params);
+
+/* Checkpoint: parameters, Adam moments and step in one file ("SEBNET01",
+ * int64 count, int64 step, then three float32 vectors).  Synchronous.
+ * Errors: SEB_ERR_IO for unreadable / malformed files. */
+int seb_net_save(const seb_net* net, const char* path);
+int seb_net_load(seb_net* net, const char* path);
+
+/* Forward pass over the batch's samples: y_dev (device [batch][4]) receives
+ * the scaled outputs. */
+int seb_net_forward(seb_net* net, const seb_train_batch* batch, float* y_dev, void* stream);
+
+/* One training step on the batch: loss = mean over samples of the squared
+ * error of the four scaled outputs against the labels (targets
+ * ((z - h_cell)/0.05, roll/0.5, pitch/0.5, risk)); backward pass; Adam
+ * (lr, beta 0.9 / 0.999, eps 1e-8) on float32 master weights.  loss_dev
+ * (device float, may be NULL) receives the batch loss.  If grad_dev (device
+ * [param_count]) is non-NULL the gradient is written there and the weights
+ * are NOT updated. */
+int seb_net_train_step(seb_net* net, const seb_train_batch* batch, float lr, float* loss_dev,
+                       float* grad_dev, void* stream);
+const char* seb_net_last_error(void);
+
+/* Surrogate inference over a whole map with the plain method as fallback.
+ * seb_surrogate_create allocates the workspace for ctx's map size (conv maps,
+ * per-cell features, per-yaw fallback lists); release with
+ * seb_surrogate_destroy.  The network must have been trained for ctx's
+ * configuration (resolution, footprint, yaw bins, constants). */
+typedef struct seb_surrogate seb_surrogate;
+int seb_surrogate_create(seb_ctx* ctx, seb_surrogate** out);
+void seb_surrogate_destroy(seb_surrogate* s);
+
+/* Fill `out` ([K][H][W]) for every state of the map `height` ([H][W], row
+ * stride ld).  Network outputs are written with status SEB_ST_VALID |
+ * SEB_ST_SURROGATE (| SEB_ST_TRAV when risk <= risk_max).  A state falls back
+ * to the plain method (Alg. 1 exactly as seb_assess_se2 computes it) when its
+ * own cell is unknown, when fewer than min_known of the 24 x 24 window's cells
+ * are known (outside the training distribution), or when the predicted risk
+ * lies within `band` of risk_max.  *n_fallback_dev (device int32, may be NULL)
+ * receives the number of states that fell back.  Asynchronous on `stream`;
+ * allocates nothing.  One surrogate handle serves one stream at a time. */
+int seb_surrogate_infer(seb_surrogate* s, const seb_net* net, const float* height, int64_t ld,
+                        const seb_out* out, float band, float min_known, int32_t* n_fallback_dev,
+                        void* stream);
+
 /* --------------------------------------------------------------- misc */
 
 const char* seb_strerror(int status);

@@ -25,239 +25,12 @@
 
 #include "../../include/seb.h"
 #include "seb_internal.hpp"
+#include "seb_state_device.hpp"
 
 namespace seb {
 namespace {
 
-template <typename T>
-struct Moments {
-    T Sz, Spz, Sqz, Szz;          // sums over valid samples of z, p z, q z, z^2 (z centred)
-    int32_t N, Sp, Sq, Spp, Spq, Sqq;
-};
-
-struct Result {
-    float z, roll, pitch, risk;
-    uint8_t st;
-};
-
-__device__ __forceinline__ int wrap(int v, int n) { return v >= n ? v - n : v; }
-
-// The footprint table is read-only for the lifetime of a launch.  Reading it
-// through the constant address space lets the compiler fetch wave-uniform
-// entries with scalar loads even though the kernel also stores to global memory.
-// (The host compilation pass of this file only parses the kernels, so there
-// the qualifier is dropped.)
-#if defined(__HIP_DEVICE_COMPILE__)
-#define SEB_CONSTANT_AS __attribute__((address_space(4)))
-#else
-#define SEB_CONSTANT_AS
-#endif
-template <typename T>
-using cptr = const SEB_CONSTANT_AS T*;
-
-template <typename T>
-__device__ __forceinline__ cptr<T> as_const(const T* p) {
-    return (cptr<T>)(p);
-}
-
-// Least-squares plane z = a + b u + c v from the moments, then Eq. 1-3 and
-// Algorithm 1.  u = hu p, v = hv q are the body-frame sample coordinates.
-template <typename T>
-__device__ Result finish(const AssessArgs& a, const Moments<T>& m, T ref) {
-    Result r;
-    const int64_t N = m.N;
-    const int64_t D = N * (int64_t)m.Spp - (int64_t)m.Sp * m.Sp;
-    const int64_t E = N * (int64_t)m.Sqq - (int64_t)m.Sq * m.Sq;
-    const int64_t F = N * (int64_t)m.Spq - (int64_t)m.Sp * m.Sq;
-    const int64_t det = D * E - F * F;
-    if (N < a.min_valid || det <= 0) {
-        r.z = r.roll = r.pitch = __builtin_nanf("");
-        r.risk = 1.f;
-        r.st = 0;
-        return r;
-    }
-    uint8_t st = SEB_ST_VALID;
-    const double de = (double)(D + E);
-    if (2 * N < a.n_total || (4.0 * (double)det) / (de * de) < a.rho16) st |= SEB_ST_DEGEN;
-
-    const T invN = T(1) / T(N);
-    const T zb = m.Sz * invN;
-    const T pz = m.Spz - T(m.Sp) * zb;      // sum (p - pbar)(z - zbar)
-    const T qz = m.Sqz - T(m.Sq) * zb;
-    const T zz = m.Szz - m.Sz * zb;         // sum (z - zbar)^2
-    const T tdet = T(det);
-    const T bp = T(N) * (T(E) * pz - T(F) * qz) / tdet;   // dz/dp
-    const T bq = T(N) * (T(D) * qz - T(F) * pz) / tdet;   // dz/dq
-    const T b = bp / T(a.hu), c = bq / T(a.hv);           // dz/du, dz/dv
-    const T zc = ref + zb - bp * (T(m.Sp) * invN) - bq * (T(m.Sq) * invN);
-    T sse = zz - bp * pz - bq * qz;
-    if (sse < T(0)) sse = T(0);
-    const T s2 = T(1) + b * b + c * c;
-    const T tr = T(a.hu) * T(a.hu) * T(D) * invN + T(a.hv) * T(a.hv) * T(E) * invN + zz;
-    const float kappa = (tr > T(0)) ? (float)(sse / (s2 * tr)) : 0.f;
-
-    const float bf = (float)b, cf = (float)c;
-    const float c1 = 1.f + cf * cf;
-    r.z = (float)zc;
-    r.roll = atanf(cf);                              // asin(b3 . y_b)
-    r.pitch = -atan2f(bf, sqrtf(c1));               // atan2(-b3 . x_b, b3 . z_b)
-    const float phx = atan2f(fabsf(bf), sqrtf(c1 * c1 + bf * bf * cf * cf));   // |asin(b3 . x_b)|
-    const float phy = fabsf(r.roll);                                             // |asin(b3 . y_b)|
-    float risk;
-    if (kappa > a.kappa_max) {
-        risk = 1.f;
-        st |= SEB_ST_CURV;
-    } else if (phx > a.phi_x_max || phy > a.phi_y_max) {
-        risk = 1.f;
-        st |= SEB_ST_TILT;
-    } else {
-        risk = a.w_kappa * kappa / a.kappa_max + a.w_phi_x * phx / a.phi_x_max +
-               a.w_phi_y * phy / a.phi_y_max;
-    }
-    if (risk <= a.risk_max) st |= SEB_ST_TRAV;
-    r.risk = risk;
-    r.st = st;
-    return r;
-}
-
-// Bilinear sample of the lane's state, centred on ref.  Corner weights are
-// wave-uniform scalars; the four heights come from two paired LDS reads.
-template <int P>
-__device__ __forceinline__ float sample(const float* tp0, int off, float4 w, float ref) {
-    const float* tp = tp0 + off;
-    float z = fmaf(w.x, tp[0], -ref);
-    z = fmaf(w.y, tp[1], z);
-    z = fmaf(w.z, tp[P], z);
-    return fmaf(w.w, tp[P + 1], z);
-}
-
-// Per-segment integer moments: (count, sum q, sum q^2) unpacked from pk and
-// combined with the segment's body-x index p.
-__device__ __forceinline__ void add_segment(Moments<float>& m, int p, uint32_t pk, int qoff,
-                                            uint32_t mask1, int sh2, float rz) {
-    const int c = (int)(pk & 63u);
-    const int Q = (int)((pk >> 6) & mask1) - qoff * c;
-    const int QQ = (int)(pk >> sh2);
-    m.N += c;
-    m.Sp += p * c;
-    m.Spp += p * p * c;
-    m.Sq += Q;
-    m.Spq += p * Q;
-    m.Sqq += QQ;
-    m.Sz += rz;
-    m.Spz = fmaf((float)p, rz, m.Spz);
-}
-
-constexpr int bits_for(int v) {
-    int b = 0;
-    while ((1 << b) <= v) ++b;
-    return b;
-}
-
-// FP32 moments of one yaw bin when every segment is a full row of NW samples:
-// the row loop is unrolled, so q and the packed integer constants of each
-// sample are literals and only the weights and offsets are loaded.
-template <int P, int NW>
-__device__ __forceinline__ void accumulate_rows(const AssessArgs& a, const float* tp0,
-                                                cptr<float4> W, cptr<int32_t> O, float ref,
-                                                Moments<float>& m) {
-    constexpr int kQoff = NW - 1;
-    constexpr int kSh2 = 6 + bits_for(NW * 2 * kQoff);
-    constexpr uint32_t kMask1 = (1u << (kSh2 - 6)) - 1u;
-    static_assert(kSh2 + bits_for(NW * kQoff * kQoff) <= 32, "packed moments overflow");
-    m.Sz = m.Spz = m.Sqz = m.Szz = 0.f;
-    m.N = m.Sp = m.Sq = m.Spp = m.Spq = m.Sqq = 0;
-    const int nrows = a.n_segs;
-    int p = 1 - nrows;
-    for (int i = 0; i < nrows; ++i, p += 2) {
-        float rz = 0.f;
-        uint32_t pk = 0u;
-#pragma unroll
-        for (int j = 0; j < NW; ++j) {
-            const float z = sample<P>(tp0, O[i * NW + j], W[i * NW + j], ref);
-            if (fabsf(z) < VALID_LIMIT) {
-                const int q = 2 * j - kQoff;
-                rz += z;
-                m.Sqz = fmaf((float)q, z, m.Sqz);
-                m.Szz = fmaf(z, z, m.Szz);
-                pk += 1u | ((uint32_t)(2 * j) << 6) | ((uint32_t)(q * q) << kSh2);
-            }
-        }
-        add_segment(m, p, pk, kQoff, kMask1, kSh2, rz);
-    }
-}
-
-// FP32 moments of one yaw bin, any footprint (segments of any length).
-template <int P>
-__device__ __forceinline__ void accumulate_segments(const AssessArgs& a, const float* tp0,
-                                                    cptr<float4> W, cptr<int32_t> O, float ref,
-                                                    Moments<float>& m) {
-    m.Sz = m.Spz = m.Sqz = m.Szz = 0.f;
-    m.N = m.Sp = m.Sq = m.Spp = m.Spq = m.Sqq = 0;
-    const cptr<Segment> segs = as_const(a.segs);
-    const cptr<float> qs = as_const(a.qs);
-    const cptr<uint32_t> pks = as_const(a.pks);
-    for (int g = 0; g < a.n_segs; ++g) {
-        const Segment sg = segs[g];
-        float rz = 0.f;
-        uint32_t pk = 0u;
-        for (int s = sg.first; s < sg.first + sg.count; ++s) {
-            const float z = sample<P>(tp0, O[s], W[s], ref);
-            if (fabsf(z) < VALID_LIMIT) {
-                rz += z;
-                m.Sqz = fmaf(qs[s], z, m.Sqz);
-                m.Szz = fmaf(z, z, m.Szz);
-                pk += pks[s];
-            }
-        }
-        add_segment(m, sg.p, pk, a.qoff, a.mask1, a.sh2, rz);
-    }
-}
-
-// FP64 moments of one yaw bin, with FP64 bilinear weights (near-degenerate path).
-template <int P>
-__device__ void accumulate64(const AssessArgs& a, const float* tp0, cptr<int32_t> O,
-                             cptr<double2> FR, double ref, Moments<double>& m) {
-    m.Sz = m.Spz = m.Sqz = m.Szz = 0.0;
-    m.N = m.Sp = m.Sq = m.Spp = m.Spq = m.Sqq = 0;
-    const cptr<Segment> segs = as_const(a.segs);
-    const cptr<float> qs = as_const(a.qs);
-    for (int g = 0; g < a.n_segs; ++g) {
-        const Segment sg = segs[g];
-        double rz = 0.0;
-        for (int s = sg.first; s < sg.first + sg.count; ++s) {
-            const double2 f = FR[s];
-            const float* tp = tp0 + O[s];
-            const double gx = 1.0 - f.x, gy = 1.0 - f.y;
-            const double z = gx * gy * (double)tp[0] + f.x * gy * (double)tp[1] +
-                             gx * f.y * (double)tp[P] + f.x * f.y * (double)tp[P + 1] - ref;
-            if (fabs(z) < (double)VALID_LIMIT) {
-                const int q = (int)qs[s];
-                rz += z;
-                m.Sqz += (double)q * z;
-                m.Szz += z * z;
-                m.N += 1;
-                m.Sq += q;
-                m.Sqq += q * q;
-                m.Sp += sg.p;
-                m.Spp += sg.p * sg.p;
-                m.Spq += sg.p * q;
-            }
-        }
-        m.Sz += rz;
-        m.Spz += (double)sg.p * rz;
-    }
-}
-
-__device__ __forceinline__ void store(const AssessArgs& a, int k, int64_t cell, const Result& r,
-                                      bool negate) {
-    const int64_t o = (int64_t)k * a.H * a.W + cell;
-    a.z[o] = r.z;
-    a.roll[o] = negate ? -r.roll : r.roll;
-    a.pitch[o] = negate ? -r.pitch : r.pitch;
-    a.risk[o] = r.risk;
-    a.status[o] = r.st;
-}
+using namespace dev;
 
 template <int P, int NW>
 __global__ __launch_bounds__(BLOCK) void assess_kernel(const AssessArgs a) {
@@ -305,45 +78,7 @@ __global__ __launch_bounds__(BLOCK) void assess_kernel(const AssessArgs a) {
     const int u0 = blockIdx.y * a.units_per_group;
     const int u1 = min(a.n_units, u0 + a.units_per_group);
     for (int u = u0; u < u1; ++u) {
-        const int64_t ub = (int64_t)u * a.n_samples;
-        const cptr<float4> W = as_const(a.wts) + ub;
-        const cptr<int32_t> O = as_const(a.offs) + ub;
-
-        // Reference height: own cell, else the first valid sample in table order.
-        // A state with no valid sample keeps ref = 0, so every sample stays invalid.
-        float ref = (fabsf(hc) < HEIGHT_LIMIT) ? hc : 0.f;
-        bool need = active && !(fabsf(hc) < HEIGHT_LIMIT);
-        if (__ballot(need)) {
-            for (int s = 0; s < a.n_samples; ++s) {
-                if (!__ballot(need)) break;
-                const float4 w = W[s];
-                const int off = O[s];
-                if (need) {
-                    const float h = sample<P>(tp0, off, w, 0.f);
-                    if (fabsf(h) < VALID_LIMIT) {
-                        ref = h;
-                        need = false;
-                    }
-                }
-            }
-        }
-
-        Moments<float> m;
-        if constexpr (NW > 0)
-            accumulate_rows<P, NW>(a, tp0, W, O, ref, m);
-        else
-            accumulate_segments<P>(a, tp0, W, O, ref, m);
-        Result r = finish<float>(a, m, ref);
-
-        if (a.precision == 1) {
-            const bool redo = (r.st & SEB_ST_DEGEN) != 0;
-            if (__ballot(redo) && redo) {
-                Moments<double> md;
-                accumulate64<P>(a, tp0, O, as_const(a.frac) + ub, (double)ref, md);
-                r = finish<double>(a, md, (double)ref);
-            }
-        }
-
+        const Result r = assess_state<NW>(a, LdsSource<P>{tp0}, u, hc, active);
         if (active) {
             store(a, u, cell, r, false);
             if (a.mirror) store(a, u + a.mirror, cell, r, true);

@@ -13,6 +13,8 @@
 
 #include "../../include/seb.h"
 #include "seb_internal.hpp"
+#include "seb_net_internal.hpp"
+#include "seb_surrogate_internal.hpp"
 
 using namespace seb;
 
@@ -259,6 +261,12 @@ struct seb_ctx {
     uint32_t* d_pks = nullptr;
     Segment* d_segs = nullptr;
     int device = 0;
+};
+
+struct seb_surrogate {
+    seb_ctx* ctx;
+    std::vector<void*> allocs;
+    seb::sur::SurArgs ws;   // workspace pointers and map geometry
 };
 
 struct seb_window {
@@ -672,6 +680,82 @@ int seb_update_window(seb_window* w, double x, double y, const float* new_cells,
     if (p.n_rects == 0) return SEB_OK;
     return run_assess(c, w->ring, w->ld, ia.rx, ia.ry, &w->out, p.n_rects, p.rects,
                       (hipStream_t)stream);
+}
+
+int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
+    if (!out) return fail(SEB_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!c) return fail(SEB_ERR_INVALID, "ctx is NULL");
+    seb_surrogate* s = new (std::nothrow) seb_surrogate();
+    if (!s) return fail(SEB_ERR_ALLOC, "host allocation failed");
+    s->ctx = c;
+    const int64_t W = c->cfg.width, H = c->cfg.height, cells = W * H;
+    const int U = c->geo.n_units;
+    auto al = [&](void** p, size_t bytes) {
+        if (hipMalloc(p, bytes) != hipSuccess) return false;
+        s->allocs.push_back(*p);
+        return true;
+    };
+    seb::sur::SurArgs& w = s->ws;
+    std::memset(&w, 0, sizeof(w));
+    const bool ok =
+        al((void**)&w.o1map, (size_t)(H + 20) * (W + 20) * seb::net::C1 * 2) &&
+        al((void**)&w.o2map, (size_t)(H + 16) * (W + 16) * seb::net::C2 * 2) &&
+        al((void**)&w.T, (size_t)cells * seb::net::H1 * 4) &&
+        al((void**)&w.Y, (size_t)U * seb::net::H1 * 4) && al((void**)&w.rows, (size_t)cells * 4) &&
+        al((void**)&w.known, (size_t)cells * 4) &&
+        al((void**)&w.counts, (size_t)c->cfg.n_yaw * 4) &&
+        al((void**)&w.lists, (size_t)U * cells * 4);
+    if (!ok) {
+        seb_surrogate_destroy(s);
+        return fail(SEB_ERR_ALLOC, "device allocation failed");
+    }
+    w.W = (int)W;
+    w.H = (int)H;
+    w.inv_res = (float)(1.0 / c->cfg.resolution);
+    w.K = c->cfg.n_yaw;
+    w.U = U;
+    w.mirror = c->geo.mirror;
+    w.pitch = c->pitch;
+    w.risk_max = (float)c->cfg.risk_max;
+    *out = s;
+    return SEB_OK;
+}
+
+void seb_surrogate_destroy(seb_surrogate* s) {
+    if (!s) return;
+    for (void* p : s->allocs) hipFree(p);
+    delete s;
+}
+
+int seb_surrogate_infer(seb_surrogate* s, const seb_net* net, const float* height, int64_t ld,
+                        const seb_out* out, float band, float min_known, int32_t* n_fallback_dev,
+                        void* stream) {
+    if (!s || !net || !height) return fail(SEB_ERR_INVALID, "surrogate, net and height must be set");
+    int rc = check_out(out);
+    if (rc != SEB_OK) return rc;
+    if (ld < s->ws.W) return fail(SEB_ERR_INVALID, "ld must be >= width");
+    if (!(band >= 0.f) || !(min_known >= 0.f) || !(min_known <= 1.f))
+        return fail(SEB_ERR_INVALID, "band must be >= 0 and min_known in [0, 1]");
+    seb::sur::SurArgs w = s->ws;
+    w.height = height;
+    w.ld = ld;
+    w.theta = seb::net::net_theta(net);
+    w.pw = seb::net::net_packed(net);
+    w.band = band;
+    w.min_known = min_known;
+    AssessArgs a;
+    base_args(s->ctx, &a);
+    a.height = height;
+    a.ld = ld;
+    a.z = out->z;
+    a.roll = out->roll;
+    a.pitch = out->pitch;
+    a.risk = out->risk;
+    a.status = out->status;
+    const hipError_t e = seb::sur::launch_surrogate(w, a, n_fallback_dev, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "surrogate launch");
+    return SEB_OK;
 }
 
 const char* seb_strerror(int status) {

@@ -1,0 +1,798 @@
+// Learned surrogate of the SE(2) assessment: training kernels (patch form) on
+// bf16 MFMA for gfx950, Adam, and the C ABI of the network handle.
+//
+// Every layer of the patch-form network is one "NT" GEMM, C[m][n] =
+// sum_k A[m][k] B[n][k], both operands K-contiguous bf16, fp32 accumulation on
+// v_mfma_f32_16x16x32_bf16.  Backward data products use transposed weight
+// copies; weight gradients are NT GEMMs of transposed deltas and activations
+// with split-K partials reduced deterministically into the parameter layout.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/seb.h"
+#include "seb_net_internal.hpp"
+
+namespace seb {
+namespace net {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf16 to_bf16(float f) {
+    // round to nearest even (inputs are finite)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __builtin_bit_cast(bf16, (uint16_t)(u >> 16));
+}
+__device__ __forceinline__ float from_bf16(bf16 h) {
+    return __uint_as_float((uint32_t)__builtin_bit_cast(uint16_t, h) << 16);
+}
+
+// ------------------------------------------------------------------ GEMM
+// Block tile 64 x 64, four waves of 32 x 32 (2 x 2 MFMA tiles of 16 x 16).
+// Operand fragments are loaded straight from global memory: lane l holds
+// row (l % 16) and k-block 8 (l / 16) of its 16 x 32 A and B slices; the
+// accumulator of lane l holds rows 4 (l / 16) + e, column l % 16.
+__global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmArgs g) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m0 = blockIdx.x * 64 + (wave >> 1) * 32;
+    const int n0 = blockIdx.y * 64 + (wave & 1) * 32;
+    const int kb = blockIdx.z * g.kchunk;
+    const int ke = min(g.K, kb + g.kchunk);
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    f32x4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero8 = {};
+    if (m0 < g.M && n0 < g.N) {
+        for (int k = kb; k < ke; k += 32) {
+            bf16x8 a[2], b[2];
+            for (int t = 0; t < 2; ++t) {
+                const int m = m0 + 16 * t + r;
+                a[t] = (m < g.M) ? *(const bf16x8*)(g.A + (int64_t)m * g.lda + k + kq) : zero8;
+                const int n = n0 + 16 * t + r;
+                b[t] = (n < g.N) ? *(const bf16x8*)(g.B + (int64_t)n * g.ldb + k + kq) : zero8;
+            }
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int e = 0; e < 4; ++e) {
+                const int m = m0 + 16 * i + 4 * (lane >> 4) + e;
+                const int n = n0 + 16 * j + (lane & 15);
+                if (m >= g.M || n >= g.N) continue;
+                float v = acc[i][j][e];
+                if (g.split) {
+                    g.C[blockIdx.z * g.split + (int64_t)m * g.ldc + n] = v;
+                    continue;
+                }
+                if (g.bias) v += g.bias[n];
+                if (g.rowv)
+                    v += g.rowv[2 * m] * g.colv[2 * n] + g.rowv[2 * m + 1] * g.colv[2 * n + 1];
+                if (g.relu) v = fmaxf(v, 0.f);
+                if (g.gate && !(from_bf16(g.gate[(int64_t)m * g.ldg + n]) > 0.f)) v = 0.f;
+                if (g.C) g.C[(int64_t)m * g.ldc + n] = v;
+                if (g.Cb) g.Cb[(int64_t)m * g.ldcb + n] = to_bf16(v);
+            }
+}
+
+// ------------------------------------------------------ patch-form inputs
+struct BatchArgs {
+    const float* maps;            // [n_maps][mh][mw]
+    int n_maps, mh, mw;
+    float inv_res;
+    int K;
+    const float* lz;              // labels [n_maps][K][mh][mw] (may be null: no targets)
+    const float* lroll;
+    const float* lpitch;
+    const float* lrisk;
+    const int32_t* samples;       // [B][4] (map, cy, cx, k)
+    int B;
+};
+
+__device__ __forceinline__ float map_at(const BatchArgs& a, int mi, int y, int x, float* known) {
+    if (y < 0 || x < 0 || y >= a.mh || x >= a.mw) {
+        *known = 0.f;
+        return 0.f;
+    }
+    const float h = a.maps[((int64_t)mi * a.mh + y) * a.mw + x];
+    const bool ok = fabsf(h) < 0x1p60f;
+    *known = ok ? 1.f : 0.f;
+    return ok ? h : 0.f;
+}
+
+// Channel c (0: x-slope, 1: y-slope, 2: known) of map cell (y, x).
+__device__ __forceinline__ float encode(const BatchArgs& a, int mi, int y, int x, int c) {
+    float v0, v1;
+    const float h0 = map_at(a, mi, y, x, &v0);
+    if (c == 2) return v0;
+    const float h1 = (c == 0) ? map_at(a, mi, y, x + 1, &v1) : map_at(a, mi, y + 1, x, &v1);
+    return v0 * v1 * (h1 - h0) * a.inv_res;
+}
+
+// conv1 im2col: A1[(b*121 + a*11 + bb)][c*16 + i*4 + j]; yaw features and targets.
+__global__ __launch_bounds__(256) void im2col1_kernel(const BatchArgs a, bf16* A1, float* sc,
+                                                      float* tgt) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t total = (int64_t)a.B * P1 * P1 * K1P;
+    if (idx < total) {
+        const int col = (int)(idx % K1P);
+        const int64_t row = idx / K1P;
+        const int pos = (int)(row % (P1 * P1));
+        const int b = (int)(row / (P1 * P1));
+        float v = 0.f;
+        if (col < K1) {
+            const int c = col / 16, i = (col / 4) % 4, j = col % 4;
+            const int mi = a.samples[4 * b], cy = a.samples[4 * b + 1], cx = a.samples[4 * b + 2];
+            const int y = cy - HALF + 2 * (pos / P1) + i, x = cx - HALF + 2 * (pos % P1) + j;
+            v = encode(a, mi, y, x, c);
+        }
+        A1[idx] = to_bf16(v);
+    }
+    if (idx < a.B) {
+        const int b = (int)idx;
+        const int mi = a.samples[4 * b], cy = a.samples[4 * b + 1], cx = a.samples[4 * b + 2];
+        const int k = a.samples[4 * b + 3];
+        const double th = 2.0 * 3.14159265358979323846 * (double)k / (double)a.K;
+        sc[2 * b] = (float)sin(th);
+        sc[2 * b + 1] = (float)cos(th);
+        if (a.lz) {
+            const int64_t o = (((int64_t)mi * a.K + k) * a.mh + cy) * a.mw + cx;
+            const float hc = a.maps[((int64_t)mi * a.mh + cy) * a.mw + cx];
+            tgt[4 * b] = (a.lz[o] - hc) / S_Z;
+            tgt[4 * b + 1] = a.lroll[o] / S_A;
+            tgt[4 * b + 2] = a.lpitch[o] / S_A;
+            tgt[4 * b + 3] = a.lrisk[o];
+        }
+    }
+}
+
+// conv2 im2col: A2[(b*25 + a2*5 + b2)][(i*3 + j)*16 + c] = o1[b*121 + (2a2+i)*11 + 2b2+j][c].
+__global__ __launch_bounds__(256) void im2col2_kernel(const bf16* o1, bf16* A2, int B) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)B * P2 * P2 * K2P) return;
+    const int col = (int)(idx % K2P);
+    const int64_t row = idx / K2P;
+    const int pos = (int)(row % (P2 * P2));
+    const int b = (int)(row / (P2 * P2));
+    bf16 v = to_bf16(0.f);
+    if (col < K2) {
+        const int tap = col / 16, c = col % 16;
+        const int y = 2 * (pos / P2) + tap / 3, x = 2 * (pos % P2) + tap % 3;
+        v = o1[((int64_t)b * P1 * P1 + y * P1 + x) * C1 + c];
+    }
+    A2[idx] = v;
+}
+
+// Backward of im2col2, gated by conv1's ReLU: da1[b*121 + p][c].
+__global__ __launch_bounds__(256) void col2im2_kernel(const float* dA2, const bf16* o1, bf16* da1,
+                                                      int B) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)B * P1 * P1 * C1) return;
+    const int c = (int)(idx % C1);
+    const int64_t row = idx / C1;
+    const int p = (int)(row % (P1 * P1));
+    const int b = (int)(row / (P1 * P1));
+    const int y = p / P1, x = p % P1;
+    float s = 0.f;
+    for (int i = 0; i < 3; ++i) {
+        const int ty = y - i;
+        if (ty < 0 || (ty & 1) || ty / 2 >= P2) continue;
+        for (int j = 0; j < 3; ++j) {
+            const int tx = x - j;
+            if (tx < 0 || (tx & 1) || tx / 2 >= P2) continue;
+            const int pos = (ty / 2) * P2 + tx / 2;
+            s += dA2[((int64_t)b * P2 * P2 + pos) * K2P + (i * 3 + j) * 16 + c];
+        }
+    }
+    if (!(from_bf16(o1[idx]) > 0.f)) s = 0.f;
+    da1[idx] = to_bf16(s);
+}
+
+// Tiled transpose of a bf16 matrix: dst[c][r] = src[r][c].
+__global__ __launch_bounds__(256) void transpose_kernel(const bf16* src, int R, int Ccols,
+                                                        int64_t lds, bf16* dst, int64_t ldd) {
+    __shared__ uint16_t tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+    for (int k = 0; k < 32; k += 8) {
+        const int r = r0 + ty + k, c = c0 + tx;
+        if (r < R && c < Ccols)
+            tile[ty + k][tx] = __builtin_bit_cast(uint16_t, src[(int64_t)r * lds + c]);
+    }
+    __syncthreads();
+    for (int k = 0; k < 32; k += 8) {
+        const int c = c0 + ty + k, r = r0 + tx;
+        if (r < R && c < Ccols)
+            dst[(int64_t)c * ldd + r] = __builtin_bit_cast(bf16, tile[tx][ty + k]);
+    }
+}
+
+// Loss: mean over the batch of sum_o w_o (y_o - t_o)^2; dy = dL/dy in bf16
+// ([B][32], columns >= 4 stay zero); per-block partial loss sums.
+__global__ __launch_bounds__(256) void loss_kernel(const float* y, int64_t ldy, const float* t,
+                                                   int B, bf16* dy, float* partial) {
+    __shared__ float red[256];
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    float l = 0.f;
+    if (b < B) {
+        for (int o = 0; o < NOUT; ++o) {
+            const float r = y[(int64_t)b * ldy + o] - t[4 * b + o];
+            l += r * r;
+            dy[(int64_t)b * 32 + o] = to_bf16(2.f * r / (float)B);
+        }
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void finish_loss_kernel(const float* partial, int n, int B, float* out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += partial[i];
+    *out = (float)(s / B);
+}
+
+// Sum split-K partials [Z][M][N] into the gradient vector.  kind 0: dst index
+// m * N + n; kind 1 (conv1): columns >= 48 dropped, m * 48 + n; kind 2 (conv2):
+// (tap, c) column -> m * 144 + c * 9 + tap, columns >= 144 dropped.
+__global__ __launch_bounds__(256) void reduce_split_kernel(const float* part, int Z, int M, int N,
+                                                           int kind, float* dst) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= M * N) return;
+    const int m = idx / N, n = idx % N;
+    float s = 0.f;
+    for (int z = 0; z < Z; ++z) s += part[(int64_t)z * M * N + idx];
+    if (kind == 0) {
+        dst[idx] = s;
+    } else if (kind == 1) {
+        if (n < K1) dst[m * K1 + n] = s;
+    } else {
+        if (n < K2) dst[m * K2 + (n % 16) * 9 + n / 16] = s;
+    }
+}
+
+// Column sums of a bf16 matrix D [M][ld] (optionally weighted by w[m][0/1]),
+// two-stage: per-block partials [gridDim.x][N][nw] then a final pass.
+__global__ __launch_bounds__(256) void colsum_kernel(const bf16* D, int64_t ld, int M, int N,
+                                                     const float* w, float* partial) {
+    const int n = threadIdx.x;   // N <= 256
+    const int rows = (M + gridDim.x - 1) / gridDim.x;
+    const int r0 = blockIdx.x * rows, r1 = min(M, r0 + rows);
+    if (n >= N) return;
+    float s = 0.f, s0 = 0.f, s1 = 0.f;
+    for (int m = r0; m < r1; ++m) {
+        const float v = from_bf16(D[(int64_t)m * ld + n]);
+        if (w) {
+            s0 += v * w[2 * m];
+            s1 += v * w[2 * m + 1];
+        } else {
+            s += v;
+        }
+    }
+    if (w) {
+        partial[((int64_t)blockIdx.x * N + n) * 2] = s0;
+        partial[((int64_t)blockIdx.x * N + n) * 2 + 1] = s1;
+    } else {
+        partial[(int64_t)blockIdx.x * N + n] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void colsum_finish_kernel(const float* partial, int nblk, int cnt,
+                                                            float* dst) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= cnt) return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * cnt + i];
+    dst[i] = s;
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float* theta, float* m, float* v, const float* g,
+                                                   int64_t n, float lr, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+}
+
+// bf16 weight copies in GEMM layouts (see PackedWeights).
+__global__ __launch_bounds__(256) void pack_kernel(const float* th, PackedWeights w) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < C1 * K1P) {                               // w1 [16][64]
+        const int o = i / K1P, c = i % K1P;
+        w.w1[i] = to_bf16(c < K1 ? th[OFF_W1 + o * K1 + c] : 0.f);
+    }
+    if (i < C2 * K2P) {                               // w2 [32][160], w2t [160][32]
+        const int o = i / K2P, c = i % K2P;
+        const float v = c < K2 ? th[OFF_W2 + o * K2 + (c % 16) * 9 + c / 16] : 0.f;
+        w.w2[i] = to_bf16(v);
+        w.w2t[c * C2 + o] = to_bf16(v);
+    }
+    if (i < H1 * F) {                                 // w3 [128][800], w3t [800][128]
+        const int o = i / F, c = i % F;
+        const float v = th[OFF_W3 + i];
+        w.w3[i] = to_bf16(v);
+        w.w3t[c * H1 + o] = to_bf16(v);
+    }
+    if (i < H2 * H1) {                                // w4 [64][128], w4t [128][64]
+        const int o = i / H1, c = i % H1;
+        const float v = th[OFF_W4 + i];
+        w.w4[i] = to_bf16(v);
+        w.w4t[c * H2 + o] = to_bf16(v);
+    }
+    if (i < 16 * H2) {                                // w5 [16][64], w5t [64][32]
+        const int o = i / H2, c = i % H2;
+        w.w5[i] = to_bf16(o < NOUT ? th[OFF_W5 + o * H2 + c] : 0.f);
+    }
+    if (i < H2 * 32) {
+        const int c = i / 32, o = i % 32;
+        w.w5t[i] = to_bf16(o < NOUT ? th[OFF_W5 + o * H2 + c] : 0.f);
+    }
+}
+
+// Counter-based init: splitmix64 of (seed, index) -> uniform in [-1, 1).
+__global__ __launch_bounds__(256) void init_kernel(float* th, int64_t n, uint64_t seed) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const float u = (float)((double)(z >> 11) * (1.0 / 9007199254740992.0)) * 2.f - 1.f;
+    // He-uniform bound sqrt(6 / fan_in) per weight tensor; biases start at zero.
+    float bound = 0.f;
+    if (i < OFF_B1) bound = sqrtf(6.f / K1);
+    else if (i >= OFF_W2 && i < OFF_B2) bound = sqrtf(6.f / K2);
+    else if (i >= OFF_W3 && i < OFF_B3) bound = sqrtf(6.f / (F + 2));
+    else if (i >= OFF_W4 && i < OFF_B4) bound = sqrtf(6.f / H1);
+    else if (i >= OFF_W5 && i < OFF_B5) bound = sqrtf(6.f / H2);
+    th[i] = u * bound;
+}
+
+}  // namespace net
+}  // namespace seb
+
+// ========================================================================
+// Host side: the network handle and its C ABI.
+// ========================================================================
+
+using seb::net::bf16;
+namespace N = seb::net;
+
+namespace {
+
+thread_local std::string g_net_error;
+
+int net_fail(int code, const std::string& msg) {
+    g_net_error = msg;
+    return code;
+}
+
+}  // namespace
+
+struct seb_net {
+    int max_batch = 0;
+    int64_t step = 0;
+    int device = 0;
+    float* theta = nullptr;
+    float* m = nullptr;
+    float* v = nullptr;
+    float* grad = nullptr;
+    N::PackedWeights pw{};
+    // workspace (max_batch rows)
+    bf16 *A1 = nullptr, *A1t = nullptr, *o1 = nullptr, *da1 = nullptr, *da1t = nullptr;
+    bf16 *A2 = nullptr, *A2t = nullptr, *f = nullptr, *ft = nullptr, *da2 = nullptr, *da2t = nullptr;
+    bf16 *h1 = nullptr, *h1t = nullptr, *da3 = nullptr, *da3t = nullptr;
+    bf16 *h2 = nullptr, *h2t = nullptr, *da4 = nullptr, *da4t = nullptr;
+    bf16 *dy = nullptr, *dyt = nullptr;
+    float *dA2 = nullptr, *y = nullptr, *tgt = nullptr, *sc = nullptr;
+    float *part = nullptr, *lpart = nullptr, *cpart = nullptr;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+constexpr int kColBlocks = 64;
+
+// Split-K partial buffer: the largest Z * M * N of the weight-gradient GEMMs.
+int64_t part_floats(int64_t Bm) {
+    auto z = [](int64_t K, int64_t chunk) { return (K + chunk - 1) / chunk; };
+    int64_t m = z(Bm, 1024) * N::H1 * N::F;
+    m = std::max(m, z(Bm, 1024) * N::H2 * N::H1);
+    m = std::max(m, z(Bm, 1024) * N::NOUT * N::H2);
+    m = std::max(m, z(Bm * N::P2 * N::P2, 4096) * N::C2 * N::K2P);
+    m = std::max(m, z(Bm * N::P1 * N::P1, 8192) * N::C1 * N::K1P);
+    return m;
+}
+
+template <typename T>
+bool dalloc(seb_net* n, T** p, int64_t count) {
+    void* q = nullptr;
+    if (hipMalloc(&q, (size_t)count * sizeof(T)) != hipSuccess) return false;
+    n->allocs.push_back(q);
+    *p = (T*)q;
+    return true;
+}
+
+int64_t blocks_for(int64_t n) { return (n + 255) / 256; }
+
+hipError_t gemm(const N::GemmArgs& g, hipStream_t s) {
+    const int zc = g.split ? (g.K + g.kchunk - 1) / g.kchunk : 1;
+    dim3 grid((g.M + 63) / 64, (g.N + 63) / 64, zc);
+    hipLaunchKernelGGL(N::gemm_nt_kernel, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+N::GemmArgs gemm_args(const bf16* A, int64_t lda, const bf16* B, int64_t ldb, int M, int Nn, int K) {
+    N::GemmArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.A = A;
+    g.lda = lda;
+    g.B = B;
+    g.ldb = ldb;
+    g.M = M;
+    g.N = Nn;
+    g.K = K;
+    g.kchunk = K;
+    return g;
+}
+
+void transpose(const bf16* src, int R, int C, int64_t lds, bf16* dst, int64_t ldd, hipStream_t s) {
+    dim3 grid((C + 31) / 32, (R + 31) / 32);
+    hipLaunchKernelGGL(N::transpose_kernel, grid, dim3(256), 0, s, src, R, C, lds, dst, ldd);
+}
+
+// Weight gradient dst = A^T-style NT GEMM of [M][K] and [Nn][K] with split-K.
+void weight_grad(seb_net* n, const bf16* A, const bf16* B, int M, int Nn, int K, int kchunk,
+                 int kind, float* dst, hipStream_t s) {
+    N::GemmArgs g = gemm_args(A, K, B, K, M, Nn, K);
+    g.kchunk = kchunk;
+    g.split = (int64_t)M * Nn;
+    g.C = n->part;
+    g.ldc = Nn;
+    gemm(g, s);
+    const int Z = (K + kchunk - 1) / kchunk;
+    hipLaunchKernelGGL(N::reduce_split_kernel, dim3(blocks_for((int64_t)M * Nn)), dim3(256), 0, s,
+                       n->part, Z, M, Nn, kind, dst);
+}
+
+void colsum(seb_net* n, const bf16* D, int64_t ld, int M, int Nn, const float* w, float* dst,
+            hipStream_t s) {
+    hipLaunchKernelGGL(N::colsum_kernel, dim3(kColBlocks), dim3(256), 0, s, D, ld, M, Nn, w,
+                       n->cpart);
+    const int cnt = Nn * (w ? 2 : 1);
+    hipLaunchKernelGGL(N::colsum_finish_kernel, dim3(blocks_for(cnt)), dim3(256), 0, s, n->cpart,
+                       kColBlocks, cnt, dst);
+}
+
+int check_batch(const seb_net* n, const seb_train_batch* b, bool need_labels) {
+    if (!n || !b) return net_fail(SEB_ERR_INVALID, "net and batch must be non-NULL");
+    if (!b->maps || !b->samples) return net_fail(SEB_ERR_INVALID, "maps and samples must be set");
+    if (b->batch <= 0 || b->batch % 32 != 0 || b->batch > n->max_batch)
+        return net_fail(SEB_ERR_INVALID, "batch must be a positive multiple of 32 <= max_batch");
+    if (b->n_maps <= 0 || b->map_h <= 0 || b->map_w <= 0 || b->n_yaw <= 0 ||
+        !(b->resolution > 0.0))
+        return net_fail(SEB_ERR_INVALID, "bad map geometry");
+    if (need_labels && (!b->label_z || !b->label_roll || !b->label_pitch || !b->label_risk))
+        return net_fail(SEB_ERR_INVALID, "training needs all four label arrays");
+    return SEB_OK;
+}
+
+N::BatchArgs batch_args(const seb_train_batch* b) {
+    N::BatchArgs a;
+    a.maps = b->maps;
+    a.n_maps = b->n_maps;
+    a.mh = b->map_h;
+    a.mw = b->map_w;
+    a.inv_res = (float)(1.0 / b->resolution);
+    a.K = b->n_yaw;
+    a.lz = b->label_z;
+    a.lroll = b->label_roll;
+    a.lpitch = b->label_pitch;
+    a.lrisk = b->label_risk;
+    a.samples = b->samples;
+    a.B = b->batch;
+    return a;
+}
+
+// Forward pass of the patch-form network for a batch; outputs y [B][4] into out.
+hipError_t forward_pass(seb_net* n, const seb_train_batch* bt, float* out, hipStream_t s) {
+    const int B = bt->batch;
+    const N::BatchArgs ba = batch_args(bt);
+    const int64_t r1 = (int64_t)B * N::P1 * N::P1, r2 = (int64_t)B * N::P2 * N::P2;
+    hipLaunchKernelGGL(N::im2col1_kernel, dim3(blocks_for(r1 * N::K1P)), dim3(256), 0, s, ba, n->A1,
+                       n->sc, n->tgt);
+    N::GemmArgs g = gemm_args(n->A1, N::K1P, n->pw.w1, N::K1P, (int)r1, N::C1, N::K1P);
+    g.bias = n->theta + N::OFF_B1;
+    g.relu = 1;
+    g.Cb = n->o1;
+    g.ldcb = N::C1;
+    gemm(g, s);
+    hipLaunchKernelGGL(N::im2col2_kernel, dim3(blocks_for(r2 * N::K2P)), dim3(256), 0, s, n->o1,
+                       n->A2, B);
+    g = gemm_args(n->A2, N::K2P, n->pw.w2, N::K2P, (int)r2, N::C2, N::K2P);
+    g.bias = n->theta + N::OFF_B2;
+    g.relu = 1;
+    g.Cb = n->f;
+    g.ldcb = N::C2;
+    gemm(g, s);
+    g = gemm_args(n->f, N::F, n->pw.w3, N::F, B, N::H1, N::F);
+    g.bias = n->theta + N::OFF_B3;
+    g.rowv = n->sc;
+    g.colv = n->theta + N::OFF_WY;
+    g.relu = 1;
+    g.Cb = n->h1;
+    g.ldcb = N::H1;
+    gemm(g, s);
+    g = gemm_args(n->h1, N::H1, n->pw.w4, N::H1, B, N::H2, N::H1);
+    g.bias = n->theta + N::OFF_B4;
+    g.relu = 1;
+    g.Cb = n->h2;
+    g.ldcb = N::H2;
+    gemm(g, s);
+    g = gemm_args(n->h2, N::H2, n->pw.w5, N::H2, B, N::NOUT, N::H2);
+    g.bias = n->theta + N::OFF_B5;
+    g.C = out;
+    g.ldc = N::NOUT;
+    return gemm(g, s);
+}
+
+hipError_t pack(seb_net* n, hipStream_t s) {
+    hipLaunchKernelGGL(N::pack_kernel, dim3(blocks_for((int64_t)N::H1 * N::F)), dim3(256), 0, s,
+                       n->theta, n->pw);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+namespace seb {
+namespace net {
+const float* net_theta(const seb_net* n) { return n->theta; }
+PackedWeights net_packed(const seb_net* n) { return n->pw; }
+}  // namespace net
+}  // namespace seb
+
+extern "C" {
+
+int64_t seb_net_param_count(void) { return N::N_PARAMS; }
+
+const char* seb_net_last_error(void) { return g_net_error.c_str(); }
+
+void seb_net_destroy(seb_net* n) {
+    if (!n) return;
+    for (void* p : n->allocs) hipFree(p);
+    delete n;
+}
+
+int seb_net_create(uint64_t seed, int32_t max_batch, seb_net** out) {
+    if (!out) return net_fail(SEB_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (max_batch < 32 || max_batch % 32 != 0 || max_batch > (1 << 16))
+        return net_fail(SEB_ERR_INVALID, "max_batch must be a multiple of 32 in [32, 65536]");
+    seb_net* n = new (std::nothrow) seb_net();
+    if (!n) return net_fail(SEB_ERR_ALLOC, "host allocation failed");
+    n->max_batch = max_batch;
+    hipGetDevice(&n->device);
+    const int64_t Bm = max_batch;
+    const int64_t r1 = Bm * N::P1 * N::P1, r2 = Bm * N::P2 * N::P2;
+    bool ok = dalloc(n, &n->theta, N::N_PARAMS) && dalloc(n, &n->m, N::N_PARAMS) &&
+              dalloc(n, &n->v, N::N_PARAMS) && dalloc(n, &n->grad, N::N_PARAMS) &&
+              dalloc(n, &n->pw.w1, N::C1 * N::K1P) && dalloc(n, &n->pw.w2, N::C2 * N::K2P) &&
+              dalloc(n, &n->pw.w3, N::H1 * N::F) && dalloc(n, &n->pw.w4, N::H2 * N::H1) &&
+              dalloc(n, &n->pw.w5, 16 * N::H2) && dalloc(n, &n->pw.w2t, N::K2P * N::C2) &&
+              dalloc(n, &n->pw.w3t, N::F * N::H1) && dalloc(n, &n->pw.w4t, N::H1 * N::H2) &&
+              dalloc(n, &n->pw.w5t, N::H2 * 32) && dalloc(n, &n->A1, r1 * N::K1P) &&
+              dalloc(n, &n->A1t, r1 * N::K1P) && dalloc(n, &n->o1, r1 * N::C1) &&
+              dalloc(n, &n->da1, r1 * N::C1) && dalloc(n, &n->da1t, r1 * N::C1) &&
+              dalloc(n, &n->A2, r2 * N::K2P) && dalloc(n, &n->A2t, r2 * N::K2P) &&
+              dalloc(n, &n->dA2, r2 * N::K2P) && dalloc(n, &n->f, Bm * N::F) &&
+              dalloc(n, &n->ft, Bm * N::F) && dalloc(n, &n->da2, Bm * N::F) &&
+              dalloc(n, &n->da2t, Bm * N::F) && dalloc(n, &n->h1, Bm * N::H1) &&
+              dalloc(n, &n->h1t, Bm * N::H1) && dalloc(n, &n->da3, Bm * N::H1) &&
+              dalloc(n, &n->da3t, Bm * N::H1) && dalloc(n, &n->h2, Bm * N::H2) &&
+              dalloc(n, &n->h2t, Bm * N::H2) && dalloc(n, &n->da4, Bm * N::H2) &&
+              dalloc(n, &n->da4t, Bm * N::H2) && dalloc(n, &n->dy, Bm * 32) &&
+              dalloc(n, &n->dyt, Bm * 32) && dalloc(n, &n->y, Bm * N::NOUT) &&
+              dalloc(n, &n->tgt, Bm * N::NOUT) && dalloc(n, &n->sc, Bm * 2) &&
+              dalloc(n, &n->part, part_floats(Bm)) && dalloc(n, &n->lpart, Bm / 256 + 1) &&
+              dalloc(n, &n->cpart, kColBlocks * 512);
+    if (!ok) {
+        seb_net_destroy(n);
+        return net_fail(SEB_ERR_ALLOC, "device allocation failed");
+    }
+    hipError_t e;
+    if ((e = hipMemset(n->dy, 0, Bm * 32 * sizeof(bf16))) != hipSuccess ||
+        (e = hipMemset(n->m, 0, N::N_PARAMS * sizeof(float))) != hipSuccess ||
+        (e = hipMemset(n->v, 0, N::N_PARAMS * sizeof(float))) != hipSuccess) {
+        seb_net_destroy(n);
+        return net_fail(SEB_ERR_HIP, std::string("hipMemset: ") + hipGetErrorString(e));
+    }
+    hipLaunchKernelGGL(N::init_kernel, dim3(blocks_for(N::N_PARAMS)), dim3(256), 0, 0, n->theta,
+                       N::N_PARAMS, seed);
+    pack(n, 0);
+    if ((e = hipDeviceSynchronize()) != hipSuccess) {
+        seb_net_destroy(n);
+        return net_fail(SEB_ERR_HIP, std::string("init: ") + hipGetErrorString(e));
+    }
+    *out = n;
+    return SEB_OK;
+}
+
+int seb_net_get_params(const seb_net* n, float* host) {
+    if (!n || !host) return net_fail(SEB_ERR_INVALID, "net and host must be non-NULL");
+    hipError_t e = hipMemcpy(host, n->theta, N::N_PARAMS * sizeof(float), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return net_fail(SEB_ERR_HIP, hipGetErrorString(e));
+    return SEB_OK;
+}
+
+int seb_net_set_params(seb_net* n, const float* host) {
+    if (!n || !host) return net_fail(SEB_ERR_INVALID, "net and host must be non-NULL");
+    hipError_t e;
+    if ((e = hipMemcpy(n->theta, host, N::N_PARAMS * sizeof(float), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemset(n->m, 0, N::N_PARAMS * sizeof(float))) != hipSuccess ||
+        (e = hipMemset(n->v, 0, N::N_PARAMS * sizeof(float))) != hipSuccess)
+        return net_fail(SEB_ERR_HIP, hipGetErrorString(e));
+    n->step = 0;
+    pack(n, 0);
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return net_fail(SEB_ERR_HIP, hipGetErrorString(e));
+    return SEB_OK;
+}
+
+// File: "SEBNET01", int64 parameter count, int64 Adam step, then theta, m, v (float32).
+int seb_net_save(const seb_net* n, const char* path) {
+    if (!n || !path) return net_fail(SEB_ERR_INVALID, "net and path must be non-NULL");
+    std::vector<float> buf(3 * N::N_PARAMS);
+    hipError_t e;
+    if ((e = hipDeviceSynchronize()) != hipSuccess ||
+        (e = hipMemcpy(buf.data(), n->theta, N::N_PARAMS * 4, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(buf.data() + N::N_PARAMS, n->m, N::N_PARAMS * 4, hipMemcpyDeviceToHost)) !=
+            hipSuccess ||
+        (e = hipMemcpy(buf.data() + 2 * N::N_PARAMS, n->v, N::N_PARAMS * 4,
+                       hipMemcpyDeviceToHost)) != hipSuccess)
+        return net_fail(SEB_ERR_HIP, hipGetErrorString(e));
+    FILE* fp = std::fopen(path, "wb");
+    if (!fp) return net_fail(SEB_ERR_IO, std::string("cannot open ") + path);
+    const int64_t hdr[2] = {N::N_PARAMS, n->step};
+    bool ok = std::fwrite("SEBNET01", 1, 8, fp) == 8 && std::fwrite(hdr, 8, 2, fp) == 2 &&
+              std::fwrite(buf.data(), 4, buf.size(), fp) == buf.size();
+    ok = (std::fclose(fp) == 0) && ok;
+    return ok ? SEB_OK : net_fail(SEB_ERR_IO, std::string("write failed: ") + path);
+}
+
+int seb_net_load(seb_net* n, const char* path) {
+    if (!n || !path) return net_fail(SEB_ERR_INVALID, "net and path must be non-NULL");
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return net_fail(SEB_ERR_IO, std::string("cannot open ") + path);
+    char magic[8];
+    int64_t hdr[2];
+    std::vector<float> buf(3 * N::N_PARAMS);
+    bool ok = std::fread(magic, 1, 8, fp) == 8 && std::memcmp(magic, "SEBNET01", 8) == 0 &&
+              std::fread(hdr, 8, 2, fp) == 2 && hdr[0] == N::N_PARAMS && hdr[1] >= 0 &&
+              std::fread(buf.data(), 4, buf.size(), fp) == buf.size();
+    std::fclose(fp);
+    if (!ok) return net_fail(SEB_ERR_IO, std::string("not a valid network file: ") + path);
+    hipError_t e;
+    if ((e = hipMemcpy(n->theta, buf.data(), N::N_PARAMS * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(n->m, buf.data() + N::N_PARAMS, N::N_PARAMS * 4, hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(n->v, buf.data() + 2 * N::N_PARAMS, N::N_PARAMS * 4,
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return net_fail(SEB_ERR_HIP, hipGetErrorString(e));
+    n->step = hdr[1];
+    pack(n, 0);
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return net_fail(SEB_ERR_HIP, hipGetErrorString(e));
+    return SEB_OK;
+}
+
+int seb_net_forward(seb_net* n, const seb_train_batch* b, float* y_dev, void* stream) {
+    int rc = check_batch(n, b, false);
+    if (rc != SEB_OK) return rc;
+    if (!y_dev) return net_fail(SEB_ERR_INVALID, "y_dev is NULL");
+    hipError_t e = forward_pass(n, b, y_dev, (hipStream_t)stream);
+    if (e != hipSuccess) return net_fail(SEB_ERR_HIP, hipGetErrorString(e));
+    return SEB_OK;
+}
+
+int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* loss_dev,
+                       float* grad_dev, void* stream) {
+    int rc = check_batch(n, bt, true);
+    if (rc != SEB_OK) return rc;
+    if (!(lr >= 0.f) || !std::isfinite(lr)) return net_fail(SEB_ERR_INVALID, "bad learning rate");
+    hipStream_t s = (hipStream_t)stream;
+    const int B = bt->batch;
+    const int r1 = B * N::P1 * N::P1, r2 = B * N::P2 * N::P2;
+    hipError_t e = forward_pass(n, bt, n->y, s);
+    if (e != hipSuccess) return net_fail(SEB_ERR_HIP, hipGetErrorString(e));
+    float* g = n->grad;
+
+    // loss and dy
+    const int lb = (B + 255) / 256;
+    hipLaunchKernelGGL(N::loss_kernel, dim3(lb), dim3(256), 0, s, n->y, (int64_t)N::NOUT, n->tgt, B,
+                       n->dy, n->lpart);
+    if (loss_dev) hipLaunchKernelGGL(N::finish_loss_kernel, dim3(1), dim3(64), 0, s, n->lpart, lb, B,
+                                     loss_dev);
+    transpose(n->dy, B, 32, 32, n->dyt, B, s);
+    // fc3
+    N::GemmArgs ga = gemm_args(n->dy, 32, n->pw.w5t, 32, B, N::H2, 32);
+    ga.gate = n->h2;
+    ga.ldg = N::H2;
+    ga.Cb = n->da4;
+    ga.ldcb = N::H2;
+    gemm(ga, s);
+    transpose(n->h2, B, N::H2, N::H2, n->h2t, B, s);
+    weight_grad(n, n->dyt, n->h2t, N::NOUT, N::H2, B, 1024, 0, g + N::OFF_W5, s);
+    colsum(n, n->dy, 32, B, N::NOUT, nullptr, g + N::OFF_B5, s);
+    // fc2
+    transpose(n->da4, B, N::H2, N::H2, n->da4t, B, s);
+    ga = gemm_args(n->da4, N::H2, n->pw.w4t, N::H2, B, N::H1, N::H2);
+    ga.gate = n->h1;
+    ga.ldg = N::H1;
+    ga.Cb = n->da3;
+    ga.ldcb = N::H1;
+    gemm(ga, s);
+    transpose(n->h1, B, N::H1, N::H1, n->h1t, B, s);
+    weight_grad(n, n->da4t, n->h1t, N::H2, N::H1, B, 1024, 0, g + N::OFF_W4, s);
+    colsum(n, n->da4, N::H2, B, N::H2, nullptr, g + N::OFF_B4, s);
+    // fc1
+    transpose(n->da3, B, N::H1, N::H1, n->da3t, B, s);
+    ga = gemm_args(n->da3, N::H1, n->pw.w3t, N::H1, B, N::F, N::H1);
+    ga.gate = n->f;
+    ga.ldg = N::F;
+    ga.Cb = n->da2;
+    ga.ldcb = N::F;
+    gemm(ga, s);
+    transpose(n->f, B, N::F, N::F, n->ft, B, s);
+    weight_grad(n, n->da3t, n->ft, N::H1, N::F, B, 1024, 0, g + N::OFF_W3, s);
+    colsum(n, n->da3, N::H1, B, N::H1, n->sc, g + N::OFF_WY, s);
+    colsum(n, n->da3, N::H1, B, N::H1, nullptr, g + N::OFF_B3, s);
+    // conv2 (da2 viewed as [B*25][32])
+    ga = gemm_args(n->da2, N::C2, n->pw.w2t, N::C2, r2, N::K2P, N::C2);
+    ga.C = n->dA2;
+    ga.ldc = N::K2P;
+    gemm(ga, s);
+    hipLaunchKernelGGL(N::col2im2_kernel, dim3(blocks_for((int64_t)r1 * N::C1)), dim3(256), 0, s,
+                       n->dA2, n->o1, n->da1, B);
+    transpose(n->da2, r2, N::C2, N::C2, n->da2t, r2, s);
+    transpose(n->A2, r2, N::K2P, N::K2P, n->A2t, r2, s);
+    weight_grad(n, n->da2t, n->A2t, N::C2, N::K2P, r2, 4096, 2, g + N::OFF_W2, s);
+    colsum(n, n->da2, N::C2, r2, N::C2, nullptr, g + N::OFF_B2, s);
+    // conv1
+    transpose(n->da1, r1, N::C1, N::C1, n->da1t, r1, s);
+    transpose(n->A1, r1, N::K1P, N::K1P, n->A1t, r1, s);
+    weight_grad(n, n->da1t, n->A1t, N::C1, N::K1P, r1, 8192, 1, g + N::OFF_W1, s);
+    colsum(n, n->da1, N::C1, r1, N::C1, nullptr, g + N::OFF_B1, s);
+
+    if (grad_dev) {
+        e = hipMemcpyAsync(grad_dev, g, N::N_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, s);
+    } else {
+        n->step += 1;
+        const double c1 = 1.0 / (1.0 - std::pow(0.9, (double)n->step));
+        const double c2 = 1.0 / (1.0 - std::pow(0.999, (double)n->step));
+        hipLaunchKernelGGL(N::adam_kernel, dim3(blocks_for(N::N_PARAMS)), dim3(256), 0, s, n->theta,
+                           n->m, n->v, g, N::N_PARAMS, lr, (float)c1, (float)c2);
+        e = pack(n, s);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return net_fail(SEB_ERR_HIP, hipGetErrorString(e));
+    return SEB_OK;
+}
+
+}  // extern "C"

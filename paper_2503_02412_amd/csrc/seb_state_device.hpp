@@ -1,0 +1,336 @@
+// Device code of the per-state assessment (Sec. V-B, Algorithm 1, with the
+// pose of Sec. III, Eq. 1-3), shared by the tiled full-map kernel (heights in
+// LDS) and the list kernel that re-assesses scattered states (heights from
+// global memory).  Both run the same arithmetic in the same order.
+#pragma once
+
+#include <cmath>
+
+#include "../../include/seb.h"
+#include "seb_internal.hpp"
+
+namespace seb {
+namespace dev {
+
+__device__ __forceinline__ int wrap(int v, int n) { return v >= n ? v - n : v; }
+
+// The footprint table is read-only for the lifetime of a launch.  Reading it
+// through the constant address space lets the compiler fetch wave-uniform
+// entries with scalar loads even though the kernel also stores to global memory.
+// (The host compilation pass of the .hip files only parses the kernels, so
+// there the qualifier is dropped.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define SEB_CONSTANT_AS __attribute__((address_space(4)))
+#else
+#define SEB_CONSTANT_AS
+#endif
+template <typename T>
+using cptr = const SEB_CONSTANT_AS T*;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+    return (cptr<T>)(p);
+}
+
+template <typename T>
+struct Moments {
+    T Sz, Spz, Sqz, Szz;          // sums over valid samples of z, p z, q z, z^2 (z centred)
+    int32_t N, Sp, Sq, Spp, Spq, Sqq;
+};
+
+struct Result {
+    float z, roll, pitch, risk;
+    uint8_t st;
+};
+
+// Least-squares plane z = a + b u + c v from the moments, then Eq. 1-3 and
+// Algorithm 1.  u = hu p, v = hv q are the body-frame sample coordinates.
+template <typename T>
+__device__ Result finish(const AssessArgs& a, const Moments<T>& m, T ref) {
+    Result r;
+    const int64_t N = m.N;
+    const int64_t D = N * (int64_t)m.Spp - (int64_t)m.Sp * m.Sp;
+    const int64_t E = N * (int64_t)m.Sqq - (int64_t)m.Sq * m.Sq;
+    const int64_t F = N * (int64_t)m.Spq - (int64_t)m.Sp * m.Sq;
+    const int64_t det = D * E - F * F;
+    if (N < a.min_valid || det <= 0) {
+        r.z = r.roll = r.pitch = __builtin_nanf("");
+        r.risk = 1.f;
+        r.st = 0;
+        return r;
+    }
+    uint8_t st = SEB_ST_VALID;
+    const double de = (double)(D + E);
+    if (2 * N < a.n_total || (4.0 * (double)det) / (de * de) < a.rho16) st |= SEB_ST_DEGEN;
+
+    const T invN = T(1) / T(N);
+    const T zb = m.Sz * invN;
+    const T pz = m.Spz - T(m.Sp) * zb;      // sum (p - pbar)(z - zbar)
+    const T qz = m.Sqz - T(m.Sq) * zb;
+    const T zz = m.Szz - m.Sz * zb;         // sum (z - zbar)^2
+    const T tdet = T(det);
+    const T bp = T(N) * (T(E) * pz - T(F) * qz) / tdet;   // dz/dp
+    const T bq = T(N) * (T(D) * qz - T(F) * pz) / tdet;   // dz/dq
+    const T b = bp / T(a.hu), c = bq / T(a.hv);           // dz/du, dz/dv
+    const T zc = ref + zb - bp * (T(m.Sp) * invN) - bq * (T(m.Sq) * invN);
+    T sse = zz - bp * pz - bq * qz;
+    if (sse < T(0)) sse = T(0);
+    const T s2 = T(1) + b * b + c * c;
+    const T tr = T(a.hu) * T(a.hu) * T(D) * invN + T(a.hv) * T(a.hv) * T(E) * invN + zz;
+    const float kappa = (tr > T(0)) ? (float)(sse / (s2 * tr)) : 0.f;
+
+    const float bf = (float)b, cf = (float)c;
+    const float c1 = 1.f + cf * cf;
+    r.z = (float)zc;
+    r.roll = atanf(cf);                              // asin(b3 . y_b)
+    r.pitch = -atan2f(bf, sqrtf(c1));               // atan2(-b3 . x_b, b3 . z_b)
+    const float phx = atan2f(fabsf(bf), sqrtf(c1 * c1 + bf * bf * cf * cf));   // |asin(b3 . x_b)|
+    const float phy = fabsf(r.roll);                                             // |asin(b3 . y_b)|
+    float risk;
+    if (kappa > a.kappa_max) {
+        risk = 1.f;
+        st |= SEB_ST_CURV;
+    } else if (phx > a.phi_x_max || phy > a.phi_y_max) {
+        risk = 1.f;
+        st |= SEB_ST_TILT;
+    } else {
+        risk = a.w_kappa * kappa / a.kappa_max + a.w_phi_x * phx / a.phi_x_max +
+               a.w_phi_y * phy / a.phi_y_max;
+    }
+    if (risk <= a.risk_max) st |= SEB_ST_TRAV;
+    r.risk = risk;
+    r.st = st;
+    return r;
+}
+
+// Height sources of a state's footprint samples.  quad() returns the four
+// corners (0,0) (1,0) (0,1) (1,1) of the sample whose corner (0,0) sits at
+// table offset `off` (dy * P + dx) from the state's cell; unknown and
+// out-of-map cells read as SENTINEL.
+template <int P>
+struct LdsSource {
+    const float* tp0;   // the state's own cell in the LDS tile
+    __device__ __forceinline__ void quad(int off, float& h00, float& h01, float& h10,
+                                         float& h11) const {
+        const float* tp = tp0 + off;
+        h00 = tp[0];
+        h01 = tp[1];
+        h10 = tp[P];
+        h11 = tp[P + 1];
+    }
+};
+
+struct GlobalSource {
+    const float* height;
+    int64_t ld;
+    int W, H, rx, ry;   // map size and ring offset
+    int ix, iy;         // the state's cell (logical)
+    int P;              // LDS pitch the table offsets were built for
+    __device__ __forceinline__ float cell(int x, int y) const {
+        if (x < 0 || y < 0 || x >= W || y >= H) return SENTINEL;
+        const float h = height[(int64_t)wrap(y + ry, H) * ld + wrap(x + rx, W)];
+        return fabsf(h) < HEIGHT_LIMIT ? h : SENTINEL;
+    }
+    __device__ __forceinline__ void quad(int off, float& h00, float& h01, float& h10,
+                                         float& h11) const {
+        // off = dy * P + dx with |dx| < P / 2
+        const int dy = (off + P / 2 + 1024 * P) / P - 1024;
+        const int dx = off - dy * P;
+        const int x = ix + dx, y = iy + dy;
+        h00 = cell(x, y);
+        h01 = cell(x + 1, y);
+        h10 = cell(x, y + 1);
+        h11 = cell(x + 1, y + 1);
+    }
+};
+
+// Bilinear sample of the state, centred on ref.  Corner weights are
+// wave-uniform scalars.
+template <class Src>
+__device__ __forceinline__ float sample(const Src& src, int off, float4 w, float ref) {
+    float h00, h01, h10, h11;
+    src.quad(off, h00, h01, h10, h11);
+    float z = fmaf(w.x, h00, -ref);
+    z = fmaf(w.y, h01, z);
+    z = fmaf(w.z, h10, z);
+    return fmaf(w.w, h11, z);
+}
+
+// Per-segment integer moments: (count, sum q, sum q^2) unpacked from pk and
+// combined with the segment's body-x index p.
+__device__ __forceinline__ void add_segment(Moments<float>& m, int p, uint32_t pk, int qoff,
+                                            uint32_t mask1, int sh2, float rz) {
+    const int c = (int)(pk & 63u);
+    const int Q = (int)((pk >> 6) & mask1) - qoff * c;
+    const int QQ = (int)(pk >> sh2);
+    m.N += c;
+    m.Sp += p * c;
+    m.Spp += p * p * c;
+    m.Sq += Q;
+    m.Spq += p * Q;
+    m.Sqq += QQ;
+    m.Sz += rz;
+    m.Spz = fmaf((float)p, rz, m.Spz);
+}
+
+constexpr int bits_for(int v) {
+    int b = 0;
+    while ((1 << b) <= v) ++b;
+    return b;
+}
+
+// FP32 moments of one yaw bin when every segment is a full row of NW samples:
+// the row loop is unrolled, so q and the packed integer constants of each
+// sample are literals and only the weights and offsets are loaded.
+template <int NW, class Src>
+__device__ __forceinline__ void accumulate_rows(const AssessArgs& a, const Src& src,
+                                                cptr<float4> W, cptr<int32_t> O, float ref,
+                                                Moments<float>& m) {
+    constexpr int kQoff = NW - 1;
+    constexpr int kSh2 = 6 + bits_for(NW * 2 * kQoff);
+    constexpr uint32_t kMask1 = (1u << (kSh2 - 6)) - 1u;
+    static_assert(kSh2 + bits_for(NW * kQoff * kQoff) <= 32, "packed moments overflow");
+    m.Sz = m.Spz = m.Sqz = m.Szz = 0.f;
+    m.N = m.Sp = m.Sq = m.Spp = m.Spq = m.Sqq = 0;
+    const int nrows = a.n_segs;
+    int p = 1 - nrows;
+    for (int i = 0; i < nrows; ++i, p += 2) {
+        float rz = 0.f;
+        uint32_t pk = 0u;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) {
+            const float z = sample(src, O[i * NW + j], W[i * NW + j], ref);
+            if (fabsf(z) < VALID_LIMIT) {
+                const int q = 2 * j - kQoff;
+                rz += z;
+                m.Sqz = fmaf((float)q, z, m.Sqz);
+                m.Szz = fmaf(z, z, m.Szz);
+                pk += 1u | ((uint32_t)(2 * j) << 6) | ((uint32_t)(q * q) << kSh2);
+            }
+        }
+        add_segment(m, p, pk, kQoff, kMask1, kSh2, rz);
+    }
+}
+
+// FP32 moments of one yaw bin, any footprint (segments of any length).
+template <class Src>
+__device__ __forceinline__ void accumulate_segments(const AssessArgs& a, const Src& src,
+                                                    cptr<float4> W, cptr<int32_t> O, float ref,
+                                                    Moments<float>& m) {
+    m.Sz = m.Spz = m.Sqz = m.Szz = 0.f;
+    m.N = m.Sp = m.Sq = m.Spp = m.Spq = m.Sqq = 0;
+    const cptr<Segment> segs = as_const(a.segs);
+    const cptr<float> qs = as_const(a.qs);
+    const cptr<uint32_t> pks = as_const(a.pks);
+    for (int g = 0; g < a.n_segs; ++g) {
+        const Segment sg = segs[g];
+        float rz = 0.f;
+        uint32_t pk = 0u;
+        for (int s = sg.first; s < sg.first + sg.count; ++s) {
+            const float z = sample(src, O[s], W[s], ref);
+            if (fabsf(z) < VALID_LIMIT) {
+                rz += z;
+                m.Sqz = fmaf(qs[s], z, m.Sqz);
+                m.Szz = fmaf(z, z, m.Szz);
+                pk += pks[s];
+            }
+        }
+        add_segment(m, sg.p, pk, a.qoff, a.mask1, a.sh2, rz);
+    }
+}
+
+// FP64 moments of one yaw bin, with FP64 bilinear weights (near-degenerate path).
+template <class Src>
+__device__ void accumulate64(const AssessArgs& a, const Src& src, cptr<int32_t> O,
+                             cptr<double2> FR, double ref, Moments<double>& m) {
+    m.Sz = m.Spz = m.Sqz = m.Szz = 0.0;
+    m.N = m.Sp = m.Sq = m.Spp = m.Spq = m.Sqq = 0;
+    const cptr<Segment> segs = as_const(a.segs);
+    const cptr<float> qs = as_const(a.qs);
+    for (int g = 0; g < a.n_segs; ++g) {
+        const Segment sg = segs[g];
+        double rz = 0.0;
+        for (int s = sg.first; s < sg.first + sg.count; ++s) {
+            const double2 f = FR[s];
+            float h00, h01, h10, h11;
+            src.quad(O[s], h00, h01, h10, h11);
+            const double gx = 1.0 - f.x, gy = 1.0 - f.y;
+            const double z = gx * gy * (double)h00 + f.x * gy * (double)h01 +
+                             gx * f.y * (double)h10 + f.x * f.y * (double)h11 - ref;
+            if (fabs(z) < (double)VALID_LIMIT) {
+                const int q = (int)qs[s];
+                rz += z;
+                m.Sqz += (double)q * z;
+                m.Szz += z * z;
+                m.N += 1;
+                m.Sq += q;
+                m.Sqq += q * q;
+                m.Sp += sg.p;
+                m.Spp += sg.p * sg.p;
+                m.Spq += sg.p * q;
+            }
+        }
+        m.Sz += rz;
+        m.Spz += (double)sg.p * rz;
+    }
+}
+
+__device__ __forceinline__ void store(const AssessArgs& a, int k, int64_t cell, const Result& r,
+                                      bool negate) {
+    const int64_t o = (int64_t)k * a.H * a.W + cell;
+    a.z[o] = r.z;
+    a.roll[o] = negate ? -r.roll : r.roll;
+    a.pitch[o] = negate ? -r.pitch : r.pitch;
+    a.risk[o] = r.risk;
+    a.status[o] = r.st;
+}
+
+// Reference height, moments, optional FP64 redo and result of one state for
+// yaw unit u.  hc = the state's own cell (SENTINEL if unknown); `active`
+// lanes take part in the reference search.
+template <int NW, class Src>
+__device__ __forceinline__ Result assess_state(const AssessArgs& a, const Src& src, int u, float hc,
+                                               bool active) {
+    const int64_t ub = (int64_t)u * a.n_samples;
+    const cptr<float4> W = as_const(a.wts) + ub;
+    const cptr<int32_t> O = as_const(a.offs) + ub;
+
+    // Reference height: own cell, else the first valid sample in table order.
+    // A state with no valid sample keeps ref = 0, so every sample stays invalid.
+    float ref = (fabsf(hc) < HEIGHT_LIMIT) ? hc : 0.f;
+    bool need = active && !(fabsf(hc) < HEIGHT_LIMIT);
+    if (__ballot(need)) {
+        for (int s = 0; s < a.n_samples; ++s) {
+            if (!__ballot(need)) break;
+            const float4 w = W[s];
+            const int off = O[s];
+            if (need) {
+                const float h = sample(src, off, w, 0.f);
+                if (fabsf(h) < VALID_LIMIT) {
+                    ref = h;
+                    need = false;
+                }
+            }
+        }
+    }
+
+    Moments<float> m;
+    if constexpr (NW > 0)
+        accumulate_rows<NW>(a, src, W, O, ref, m);
+    else
+        accumulate_segments(a, src, W, O, ref, m);
+    Result r = finish<float>(a, m, ref);
+
+    if (a.precision == 1) {
+        const bool redo = (r.st & SEB_ST_DEGEN) != 0;
+        if (__ballot(redo) && redo) {
+            Moments<double> md;
+            accumulate64(a, src, O, as_const(a.frac) + ub, (double)ref, md);
+            r = finish<double>(a, md, (double)ref);
+        }
+    }
+    return r;
+}
+
+}  // namespace dev
+}  // namespace seb

@@ -1,0 +1,41 @@
+// Internal declarations of surrogate inference (map form) with plain fallback.
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+#include "seb_internal.hpp"
+#include "seb_net_internal.hpp"
+
+namespace seb {
+namespace sur {
+
+struct SurArgs {
+    const float* height;         // map [H][ld], NaN = unknown
+    int64_t ld;
+    int W, H;
+    float inv_res;
+    int K, U, mirror;            // yaw bins, units evaluated (K/2 if mirrored), mirror offset
+    int pitch;                   // LDS pitch of the context's table offsets
+    // network
+    const float* theta;          // float32 parameters (biases and Wy are read from here)
+    net::PackedWeights pw;       // bf16 GEMM weights
+    // workspace
+    net::bf16* o1map;            // [(H+20)(W+20)][16]  conv1 at positions -12 .. H+7
+    net::bf16* o2map;            // [(H+16)(W+16)][32]  conv2 at positions -12 .. H+3
+    float* T;                    // [H*W][128]          fc1 without the yaw term
+    float* Y;                    // [U][128]            fc1 yaw term
+    float* rows;                 // [H*W]               known cells per 24-cell row run
+    float* known;                // [H*W]               known fraction of the 24 x 24 window
+    int32_t* counts;             // [K]                 flagged states per yaw unit
+    int32_t* lists;              // [U][H*W]            flagged cells per yaw unit
+    // fallback rule
+    float risk_max, band, min_known;
+};
+
+hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, int32_t* n_fallback,
+                            hipStream_t stream);
+
+}  // namespace sur
+}  // namespace seb

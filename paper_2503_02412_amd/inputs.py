@@ -268,3 +268,35 @@ def rolling_world(params: Params = CONFIG3, seed: int = 3, n_steps: int = 100,
     heights = fractal_terrain(w, h, res, seed + 1000, hole_frac=hole_frac,
                               n_steps=4 * max(1, (w * h) // (400 * 400)))
     return World(heights, gx_lo, gy_lo, res), traj
+
+
+# --------------------------------------------------------------------------
+# Learned-surrogate data: config-1-style sinusoid terrains (64 x 64 @ 0.1 m)
+# with two step lines and 5% unknown blobs, labelled by the plain method with
+# the 200 x 200 workload's footprint (1.0 x 0.6 m on 20 x 12) and 36 yaw bins.
+# --------------------------------------------------------------------------
+
+SURROGATE_LABEL_PARAMS = CONFIG2.with_(width=64, height=64)
+SURROGATE_TRAIN_SEEDS = tuple(range(1000, 1070))
+SURROGATE_VAL_SEEDS = (1070, 1071)
+SURROGATE_EVAL_SEEDS = (2000, 2001, 2002, 2003)
+
+
+def surrogate_training_map(seed: int, size: int = 64, res: float = 0.1) -> np.ndarray:
+    rng = _rng(seed)
+    h = sinusoid_terrain(size, size, res, seed + 50000).astype(np.float64)
+    h = add_steps(h, res, rng, n_steps=2)
+    h = add_holes(h, rng, 0.05)
+    return h.astype(np.float32)
+
+
+def surrogate_samples(n_maps: int, size: int, n_yaw: int, seed: int, count: int | None = None,
+                      half: int = 12) -> np.ndarray:
+    """All (map, cy, cx, k) whose input window [c-12, c+12] lies inside the map,
+    in a seeded random order (first `count` kept); int32 [count, 4]."""
+    c = np.arange(half, size - half)
+    m, y, x, k = np.meshgrid(np.arange(n_maps), c, c, np.arange(n_yaw), indexing="ij")
+    s = np.stack([m.ravel(), y.ravel(), x.ravel(), k.ravel()], 1).astype(np.int32)
+    perm = _rng(seed).permutation(len(s))
+    s = s[perm]
+    return s if count is None else s[:count]

@@ -271,3 +271,166 @@ class Window:
 
 def version() -> str:
     return lib().seb_version().decode()
+
+
+# ------------------------------------------------------------ surrogate net
+
+class TrainBatch(C.Structure):
+    _fields_ = [
+        ("maps", C.c_void_p), ("n_maps", C.c_int32), ("map_h", C.c_int32), ("map_w", C.c_int32),
+        ("resolution", C.c_double), ("n_yaw", C.c_int32),
+        ("label_z", C.c_void_p), ("label_roll", C.c_void_p), ("label_pitch", C.c_void_p),
+        ("label_risk", C.c_void_p), ("samples", C.c_void_p), ("batch", C.c_int32),
+    ]
+
+
+_SIGS.update({
+    "seb_net_param_count": (C.c_int64, []),
+    "seb_net_create": (C.c_int, [C.c_uint64, C.c_int32, C.POINTER(C.c_void_p)]),
+    "seb_net_destroy": (None, [C.c_void_p]),
+    "seb_net_get_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "seb_net_set_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "seb_net_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "seb_net_load": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "seb_net_forward": (C.c_int, [C.c_void_p, C.POINTER(TrainBatch), C.c_void_p, C.c_void_p]),
+    "seb_net_train_step": (C.c_int, [C.c_void_p, C.POINTER(TrainBatch), C.c_float, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]),
+    "seb_net_last_error": (C.c_char_p, []),
+})
+
+
+def _net_check(rc: int, where: str):
+    if rc != SEB_OK:
+        raise SebError(rc, where, lib().seb_net_last_error().decode())
+
+
+class Net:
+    """The surrogate network (seb_net_*)."""
+
+    def __init__(self, seed: int = 0, max_batch: int = 4096):
+        h = C.c_void_p()
+        _net_check(lib().seb_net_create(int(seed), int(max_batch), C.byref(h)), "seb_net_create")
+        self._h = h
+        self.max_batch = max_batch
+
+    @staticmethod
+    def param_count() -> int:
+        return int(lib().seb_net_param_count())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().seb_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        import numpy as np
+        out = np.empty(self.param_count(), dtype=np.float32)
+        _net_check(lib().seb_net_get_params(self._h, out.ctypes.data), "seb_net_get_params")
+        return out
+
+    def set_params(self, vec):
+        import numpy as np
+        v = np.ascontiguousarray(vec, dtype=np.float32)
+        if v.size != self.param_count():
+            raise ValueError("parameter vector has the wrong length")
+        _net_check(lib().seb_net_set_params(self._h, v.ctypes.data), "seb_net_set_params")
+
+    def save(self, path: str):
+        _net_check(lib().seb_net_save(self._h, path.encode()), "seb_net_save")
+
+    def load(self, path: str):
+        _net_check(lib().seb_net_load(self._h, path.encode()), "seb_net_load")
+
+    @staticmethod
+    def _batch(maps, samples, resolution, n_yaw, labels=None) -> TrainBatch:
+        import torch
+        if not (maps.is_cuda and maps.dtype == torch.float32 and maps.dim() == 3
+                and maps.is_contiguous()):
+            raise ValueError("maps must be a contiguous float32 CUDA tensor [n, H, W]")
+        if not (samples.is_cuda and samples.dtype == torch.int32 and samples.dim() == 2
+                and samples.shape[1] == 4 and samples.is_contiguous()):
+            raise ValueError("samples must be a contiguous int32 CUDA tensor [B, 4]")
+        n, H, W = maps.shape
+        s = samples.cpu()
+        if samples.shape[0] and (int(s[:, 0].min()) < 0 or int(s[:, 0].max()) >= n
+                                 or int(s[:, 1].min()) < 0 or int(s[:, 1].max()) >= H
+                                 or int(s[:, 2].min()) < 0 or int(s[:, 2].max()) >= W
+                                 or int(s[:, 3].min()) < 0 or int(s[:, 3].max()) >= n_yaw):
+            raise ValueError("sample indices out of range")
+        ptr = [None] * 4
+        if labels is not None:
+            for i, k in enumerate(("z", "roll", "pitch", "risk")):
+                t = labels[k]
+                if tuple(t.shape) != (n, n_yaw, H, W) or not t.is_contiguous() or not t.is_cuda:
+                    raise ValueError(f"label '{k}' must be a contiguous CUDA tensor [n, K, H, W]")
+                ptr[i] = t.data_ptr()
+        return TrainBatch(maps.data_ptr(), n, H, W, float(resolution), int(n_yaw), ptr[0], ptr[1],
+                          ptr[2], ptr[3], samples.data_ptr(), samples.shape[0])
+
+    def forward(self, maps, samples, resolution, n_yaw, stream=None):
+        import torch
+        b = self._batch(maps, samples, resolution, n_yaw)
+        y = torch.empty((samples.shape[0], 4), dtype=torch.float32, device=maps.device)
+        _net_check(lib().seb_net_forward(self._h, C.byref(b), C.c_void_p(y.data_ptr()),
+                                         _stream_handle(stream)), "seb_net_forward")
+        return y
+
+    def train_step(self, maps, labels, samples, resolution, n_yaw, lr, loss=None, grad=None,
+                   stream=None):
+        b = self._batch(maps, samples, resolution, n_yaw, labels)
+        _net_check(lib().seb_net_train_step(
+            self._h, C.byref(b), C.c_float(lr),
+            C.c_void_p(None if loss is None else loss.data_ptr()),
+            C.c_void_p(None if grad is None else grad.data_ptr()), _stream_handle(stream)),
+            "seb_net_train_step")
+
+
+_SIGS.update({
+    "seb_surrogate_create": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "seb_surrogate_destroy": (None, [C.c_void_p]),
+    "seb_surrogate_infer": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                      C.POINTER(Out), C.c_float, C.c_float, C.c_void_p,
+                                      C.c_void_p]),
+})
+
+
+class Surrogate:
+    """Surrogate inference workspace for one context (seb_surrogate_*)."""
+
+    def __init__(self, ctx: Context):
+        h = C.c_void_p()
+        _check(lib().seb_surrogate_create(ctx._h, C.byref(h)), "seb_surrogate_create")
+        self._h = h
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().seb_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def infer(self, net: "Net", height, out=None, band: float = 0.1, min_known: float = 0.75,
+              n_fallback=None, stream=None):
+        """seb_surrogate_infer; returns the outputs (n_fallback: optional int32 CUDA tensor)."""
+        p = self.ctx.params
+        _check_map(height, p)
+        if out is None:
+            out = alloc_outputs(p, height.device)
+        o = _out_struct(out, p)
+        nf = None if n_fallback is None else n_fallback.data_ptr()
+        _check(lib().seb_surrogate_infer(self._h, net._h, C.c_void_p(height.data_ptr()),
+                                         height.stride(0), C.byref(o), C.c_float(band),
+                                         C.c_float(min_known), C.c_void_p(nf),
+                                         _stream_handle(stream)), "seb_surrogate_infer")
+        return out

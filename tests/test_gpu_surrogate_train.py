@@ -1,0 +1,69 @@
+"""Train the surrogate on plain-kernel labels and measure it against the FP64
+oracle on the 200 x 200 evaluation maps, beside an untrained network and a
+predict-the-mean baseline."""
+import numpy as np
+import pytest
+
+from paper_2503_02412_amd import inputs as I
+from paper_2503_02412_amd import seb
+from paper_2503_02412_amd.surrogate import TrainingData, train
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu-case] {request.node.nodeid}", flush=True)
+
+
+def errors(out, o, own_known):
+    """Mean / max |error| per output on states the network answered."""
+    st = out["status"]
+    m = ((st & seb.ST_SURROGATE) > 0) & ((o.status & 1) > 0)
+    res = {"n": int(m.sum())}
+    for f in ("z", "roll", "pitch", "risk"):
+        d = np.abs(out[f][m].astype(np.float64) - getattr(o, f)[m])
+        res[f] = (float(d.mean()), float(d.max()))
+    res["mask_agree"] = float(np.mean(((st[m] & 16) > 0) == ((o.status[m] & 16) > 0)))
+    return res
+
+
+def test_trained_surrogate_beats_baselines(orc):
+    import torch
+    data = TrainingData(count=2_000_000)
+    print("training samples", data.n_samples)
+    assert data.n_samples > 1_500_000
+    net = seb.Net(seed=1, max_batch=4096)
+    hist = train(net, data, steps=2000, batch=4096)
+    print("loss", hist[0], hist[len(hist) // 2], hist[-1])
+    assert hist[-50:].mean() < 0.5 * hist[:50].mean()
+    untrained = seb.Net(seed=1, max_batch=4096)
+    # predict-the-mean baseline: constant output equal to the mean training target
+    p = I.CONFIG2
+    stats = {"trained": [], "untrained": [], "mean": []}
+    with seb.Context(p) as ctx:
+        sur = seb.Surrogate(ctx)
+        for seed in I.SURROGATE_EVAL_SEEDS[:2]:
+            h = I.config2_map(seed)
+            dh = torch.from_numpy(h).cuda()
+            o = orc.assess_rect(p, h)
+            nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+            out = sur.infer(net, dh, band=0.1, min_known=0.75, n_fallback=nf)
+            g = {k: v.cpu().numpy() for k, v in out.items()}
+            e = errors(g, o, np.isfinite(h))
+            e["fallback"] = int(nf.item()) / p.n_states
+            stats["trained"].append(e)
+            out_u = sur.infer(untrained, dh, band=0.0, min_known=0.0)
+            stats["untrained"].append(errors({k: v.cpu().numpy() for k, v in out_u.items()}, o,
+                                             None))
+            v = (o.status & 1) > 0
+            stats["mean"].append({f: float(np.abs(getattr(o, f)[v] - np.mean(getattr(o, f)[v]))
+                                           .mean()) for f in ("roll", "pitch", "risk")})
+    for k, v in stats.items():
+        print(k, v)
+    for e, u, mb in zip(stats["trained"], stats["untrained"], stats["mean"]):
+        for f in ("roll", "pitch", "risk"):
+            assert e[f][0] < 0.5 * u[f][0], f
+            assert e[f][0] < 0.5 * mb[f], f
+        assert e["mask_agree"] > 0.9
+        assert e["fallback"] < 0.6
