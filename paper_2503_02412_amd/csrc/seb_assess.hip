@@ -23,7 +23,7 @@
 // least-squares plane is then a closed-form 2 x 2 solve.
 #include <cmath>
 
-#include "../../include/seb.h"
+#include "seb.h"
 #include "seb_internal.hpp"
 #include "seb_state_device.hpp"
 

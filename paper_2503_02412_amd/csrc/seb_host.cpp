@@ -11,7 +11,7 @@
 
 #include <hip/hip_runtime.h>
 
-#include "../../include/seb.h"
+#include "seb.h"
 #include "seb_internal.hpp"
 #include "seb_net_internal.hpp"
 #include "seb_surrogate_internal.hpp"
@@ -484,7 +484,7 @@ int seb_create(const seb_config* cfg, seb_ctx** out) {
     std::string why;
     build_geometry(*cfg, &c->geo, &why);
     c->pitch = pick_pitch(c->geo.R);
-    hipGetDevice(&c->device);
+    (void)hipGetDevice(&c->device);
 
     // FP64 table: per yaw bin, per sample, the snapped grid offset split into
     // an integer corner and bilinear fractions.
@@ -547,7 +547,7 @@ void seb_destroy(seb_ctx* c) {
     if (!c) return;
     for (void* p : {(void*)c->d_wts, (void*)c->d_offs, (void*)c->d_frac, (void*)c->d_qs,
                     (void*)c->d_pks, (void*)c->d_segs})
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
     delete c;
 }
 
@@ -724,7 +724,7 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
 
 void seb_surrogate_destroy(seb_surrogate* s) {
     if (!s) return;
-    for (void* p : s->allocs) hipFree(p);
+    for (void* p : s->allocs) (void)hipFree(p);
     delete s;
 }
 

@@ -14,7 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/seb.h"
+#include "seb.h"
 #include "seb_net_internal.hpp"
 
 namespace seb {
@@ -577,7 +577,7 @@ const char* seb_net_last_error(void) { return g_net_error.c_str(); }
 
 void seb_net_destroy(seb_net* n) {
     if (!n) return;
-    for (void* p : n->allocs) hipFree(p);
+    for (void* p : n->allocs) (void)hipFree(p);
     delete n;
 }
 
@@ -589,7 +589,7 @@ int seb_net_create(uint64_t seed, int32_t max_batch, seb_net** out) {
     seb_net* n = new (std::nothrow) seb_net();
     if (!n) return net_fail(SEB_ERR_ALLOC, "host allocation failed");
     n->max_batch = max_batch;
-    hipGetDevice(&n->device);
+    (void)hipGetDevice(&n->device);
     const int64_t Bm = max_batch;
     const int64_t r1 = Bm * N::P1 * N::P1, r2 = Bm * N::P2 * N::P2;
     bool ok = dalloc(n, &n->theta, N::N_PARAMS) && dalloc(n, &n->m, N::N_PARAMS) &&

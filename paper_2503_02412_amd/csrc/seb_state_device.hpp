@@ -6,7 +6,7 @@
 
 #include <cmath>
 
-#include "../../include/seb.h"
+#include "seb.h"
 #include "seb_internal.hpp"
 
 namespace seb {

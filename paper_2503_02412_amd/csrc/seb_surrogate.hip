@@ -14,7 +14,7 @@
 // -- are appended to per-yaw lists and re-assessed by the plain method.
 #include <cmath>
 
-#include "../../include/seb.h"
+#include "seb.h"
 #include "seb_internal.hpp"
 #include "seb_net_internal.hpp"
 #include "seb_state_device.hpp"
