@@ -44,7 +44,7 @@ def flops_per_state(params) -> int:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("seb_assess.hip", "seb_internal.hpp"):
+    for f in ("seb_assess.hip", "seb_state_device.hpp", "seb_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2503_02412_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
