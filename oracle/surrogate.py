@@ -126,41 +126,50 @@ def relu(x):
     return np.maximum(x, 0.0)
 
 
-def forward(P: dict, X: np.ndarray, sc: np.ndarray):
-    """X [B, 3, 24, 24], sc [B, 2] = (sin yaw, cos yaw) -> y [B, 4] and a cache."""
+def _identity(x):
+    return x
+
+
+def forward(P: dict, X: np.ndarray, sc: np.ndarray, rnd=_identity):
+    """X [B, 3, 24, 24], sc [B, 2] = (sin yaw, cos yaw) -> y [B, 4] and a cache.
+
+    `rnd` is applied to every hidden activation (identity by default; pass
+    bf16_round to mirror hardware that stores activations in bfloat16)."""
     B = X.shape[0]
     a1 = conv_stride2(X, P["W1"]) + P["b1"][None, :, None, None]
-    o1 = relu(a1)
+    o1 = rnd(relu(a1))
     a2 = conv_stride2(o1, P["W2"]) + P["b2"][None, :, None, None]
-    o2 = relu(a2)
+    o2 = rnd(relu(a2))
     f = o2.transpose(0, 2, 3, 1).reshape(B, 800)
     a3 = f @ P["W3"].T + sc @ P["Wy"].T + P["b3"]
-    h1 = relu(a3)
+    h1 = rnd(relu(a3))
     a4 = h1 @ P["W4"].T + P["b4"]
-    h2 = relu(a4)
+    h2 = rnd(relu(a4))
     y = h2 @ P["W5"].T + P["b5"]
     cache = dict(X=X, sc=sc, a1=a1, o1=o1, a2=a2, o2=o2, f=f, a3=a3, h1=h1, a4=a4, h2=h2)
     return y, cache
 
 
-def backward(P: dict, cache: dict, dy: np.ndarray) -> dict:
+def backward(P: dict, cache: dict, dy: np.ndarray, rnd=_identity) -> dict:
+    """Gradients of the loss in every parameter given dL/dy.  `rnd` is applied
+    to the back-propagated deltas (identity by default)."""
     B = dy.shape[0]
     g = {}
+    dy = rnd(dy)
     g["W5"] = dy.T @ cache["h2"]
     g["b5"] = dy.sum(0)
-    da4 = (dy @ P["W5"]) * (cache["a4"] > 0)
+    da4 = rnd((dy @ P["W5"]) * (cache["a4"] > 0))
     g["W4"] = da4.T @ cache["h1"]
     g["b4"] = da4.sum(0)
-    da3 = (da4 @ P["W4"]) * (cache["a3"] > 0)
+    da3 = rnd((da4 @ P["W4"]) * (cache["a3"] > 0))
     g["W3"] = da3.T @ cache["f"]
     g["Wy"] = da3.T @ cache["sc"]
     g["b3"] = da3.sum(0)
-    df = da3 @ P["W3"]
-    do2 = df.reshape(B, 5, 5, 32).transpose(0, 3, 1, 2)
-    da2 = do2 * (cache["a2"] > 0)
+    df = rnd((da3 @ P["W3"]) * (cache["f"] > 0))
+    da2 = df.reshape(B, 5, 5, 32).transpose(0, 3, 1, 2)
     g["b2"] = da2.sum((0, 2, 3))
     do1, g["W2"] = conv_stride2_backward(cache["o1"], P["W2"], da2)
-    da1 = do1 * (cache["a1"] > 0)
+    da1 = rnd(do1 * (cache["a1"] > 0))
     g["b1"] = da1.sum((0, 2, 3))
     _, g["W1"] = conv_stride2_backward(cache["X"], P["W1"], da1)
     return g
