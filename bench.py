@@ -144,7 +144,7 @@ def bench_large(torch, seb):
             "frac_of_vendor_fp32": f / (ms * 1e-3) / 1e12 / VENDOR_FP32_PEAK_TFLOPS}
 
 
-def bench_surrogate(torch, seb, train_steps: int = 2000, eval_maps: int = 4):
+def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4):
     """Train the surrogate on plain-kernel labels, then time inference with the
     plain fallback on 200x200x36 evaluation maps against the plain kernel, and
     measure its error against the FP64 oracle on the states it answered."""
@@ -169,7 +169,7 @@ def bench_surrogate(torch, seb, train_steps: int = 2000, eval_maps: int = 4):
     for seed in I.SURROGATE_EVAL_SEEDS[:eval_maps]:
         h = I.config2_map(seed)
         dh = torch.from_numpy(h).cuda()
-        t_sur.append(time_launches(torch, lambda: sur.infer(net, dh, out, band=0.1, min_known=0.75,
+        t_sur.append(time_launches(torch, lambda: sur.infer(net, dh, out, band=0.1, min_known=0.5,
                                                             n_fallback=nf), 50, 5))
         fallback.append(int(nf.item()) / p.n_states)
         g = {k: v.cpu().numpy() for k, v in out.items()}
@@ -183,7 +183,7 @@ def bench_surrogate(torch, seb, train_steps: int = 2000, eval_maps: int = 4):
     ms_sur, ms_plain = float(np.mean(t_sur)), float(np.mean(t_plain))
     return {
         "workload": "2-conv + 3-layer MLP (bf16, MFMA) on 24x24 slope/known patches + yaw; "
-                    "trained on ~2M plain-kernel labels of 70 seeded 64x64 sinusoid terrains; "
+                    "trained on 2M plain-kernel labels of 70 seeded 64x64 sinusoid terrains; "
                     f"evaluated on {eval_maps} seeded 200x200x36 fractal maps",
         "train_steps": train_steps, "train_batch": 4096,
         "train_samples_per_s": train_steps * 4096 / t_train, "label_seconds": t_data,
@@ -195,7 +195,7 @@ def bench_surrogate(torch, seb, train_steps: int = 2000, eval_maps: int = 4):
         "mean_abs_err": {f: float(np.concatenate(v).mean()) for f, v in err.items()},
         "max_abs_err": {f: float(np.concatenate(v).max()) for f, v in err.items()},
         "mask_agreement": mask_ok / max(1, answered),
-        "band": 0.1, "min_known": 0.75,
+        "band": 0.1, "min_known": 0.5,
     }
 
 

@@ -71,8 +71,9 @@ typedef struct seb_config {
     double w_kappa, w_phi_x, w_phi_y, risk_max;
     int32_t min_valid;           /* >= 3 samples needed for a fit                 */
     int32_t precision;           /* 0 FP32; 1 FP32 + FP64 for near-degenerate    */
-    int32_t fit;                 /* 0 least-squares plane (1: principal-component,
-                                    not provided by the kernels)                   */
+    int32_t fit;                 /* 0 least-squares plane; 1 principal-component
+                                    plane of Algorithm 1 (minimum eigenvector of
+                                    the footprint covariance, solved in FP64)     */
 } seb_config;
 
 /* Output arrays, each [K][H][W] on the device.  z and the angles are NaN for

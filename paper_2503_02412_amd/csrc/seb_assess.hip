@@ -32,7 +32,7 @@ namespace {
 
 using namespace dev;
 
-template <int P, int NW>
+template <int P, int NW, int FIT>
 __global__ __launch_bounds__(BLOCK) void assess_kernel(const AssessArgs a) {
     extern __shared__ float tile[];
     const int tid = threadIdx.x;
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(BLOCK) void assess_kernel(const AssessArgs a) {
     const int u0 = blockIdx.y * a.units_per_group;
     const int u1 = min(a.n_units, u0 + a.units_per_group);
     for (int u = u0; u < u1; ++u) {
-        const Result r = assess_state<NW>(a, LdsSource<P>{tp0}, u, hc, active);
+        const Result r = assess_state<NW, FIT>(a, LdsSource<P>{tp0}, u, hc, active);
         if (active) {
             store(a, u, cell, r, false);
             if (a.mirror) store(a, u + a.mirror, cell, r, true);
@@ -127,14 +127,22 @@ int pick_pitch(int R) {
 
 bool has_row_kernel(int row_len) { return row_len == 4 || row_len == 12 || row_len == 24; }
 
+template <int P, int FIT>
+static void launch_pf(const AssessArgs& a, dim3 grid, size_t lds, hipStream_t stream) {
+    switch (a.row_len) {
+        case 4: hipLaunchKernelGGL((assess_kernel<P, 4, FIT>), grid, dim3(BLOCK), lds, stream, a); break;
+        case 12: hipLaunchKernelGGL((assess_kernel<P, 12, FIT>), grid, dim3(BLOCK), lds, stream, a); break;
+        case 24: hipLaunchKernelGGL((assess_kernel<P, 24, FIT>), grid, dim3(BLOCK), lds, stream, a); break;
+        default: hipLaunchKernelGGL((assess_kernel<P, 0, FIT>), grid, dim3(BLOCK), lds, stream, a); break;
+    }
+}
+
 template <int P>
 static hipError_t launch_p(const AssessArgs& a, dim3 grid, size_t lds, hipStream_t stream) {
-    switch (a.row_len) {
-        case 4: hipLaunchKernelGGL((assess_kernel<P, 4>), grid, dim3(BLOCK), lds, stream, a); break;
-        case 12: hipLaunchKernelGGL((assess_kernel<P, 12>), grid, dim3(BLOCK), lds, stream, a); break;
-        case 24: hipLaunchKernelGGL((assess_kernel<P, 24>), grid, dim3(BLOCK), lds, stream, a); break;
-        default: hipLaunchKernelGGL((assess_kernel<P, 0>), grid, dim3(BLOCK), lds, stream, a); break;
-    }
+    if (a.fit == 1)
+        launch_pf<P, 1>(a, grid, lds, stream);
+    else
+        launch_pf<P, 0>(a, grid, lds, stream);
     return hipGetLastError();
 }
 

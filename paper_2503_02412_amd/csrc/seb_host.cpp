@@ -233,10 +233,6 @@ int validate(const seb_config* c, std::string* why) {
         *why = "at most 65536 footprint samples are supported";
         return SEB_ERR_UNSUPPORTED;
     }
-    if (c->fit == 1) {
-        *why = "the principal-component fit is not provided by the kernels";
-        return SEB_ERR_UNSUPPORTED;
-    }
     return SEB_OK;
 }
 
@@ -314,6 +310,7 @@ void base_args(const seb_ctx* c, AssessArgs* a) {
     a->risk_max = (float)g.risk_max;
     a->min_valid = g.min_valid;
     a->precision = g.precision;
+    a->fit = g.fit;
 }
 
 // Tile decomposition of the state rectangles; chooses the yaw bins per workgroup.
@@ -704,7 +701,8 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
         al((void**)&w.Y, (size_t)U * seb::net::H1 * 4) && al((void**)&w.rows, (size_t)cells * 4) &&
         al((void**)&w.known, (size_t)cells * 4) &&
         al((void**)&w.counts, (size_t)c->cfg.n_yaw * 4) &&
-        al((void**)&w.lists, (size_t)U * cells * 4);
+        al((void**)&w.lists, (size_t)U * cells * 4) &&
+        al((void**)&w.pad, (size_t)(H + 2 * c->geo.R) * (W + 2 * c->geo.R) * 4);
     if (!ok) {
         seb_surrogate_destroy(s);
         return fail(SEB_ERR_ALLOC, "device allocation failed");
@@ -716,6 +714,7 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
     w.U = U;
     w.mirror = c->geo.mirror;
     w.pitch = c->pitch;
+    w.R = c->geo.R;
     w.risk_max = (float)c->cfg.risk_max;
     *out = s;
     return SEB_OK;

@@ -80,6 +80,7 @@ struct AssessArgs {
     float kappa_max, phi_x_max, phi_y_max, w_kappa, w_phi_x, w_phi_y, risk_max;
     int32_t min_valid;
     int32_t precision;
+    int32_t fit;                 // 0 least-squares plane, 1 principal-component plane
     // state rectangles (logical coordinates) and their tile decomposition
     int32_t n_rects;
     int32_t rect[MAX_RECTS][4];

@@ -43,9 +43,88 @@ struct Result {
     uint8_t st;
 };
 
-// Least-squares plane z = a + b u + c v from the moments, then Eq. 1-3 and
-// Algorithm 1.  u = hu p, v = hv q are the body-frame sample coordinates.
-template <typename T>
+// Algorithm 1's two early-outs and the weighted risk, from the curvature and
+// the two tilt magnitudes; sets the obstacle and traversable bits.
+__device__ __forceinline__ float weigh_risk(const AssessArgs& a, float kappa, float phx, float phy,
+                                            uint8_t& st) {
+    float risk;
+    if (kappa > a.kappa_max) {
+        risk = 1.f;
+        st |= SEB_ST_CURV;
+    } else if (phx > a.phi_x_max || phy > a.phi_y_max) {
+        risk = 1.f;
+        st |= SEB_ST_TILT;
+    } else {
+        risk = a.w_kappa * kappa / a.kappa_max + a.w_phi_x * phx / a.phi_x_max +
+               a.w_phi_y * phy / a.phi_y_max;
+    }
+    if (risk <= a.risk_max) st |= SEB_ST_TRAV;
+    return risk;
+}
+
+// Principal-component plane of Algorithm 1: the eigenvector of the footprint
+// scatter S (N times the covariance) with the smallest eigenvalue, turned to
+// point up, and kappa = lambda_min / tr S.  Always solved in FP64.
+// lambda_min is the smallest root of the characteristic polynomial
+// f(l) = l^3 - c2 l^2 + c1 l - c0 (c2 = tr S, c1 = sum of the principal 2 x 2
+// minors, c0 = det S), found by Newton's method from l = 0.  S is positive
+// semi-definite, so every root is real and >= 0, and lambda_min <= tr S / 3;
+// on [0, lambda_min] f is therefore increasing and concave (f'' = 6 l - 2 c2),
+// and the iterates rise monotonically to lambda_min without overshooting it:
+// quadratically for a simple root, halving the distance for a double one.
+// The iteration stops when a step no longer increases l.  The eigenvector is
+// the longest of the three cross products of two rows of S - lambda_min I
+// (each is orthogonal to the row space).  A scatter whose smallest eigenvalue
+// is repeated has no unique normal; it gets (0, 0, 1).
+struct PcaPlane {
+    double nu, nv, nz;   // unit normal in the yaw frame, nz >= 0
+    double kappa;
+};
+
+__device__ inline PcaPlane pca_plane(double suu, double svv, double szz, double suv, double suz,
+                                     double svz) {
+    const double c2 = suu + svv + szz;
+    const double c1 = (suu * svv - suv * suv) + (suu * szz - suz * suz) + (svv * szz - svz * svz);
+    const double c0 = suu * (svv * szz - svz * svz) - suv * (suv * szz - svz * suz) +
+                      suz * (suv * svz - svv * suz);
+    double lam = 0.0;
+    for (int it = 0; it < 128; ++it) {
+        const double f = ((lam - c2) * lam + c1) * lam - c0;
+        const double df = (3.0 * lam - 2.0 * c2) * lam + c1;
+        if (!(f < 0.0) || !(df > 0.0)) break;
+        const double next = lam - f / df;
+        if (!(next > lam)) break;
+        lam = next;
+    }
+    const double a0 = suu - lam, a1 = svv - lam, a2 = szz - lam;
+    // rows (a0, suv, suz), (suv, a1, svz), (suz, svz, a2)
+    const double x01 = suv * svz - suz * a1, y01 = suz * suv - a0 * svz, z01 = a0 * a1 - suv * suv;
+    const double x02 = suv * a2 - suz * svz, y02 = suz * suz - a0 * a2, z02 = a0 * svz - suv * suz;
+    const double x12 = a1 * a2 - svz * svz, y12 = svz * suz - suv * a2, z12 = suv * svz - a1 * suz;
+    const double d01 = x01 * x01 + y01 * y01 + z01 * z01;
+    const double d02 = x02 * x02 + y02 * y02 + z02 * z02;
+    const double d12 = x12 * x12 + y12 * y12 + z12 * z12;
+    double x = 0.0, y = 0.0, z = 1.0, d = 1.0;
+    if (d01 >= d02 && d01 >= d12 && d01 > 0.0) {
+        x = x01; y = y01; z = z01; d = d01;
+    } else if (d02 >= d12 && d02 > 0.0) {
+        x = x02; y = y02; z = z02; d = d02;
+    } else if (d12 > 0.0) {
+        x = x12; y = y12; z = z12; d = d12;
+    }
+    const double s = (z < 0.0 ? -1.0 : 1.0) / sqrt(d);
+    PcaPlane pl;
+    pl.nu = x * s;
+    pl.nv = y * s;
+    pl.nz = z * s;
+    pl.kappa = (c2 > 0.0) ? lam / c2 : 0.0;
+    return pl;
+}
+
+// Plane from the moments, then Eq. 1-3 and Algorithm 1.  u = hu p, v = hv q
+// are the body-frame sample coordinates.  fit 0: least-squares plane
+// z = a + b u + c v; fit 1: principal-component plane.
+template <int FIT, typename T>
 __device__ Result finish(const AssessArgs& a, const Moments<T>& m, T ref) {
     Result r;
     const int64_t N = m.N;
@@ -68,6 +147,24 @@ __device__ Result finish(const AssessArgs& a, const Moments<T>& m, T ref) {
     const T pz = m.Spz - T(m.Sp) * zb;      // sum (p - pbar)(z - zbar)
     const T qz = m.Sqz - T(m.Sq) * zb;
     const T zz = m.Szz - m.Sz * zb;         // sum (z - zbar)^2
+    if constexpr (FIT == 1) {
+        // Scatter in metres: S_uu = hu^2 D / N, S_vv = hv^2 E / N, S_uv = hu hv F / N.
+        const double hu = a.hu, hv = a.hv, dN = (double)N;
+        const PcaPlane pl = pca_plane(hu * hu * (double)D / dN, hv * hv * (double)E / dN,
+                                      (double)zz, hu * hv * (double)F / dN, hu * (double)pz,
+                                      hv * (double)qz);
+        // The plane through the centroid, evaluated at the state's cell centre.
+        const double ubar = hu * (double)m.Sp / dN, vbar = hv * (double)m.Sq / dN;
+        r.z = (float)((double)ref + (double)zb + (pl.nu * ubar + pl.nv * vbar) / pl.nz);
+        const float nu = (float)pl.nu, nv = (float)pl.nv, nz = (float)pl.nz;
+        const float l2 = nv * nv + nz * nz;
+        r.roll = atan2f(-nv, nz);                                        // asin(b3 . y_b)
+        r.pitch = atan2f(nu, sqrtf(l2));                                 // atan2(-b3 . x_b, b3 . z_b)
+        const float phx = atan2f(nz * fabsf(nu), sqrtf(nu * nu * nv * nv + l2 * l2));
+        r.risk = weigh_risk(a, (float)pl.kappa, phx, fabsf(r.roll), st);
+        r.st = st;
+        return r;
+    }
     const T tdet = T(det);
     const T bp = T(N) * (T(E) * pz - T(F) * qz) / tdet;   // dz/dp
     const T bq = T(N) * (T(D) * qz - T(F) * pz) / tdet;   // dz/dq
@@ -86,19 +183,7 @@ __device__ Result finish(const AssessArgs& a, const Moments<T>& m, T ref) {
     r.pitch = -atan2f(bf, sqrtf(c1));               // atan2(-b3 . x_b, b3 . z_b)
     const float phx = atan2f(fabsf(bf), sqrtf(c1 * c1 + bf * bf * cf * cf));   // |asin(b3 . x_b)|
     const float phy = fabsf(r.roll);                                             // |asin(b3 . y_b)|
-    float risk;
-    if (kappa > a.kappa_max) {
-        risk = 1.f;
-        st |= SEB_ST_CURV;
-    } else if (phx > a.phi_x_max || phy > a.phi_y_max) {
-        risk = 1.f;
-        st |= SEB_ST_TILT;
-    } else {
-        risk = a.w_kappa * kappa / a.kappa_max + a.w_phi_x * phx / a.phi_x_max +
-               a.w_phi_y * phy / a.phi_y_max;
-    }
-    if (risk <= a.risk_max) st |= SEB_ST_TRAV;
-    r.risk = risk;
+    r.risk = weigh_risk(a, kappa, phx, phy, st);
     r.st = st;
     return r;
 }
@@ -141,6 +226,24 @@ struct GlobalSource {
         h01 = cell(x + 1, y);
         h10 = cell(x, y + 1);
         h11 = cell(x + 1, y + 1);
+    }
+};
+
+// A sentinel-padded copy of the map in global memory: row stride ldp, the
+// state's own cell at `base`; no bounds checks needed within the halo.
+struct PaddedSource {
+    const float* base;
+    int ldp;
+    int P;              // LDS pitch the table offsets were built for
+    __device__ __forceinline__ void quad(int off, float& h00, float& h01, float& h10,
+                                         float& h11) const {
+        const int dy = (off + P / 2 + 1024 * P) / P - 1024;
+        const int dx = off - dy * P;
+        const float* p = base + (int64_t)dy * ldp + dx;
+        h00 = p[0];
+        h01 = p[1];
+        h10 = p[ldp];
+        h11 = p[ldp + 1];
     }
 };
 
@@ -288,7 +391,7 @@ __device__ __forceinline__ void store(const AssessArgs& a, int k, int64_t cell, 
 // Reference height, moments, optional FP64 redo and result of one state for
 // yaw unit u.  hc = the state's own cell (SENTINEL if unknown); `active`
 // lanes take part in the reference search.
-template <int NW, class Src>
+template <int NW, int FIT, class Src>
 __device__ __forceinline__ Result assess_state(const AssessArgs& a, const Src& src, int u, float hc,
                                                bool active) {
     const int64_t ub = (int64_t)u * a.n_samples;
@@ -319,14 +422,14 @@ __device__ __forceinline__ Result assess_state(const AssessArgs& a, const Src& s
         accumulate_rows<NW>(a, src, W, O, ref, m);
     else
         accumulate_segments(a, src, W, O, ref, m);
-    Result r = finish<float>(a, m, ref);
+    Result r = finish<FIT>(a, m, ref);
 
     if (a.precision == 1) {
         const bool redo = (r.st & SEB_ST_DEGEN) != 0;
         if (__ballot(redo) && redo) {
             Moments<double> md;
             accumulate64(a, src, O, as_const(a.frac) + ub, (double)ref, md);
-            r = finish<double>(a, md, (double)ref);
+            r = finish<FIT>(a, md, (double)ref);
         }
     }
     return r;

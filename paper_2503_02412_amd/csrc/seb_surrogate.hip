@@ -273,8 +273,24 @@ __global__ __launch_bounds__(256) void head_kernel(const SurArgs s, const Assess
     if (a.mirror) store(a, u + a.mirror, cell, res, true);
 }
 
-// Plain-method re-assessment of the listed states of yaw unit blockIdx.y.
-template <int NW>
+// The map with SENTINEL for unknown cells and an R-cell border, so the
+// fallback kernel reads footprint corners without bounds checks.
+__global__ void pad_kernel(const SurArgs s) {
+    const int Wp = s.W + 2 * s.R;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)(s.H + 2 * s.R) * Wp) return;
+    const int y = (int)(i / Wp) - s.R, x = (int)(i % Wp) - s.R;
+    float v = SENTINEL;
+    if (y >= 0 && x >= 0 && y < s.H && x < s.W) {
+        const float h = s.height[(int64_t)y * s.ld + x];
+        if (fabsf(h) < HEIGHT_LIMIT) v = h;
+    }
+    s.pad[i] = v;
+}
+
+// Plain-method re-assessment of the listed states of yaw unit blockIdx.y:
+// the same arithmetic as the tiled kernel, heights from the padded map.
+template <int NW, int FIT>
 __global__ __launch_bounds__(64) void fallback_kernel(const SurArgs s, const AssessArgs a) {
     const int u = blockIdx.y;
     const int count = s.counts[u];
@@ -283,18 +299,14 @@ __global__ __launch_bounds__(64) void fallback_kernel(const SurArgs s, const Ass
     const bool active = i < count;
     const int64_t cells = (int64_t)s.H * s.W;
     const int cell = active ? s.lists[(int64_t)u * cells + i] : 0;
-    GlobalSource src;
-    src.height = s.height;
-    src.ld = s.ld;
-    src.W = s.W;
-    src.H = s.H;
-    src.rx = 0;
-    src.ry = 0;
-    src.ix = cell % s.W;
-    src.iy = cell / s.W;
+    const int ix = cell % s.W, iy = cell / s.W;
+    const int ldp = s.W + 2 * s.R;
+    PaddedSource src;
+    src.base = s.pad + (int64_t)(iy + s.R) * ldp + (ix + s.R);
+    src.ldp = ldp;
     src.P = s.pitch;
-    const float hc = src.cell(src.ix, src.iy);
-    const Result r = assess_state<NW>(a, src, u, hc, active);
+    const float hc = src.base[0];
+    const Result r = assess_state<NW, FIT>(a, src, u, hc, active);
     if (active) {
         store(a, u, cell, r, false);
         if (a.mirror) store(a, u + a.mirror, cell, r, true);
@@ -308,6 +320,16 @@ __global__ void total_kernel(const SurArgs s, int32_t* out) {
     *out = n * (s.mirror ? 2 : 1);
 }
 
+template <int FIT>
+void launch_fallback(const SurArgs& s, const AssessArgs& a, dim3 fg, hipStream_t stream) {
+    switch (a.row_len) {
+        case 4: hipLaunchKernelGGL((fallback_kernel<4, FIT>), fg, dim3(64), 0, stream, s, a); break;
+        case 12: hipLaunchKernelGGL((fallback_kernel<12, FIT>), fg, dim3(64), 0, stream, s, a); break;
+        case 24: hipLaunchKernelGGL((fallback_kernel<24, FIT>), fg, dim3(64), 0, stream, s, a); break;
+        default: hipLaunchKernelGGL((fallback_kernel<0, FIT>), fg, dim3(64), 0, stream, s, a); break;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, int32_t* n_fallback,
@@ -315,6 +337,8 @@ hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, int32_t* n_fa
     const int64_t cells = (int64_t)s.H * s.W;
     auto blocks = [](int64_t n, int b) { return (unsigned)((n + b - 1) / b); };
     hipLaunchKernelGGL(yaw_kernel, dim3(blocks(std::max<int64_t>(s.U * net::H1, s.K), 256)),
+                       dim3(256), 0, stream, s);
+    hipLaunchKernelGGL(pad_kernel, dim3(blocks((int64_t)(s.H + 2 * s.R) * (s.W + 2 * s.R), 256)),
                        dim3(256), 0, stream, s);
     hipLaunchKernelGGL(known_rows_kernel, dim3(blocks(cells, 256)), dim3(256), 0, stream, s);
     hipLaunchKernelGGL(known_cols_kernel, dim3(blocks(cells, 256)), dim3(256), 0, stream, s);
@@ -325,12 +349,10 @@ hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, int32_t* n_fa
     hipLaunchKernelGGL(fc1_map_kernel, dim3(blocks(cells, 64)), dim3(256), 0, stream, s);
     hipLaunchKernelGGL(head_kernel, dim3(blocks(cells * s.U, 64)), dim3(256), 0, stream, s, a);
     const dim3 fg(blocks(cells, 64), s.U);
-    switch (a.row_len) {
-        case 4: hipLaunchKernelGGL(fallback_kernel<4>, fg, dim3(64), 0, stream, s, a); break;
-        case 12: hipLaunchKernelGGL(fallback_kernel<12>, fg, dim3(64), 0, stream, s, a); break;
-        case 24: hipLaunchKernelGGL(fallback_kernel<24>, fg, dim3(64), 0, stream, s, a); break;
-        default: hipLaunchKernelGGL(fallback_kernel<0>, fg, dim3(64), 0, stream, s, a); break;
-    }
+    if (a.fit == 1)
+        launch_fallback<1>(s, a, fg, stream);
+    else
+        launch_fallback<0>(s, a, fg, stream);
     if (n_fallback) hipLaunchKernelGGL(total_kernel, dim3(1), dim3(64), 0, stream, s, n_fallback);
     return hipGetLastError();
 }

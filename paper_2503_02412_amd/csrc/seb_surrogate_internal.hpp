@@ -30,6 +30,8 @@ struct SurArgs {
     float* known;                // [H*W]               known fraction of the 24 x 24 window
     int32_t* counts;             // [K]                 flagged states per yaw unit
     int32_t* lists;              // [U][H*W]            flagged cells per yaw unit
+    float* pad;                  // [(H+2R)][(W+2R)]    map with SENTINEL for unknown / outside
+    int R;                       // halo of the padded map (the context's footprint reach)
     // fallback rule
     float risk_max, band, min_known;
 };

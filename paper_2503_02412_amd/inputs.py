@@ -291,10 +291,11 @@ def surrogate_training_map(seed: int, size: int = 64, res: float = 0.1) -> np.nd
 
 
 def surrogate_samples(n_maps: int, size: int, n_yaw: int, seed: int, count: int | None = None,
-                      half: int = 12) -> np.ndarray:
-    """All (map, cy, cx, k) whose input window [c-12, c+12] lies inside the map,
-    in a seeded random order (first `count` kept); int32 [count, 4]."""
-    c = np.arange(half, size - half)
+                      margin: int = 0) -> np.ndarray:
+    """All (map, cy, cx, k) with the cell at least `margin` cells inside the map
+    (windows may extend past the edge), in a seeded random order (first
+    `count` kept); int32 [count, 4]."""
+    c = np.arange(margin, size - margin)
     m, y, x, k = np.meshgrid(np.arange(n_maps), c, c, np.arange(n_yaw), indexing="ij")
     s = np.stack([m.ravel(), y.ravel(), x.ravel(), k.ravel()], 1).astype(np.int32)
     perm = _rng(seed).permutation(len(s))

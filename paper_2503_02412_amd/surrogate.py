@@ -33,7 +33,8 @@ class TrainingData:
                 ctx.assess(self.maps[i], out)
         torch.cuda.synchronize()
         # Samples: yaw bins of the first half (the second half mirrors them),
-        # window inside the map, own cell known, plain fit valid.
+        # every cell (windows may reach past the map edge), own cell known,
+        # plain fit valid.
         cand = I.surrogate_samples(n, params.width, K // 2 if K % 2 == 0 else K, sample_seed)
         st = status.cpu().numpy()
         ok = (st[cand[:, 0], cand[:, 3], cand[:, 1], cand[:, 2]] & seb.ST_VALID) > 0

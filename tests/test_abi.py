@@ -53,7 +53,7 @@ def test_presets_are_valid(name):
     (dict(kappa_max=0.0), seb.SEB_ERR_INVALID),
     (dict(min_valid=2), seb.SEB_ERR_INVALID),
     (dict(precision=3), seb.SEB_ERR_INVALID),
-    (dict(fit=1), seb.SEB_ERR_UNSUPPORTED),
+    (dict(fit=2), seb.SEB_ERR_INVALID),
     (dict(fp_length=12.0, fp_width=12.0), seb.SEB_ERR_UNSUPPORTED),   # halo too wide for LDS
 ])
 def test_invalid_configs_are_rejected(change, code):

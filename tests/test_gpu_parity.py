@@ -98,6 +98,41 @@ def test_ellipse_footprint(torch_cuda, orc):
     compare(run(torch_cuda, p, h), orc.assess_rect(p, h), p)
 
 
+@pytest.mark.parametrize("case", ["config1", "ragged_odd_k", "ellipse", "config2"])
+def test_principal_component_fit(torch_cuda, orc, case):
+    """fit 1: the minimum-eigenvector plane of Algorithm 1, against the
+    oracle's Jacobi eigen-decomposition of the same covariance."""
+    if case == "config1":
+        p, h = I.CONFIG1, I.config1_map(1)
+    elif case == "ragged_odd_k":
+        p = I.Params(37, 23, 0.1, 15, 0.7, 0.5, 7, 5)
+        rng = np.random.default_rng(3)
+        h = I.sinusoid_terrain(37, 23, 0.1, 9)
+        h[rng.random(h.shape) < 0.08] = np.nan
+    elif case == "ellipse":
+        p = I.Params(48, 40, 0.05, 24, 0.8, 0.5, 16, 10, fp_shape=1)
+        h = I.fractal_terrain(48, 40, 0.05, 21, hole_frac=0.05)
+    else:
+        p, h = I.CONFIG2, I.config2_map(2)
+    p = p.with_(fit=1)
+    s = compare(run(torch_cuda, p, h), orc.assess_rect(p, h), p)
+    print(s)
+
+
+def test_fits_coincide_on_a_plane(torch_cuda):
+    """On a planar map both fits recover the same plane."""
+    p = I.CONFIG1
+    yy, xx = np.mgrid[0:64, 0:64]
+    h = (0.02 * xx - 0.013 * yy + 0.5).astype(np.float32)
+    h[5:9, 40:47] = np.nan
+    a = run(torch_cuda, p, h)
+    b = run(torch_cuda, p.with_(fit=1), h)
+    assert np.array_equal(a["status"], b["status"])
+    v = (a["status"] & 1) > 0
+    for f in ("z", "roll", "pitch", "risk"):
+        assert np.max(np.abs(a[f][v] - b[f][v])) < 2e-5, f
+
+
 def test_unknown_and_flat_maps(torch_cuda):
     p = I.CONFIG1
     g = run(torch_cuda, p, np.full((64, 64), np.nan, np.float32))
@@ -176,11 +211,12 @@ def hardest_subregion(h, reach, size=64, stride=16):
     return arg
 
 
-def test_precision_mode_on_degenerate_states(torch_cuda, orc):
+@pytest.mark.parametrize("fit", [0, 1])
+def test_precision_mode_on_degenerate_states(torch_cuda, orc, fit):
     """FP32 + FP64 (precision 1) on the large-footprint map with 15% holes:
     near-degenerate states are recomputed in FP64 and land much closer to
     the oracle."""
-    p0 = I.CONFIG5
+    p0 = I.CONFIG5.with_(fit=fit)
     h = I.config5_map(5)
     x0, y0 = hardest_subregion(h, orc.reach(p0))
     errs = {}
