@@ -699,10 +699,7 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
         al((void**)&w.o2map, (size_t)(H + 16) * (W + 16) * seb::net::C2 * 2) &&
         al((void**)&w.T, (size_t)cells * seb::net::H1 * 4) &&
         al((void**)&w.Y, (size_t)U * seb::net::H1 * 4) && al((void**)&w.rows, (size_t)cells * 4) &&
-        al((void**)&w.known, (size_t)cells * 4) &&
-        al((void**)&w.counts, (size_t)c->cfg.n_yaw * 4) &&
-        al((void**)&w.lists, (size_t)U * cells * 4) &&
-        al((void**)&w.pad, (size_t)(H + 2 * c->geo.R) * (W + 2 * c->geo.R) * 4);
+        al((void**)&w.known, (size_t)cells * 4) && al((void**)&w.need, (size_t)U * cells);
     if (!ok) {
         seb_surrogate_destroy(s);
         return fail(SEB_ERR_ALLOC, "device allocation failed");
@@ -714,7 +711,6 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
     w.U = U;
     w.mirror = c->geo.mirror;
     w.pitch = c->pitch;
-    w.R = c->geo.R;
     w.risk_max = (float)c->cfg.risk_max;
     *out = s;
     return SEB_OK;
@@ -742,6 +738,7 @@ int seb_surrogate_infer(seb_surrogate* s, const seb_net* net, const float* heigh
     w.pw = seb::net::net_packed(net);
     w.band = band;
     w.min_known = min_known;
+    w.n_fallback = n_fallback_dev;
     AssessArgs a;
     base_args(s->ctx, &a);
     a.height = height;
@@ -751,8 +748,13 @@ int seb_surrogate_infer(seb_surrogate* s, const seb_net* net, const float* heigh
     a.pitch = out->pitch;
     a.risk = out->risk;
     a.status = out->status;
-    const hipError_t e = seb::sur::launch_surrogate(w, a, n_fallback_dev, (hipStream_t)stream);
+    hipError_t e = seb::sur::launch_surrogate(w, a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "surrogate launch");
+    // The plain method for the flagged states, compacted tile by tile.
+    a.need = w.need;
+    a.count = n_fallback_dev;
+    e = launch_assess_flagged(a, s->ctx->pitch, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fallback assessment launch");
     return SEB_OK;
 }
 

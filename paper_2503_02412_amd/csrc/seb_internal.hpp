@@ -81,6 +81,10 @@ struct AssessArgs {
     int32_t min_valid;
     int32_t precision;
     int32_t fit;                 // 0 least-squares plane, 1 principal-component plane
+    const uint8_t* need;         // [n_units][H][W] (ring cells) for the flagged-state
+                                 // kernel: assess the states whose byte is nonzero
+    int32_t* count;              // optional: the flagged-state kernel adds the number of
+                                 // states it assessed (both mirror bins)
     // state rectangles (logical coordinates) and their tile decomposition
     int32_t n_rects;
     int32_t rect[MAX_RECTS][4];
@@ -102,6 +106,8 @@ struct InsertArgs {
 
 // Launchers (seb_assess.hip).  Return hipSuccess or the launch error.
 hipError_t launch_assess(const AssessArgs& a, int pitch, hipStream_t stream);
+// Assess only the states whose a.need byte is set, anywhere in the map.
+hipError_t launch_assess_flagged(const AssessArgs& a, int pitch, hipStream_t stream);
 // Row lengths with a specialised (fully unrolled) inner loop.
 bool has_row_kernel(int row_len);
 hipError_t launch_insert(const InsertArgs& a, hipStream_t stream);

@@ -1,7 +1,7 @@
 // Device code of the per-state assessment (Sec. V-B, Algorithm 1, with the
-// pose of Sec. III, Eq. 1-3), shared by the tiled full-map kernel (heights in
-// LDS) and the list kernel that re-assesses scattered states (heights from
-// global memory).  Both run the same arithmetic in the same order.
+// pose of Sec. III, Eq. 1-3) for the tiled kernel, which serves full maps,
+// rolling-window bands and the surrogate's fallback states alike.  Heights
+// are read through a source type (the LDS tile).
 #pragma once
 
 #include <cmath>
@@ -188,7 +188,7 @@ __device__ Result finish(const AssessArgs& a, const Moments<T>& m, T ref) {
     return r;
 }
 
-// Height sources of a state's footprint samples.  quad() returns the four
+// Height source of a state's footprint samples.  quad() returns the four
 // corners (0,0) (1,0) (0,1) (1,1) of the sample whose corner (0,0) sits at
 // table offset `off` (dy * P + dx) from the state's cell; unknown and
 // out-of-map cells read as SENTINEL.
@@ -202,48 +202,6 @@ struct LdsSource {
         h01 = tp[1];
         h10 = tp[P];
         h11 = tp[P + 1];
-    }
-};
-
-struct GlobalSource {
-    const float* height;
-    int64_t ld;
-    int W, H, rx, ry;   // map size and ring offset
-    int ix, iy;         // the state's cell (logical)
-    int P;              // LDS pitch the table offsets were built for
-    __device__ __forceinline__ float cell(int x, int y) const {
-        if (x < 0 || y < 0 || x >= W || y >= H) return SENTINEL;
-        const float h = height[(int64_t)wrap(y + ry, H) * ld + wrap(x + rx, W)];
-        return fabsf(h) < HEIGHT_LIMIT ? h : SENTINEL;
-    }
-    __device__ __forceinline__ void quad(int off, float& h00, float& h01, float& h10,
-                                         float& h11) const {
-        // off = dy * P + dx with |dx| < P / 2
-        const int dy = (off + P / 2 + 1024 * P) / P - 1024;
-        const int dx = off - dy * P;
-        const int x = ix + dx, y = iy + dy;
-        h00 = cell(x, y);
-        h01 = cell(x + 1, y);
-        h10 = cell(x, y + 1);
-        h11 = cell(x + 1, y + 1);
-    }
-};
-
-// A sentinel-padded copy of the map in global memory: row stride ldp, the
-// state's own cell at `base`; no bounds checks needed within the halo.
-struct PaddedSource {
-    const float* base;
-    int ldp;
-    int P;              // LDS pitch the table offsets were built for
-    __device__ __forceinline__ void quad(int off, float& h00, float& h01, float& h10,
-                                         float& h11) const {
-        const int dy = (off + P / 2 + 1024 * P) / P - 1024;
-        const int dx = off - dy * P;
-        const float* p = base + (int64_t)dy * ldp + dx;
-        h00 = p[0];
-        h01 = p[1];
-        h10 = p[ldp];
-        h11 = p[ldp + 1];
     }
 };
 
@@ -297,18 +255,47 @@ __device__ __forceinline__ void accumulate_rows(const AssessArgs& a, const Src& 
     m.N = m.Sp = m.Sq = m.Spp = m.Spq = m.Sqq = 0;
     const int nrows = a.n_segs;
     int p = 1 - nrows;
+    // Samples go in chunks of four.  A chunk's table entries arrive in two
+    // wide scalar loads, issued together with its eight LDS reads and the
+    // next chunk's table prefetch, so a wave waits once per chunk instead of
+    // once per sample (scalar and LDS loads share one wait counter).
+    constexpr int CH = 4;
+    static_assert(NW % CH == 0, "row length must be a multiple of the chunk");
+    float4 wn[CH];
+    int on[CH];
+#pragma unroll
+    for (int s = 0; s < CH; ++s) { wn[s] = W[s]; on[s] = O[s]; }
     for (int i = 0; i < nrows; ++i, p += 2) {
         float rz = 0.f;
         uint32_t pk = 0u;
 #pragma unroll
-        for (int j = 0; j < NW; ++j) {
-            const float z = sample(src, O[i * NW + j], W[i * NW + j], ref);
-            if (fabsf(z) < VALID_LIMIT) {
-                const int q = 2 * j - kQoff;
-                rz += z;
-                m.Sqz = fmaf((float)q, z, m.Sqz);
-                m.Szz = fmaf(z, z, m.Szz);
-                pk += 1u | ((uint32_t)(2 * j) << 6) | ((uint32_t)(q * q) << kSh2);
+        for (int c = 0; c < NW; c += CH) {
+            float4 w[CH];
+            int o[CH];
+#pragma unroll
+            for (int s = 0; s < CH; ++s) { w[s] = wn[s]; o[s] = on[s]; }
+            float h[CH][4];
+#pragma unroll
+            for (int s = 0; s < CH; ++s) src.quad(o[s], h[s][0], h[s][1], h[s][2], h[s][3]);
+            // prefetch the next chunk's table entries (the last chunk of the
+            // unit re-loads itself, so no read leaves the unit's table)
+            const int nx = min(i * NW + c + CH, nrows * NW - CH);
+#pragma unroll
+            for (int s = 0; s < CH; ++s) { wn[s] = W[nx + s]; on[s] = O[nx + s]; }
+#pragma unroll
+            for (int s = 0; s < CH; ++s) {
+                const int j = c + s;
+                float z = fmaf(w[s].x, h[s][0], -ref);
+                z = fmaf(w[s].y, h[s][1], z);
+                z = fmaf(w[s].z, h[s][2], z);
+                z = fmaf(w[s].w, h[s][3], z);
+                if (fabsf(z) < VALID_LIMIT) {
+                    const int q = 2 * j - kQoff;
+                    rz += z;
+                    m.Sqz = fmaf((float)q, z, m.Sqz);
+                    m.Szz = fmaf(z, z, m.Szz);
+                    pk += 1u | ((uint32_t)(2 * j) << 6) | ((uint32_t)(q * q) << kSh2);
+                }
             }
         }
         add_segment(m, p, pk, kQoff, kMask1, kSh2, rz);

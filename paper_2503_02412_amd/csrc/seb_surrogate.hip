@@ -11,7 +11,8 @@
 //
 // Flagged states -- unknown own cell, too few known cells in the window (out
 // of the training distribution), or predicted risk within `band` of risk_max
-// -- are appended to per-yaw lists and re-assessed by the plain method.
+// -- are marked in a per-state mask; the plain method then re-assesses exactly
+// those, compacted tile by tile (assess_flagged_kernel).
 #include <cmath>
 
 #include "seb.h"
@@ -161,15 +162,12 @@ __global__ __launch_bounds__(256) void fc1_map_kernel(const SurArgs s) {
 // Yaw term of fc1 for the first U yaw bins: Y[u][n] = Wy[n] . (sin, cos)(2 pi u / K).
 __global__ void yaw_kernel(const SurArgs s) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= s.U * net::H1) {
-        if (i < s.K) s.counts[i] = 0;
-        return;
-    }
+    if (i == 0 && s.n_fallback) *s.n_fallback = 0;
+    if (i >= s.U * net::H1) return;
     const int u = i / net::H1, n = i % net::H1;
     const double th = 2.0 * 3.14159265358979323846 * (double)u / (double)s.K;
     const float sn = (float)sin(th), cs = (float)cos(th);
     s.Y[i] = sn * s.theta[net::OFF_WY + 2 * n] + cs * s.theta[net::OFF_WY + 2 * n + 1];
-    if (i < s.K) s.counts[i] = 0;
 }
 
 // Known cells in each cell's 24 x 24 window: row sums, then column sums.
@@ -197,149 +195,112 @@ __global__ void known_cols_kernel(const SurArgs s) {
     s.known[p] = n * (1.f / (net::PATCH * net::PATCH));
 }
 
-// Head per state (cell, yaw unit), 16 states per wave tile:
-// h1 = ReLU(T + Y) -> fc2 (MFMA) -> ReLU -> fc3 (MFMA) -> outputs and flags.
+// Head of every state (cell, yaw unit): a wave owns 16 cells and loops over
+// the yaw units, keeping fc2's weights, its biases and the cells' fc1 values
+// (without the yaw term) in registers.  Both layers are computed transposed,
+// neurons x states:
+//   fc2: D2 (64 x 16) = W4 (64 x 128) . h1^T,   h1 = ReLU(T + Y[u]) in bf16
+//   fc3: D3 (16 x 16, rows 0..3 used) = W5' (16 x 64) . h2^T,  h2 = ReLU(D2 + b4)
+// In the 16x16x32 MFMA, lane (r, g) = (lane % 16, lane / 16) supplies A's row r
+// and B's column r at reduction indices 8g .. 8g+7 and receives D rows
+// 4g .. 4g+3 of column r.  The lane holding D2's rows 16t + 4g + e (t = 0..3)
+// is therefore the lane that supplies fc3's B column r: fc3 takes them as
+// reduction index 32ks + 8g + e' with neuron 32ks + 4g + e' for e' < 4 and
+// 32ks + 16 + 4g + (e' - 4) for e' >= 4, and W5' is gathered in the same
+// order, which leaves the sum unchanged and needs no trip through LDS.  Stores
+// go to 16 consecutive cells of one yaw plane.
 __global__ __launch_bounds__(256) void head_kernel(const SurArgs s, const AssessArgs a) {
-    __shared__ bf16 h2s[4][16][net::H2 + 8];
-    __shared__ float ys[4][16][4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
     const int64_t cells = (int64_t)s.H * s.W;
-    const int64_t states = cells * s.U;
-    const int64_t s0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
-    if (s0 >= states) return;
-    const int r = lane & 15, kq = lane >> 4;
-    const int64_t st = min(s0 + r, states - 1);
-    const int64_t cell = st / s.U;
-    const int u = (int)(st % s.U);
-    f32x4 acc[4];
-    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int ks = 0; ks < net::H1 / 32; ++ks) {
-        const int k = 32 * ks + 8 * kq;
-        const float4* tp = (const float4*)(s.T + cell * net::H1 + k);
-        const float4* yp = (const float4*)(s.Y + u * net::H1 + k);
-        const float4 t0 = tp[0], t1 = tp[1], y0 = yp[0], y1 = yp[1];
-        bf16x8 a;
-        a[0] = to_bf16(fmaxf(t0.x + y0.x, 0.f));
-        a[1] = to_bf16(fmaxf(t0.y + y0.y, 0.f));
-        a[2] = to_bf16(fmaxf(t0.z + y0.z, 0.f));
-        a[3] = to_bf16(fmaxf(t0.w + y0.w, 0.f));
-        a[4] = to_bf16(fmaxf(t1.x + y1.x, 0.f));
-        a[5] = to_bf16(fmaxf(t1.y + y1.y, 0.f));
-        a[6] = to_bf16(fmaxf(t1.z + y1.z, 0.f));
-        a[7] = to_bf16(fmaxf(t1.w + y1.w, 0.f));
-        for (int t = 0; t < 4; ++t) {
-            const bf16x8 b = *(const bf16x8*)(s.pw.w4 + (16 * t + r) * net::H1 + k);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
-        }
+    const int64_t c0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+    if (c0 >= cells) return;
+    const bool real = c0 + r < cells;
+    const int64_t cell = real ? c0 + r : cells - 1;
+
+    bf16x8 w4[4][4];                         // [t][ks]: W4[16t + r][32ks + 8g + e]
+    float b4v[4][4];                         // [t][e]:  b4[16t + 4g + e]
+    float tv[4][8];                          // [ks][e]: T[cell][32ks + 8g + e]
+    bf16x8 w5[2];                            // [ks][e']: W5[r][neuron(ks, g, e')]
+    for (int t = 0; t < 4; ++t) {
+        for (int ks = 0; ks < 4; ++ks)
+            w4[t][ks] = *(const bf16x8*)(s.pw.w4 + (16 * t + r) * net::H1 + 32 * ks + 8 * g);
+        for (int e = 0; e < 4; ++e) b4v[t][e] = s.theta[net::OFF_B4 + 16 * t + 4 * g + e];
     }
-    for (int t = 0; t < 4; ++t)
-        for (int e = 0; e < 4; ++e) {
-            const int n = 16 * t + r;
-            h2s[wave][4 * kq + e][n] = to_bf16(fmaxf(acc[t][e] + s.theta[net::OFF_B4 + n], 0.f));
-        }
-    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): LDS writes of this wave done
-    __builtin_amdgcn_wave_barrier();
-    f32x4 y = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int ks = 0; ks < net::H2 / 32; ++ks) {
-        const int k = 32 * ks + 8 * kq;
-        const bf16x8 av = *(const bf16x8*)(&h2s[wave][r][k]);
-        const bf16x8 b = *(const bf16x8*)(s.pw.w5 + r * net::H2 + k);
-        y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, y, 0, 0, 0);
+    for (int ks = 0; ks < 4; ++ks) {
+        const float4* tp = (const float4*)(s.T + cell * net::H1 + 32 * ks + 8 * g);
+        const float4 t0 = tp[0], t1 = tp[1];
+        tv[ks][0] = t0.x; tv[ks][1] = t0.y; tv[ks][2] = t0.z; tv[ks][3] = t0.w;
+        tv[ks][4] = t1.x; tv[ks][5] = t1.y; tv[ks][6] = t1.z; tv[ks][7] = t1.w;
     }
-    if (r < net::NOUT)
-        for (int e = 0; e < 4; ++e) ys[wave][4 * kq + e][r] = y[e] + s.theta[net::OFF_B5 + r];
-    __builtin_amdgcn_s_waitcnt(0xc07f);
-    __builtin_amdgcn_wave_barrier();
-    if (lane >= 16 || s0 + lane >= states) return;
-    const float* o = ys[wave][lane];
+    for (int ks = 0; ks < 2; ++ks)
+        for (int e = 0; e < 8; ++e) {
+            const int n = 32 * ks + (e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4));
+            w5[ks][e] = s.pw.w5[r * net::H2 + n];   // rows 4..15 of the packed W5 are zero
+        }
+
+    // Per-cell part of the fallback rule and the plane height offset.
     const int cy = (int)(cell / s.W), cx = (int)(cell % s.W);
     float kn;
     const float hc = height_at(s, cy, cx, &kn);
-    const float risk = fminf(fmaxf(o[3], 0.f), 1.f);
-    const bool fallback = !(kn > 0.f) || s.known[cell] < s.min_known ||
-                          fabsf(risk - s.risk_max) < s.band;
-    if (fallback) {
-        const int idx = atomicAdd(&s.counts[u], 1);
-        s.lists[(int64_t)u * cells + idx] = (int)cell;
-        return;
-    }
-    Result res;
-    res.z = hc + net::S_Z * o[0];
-    res.roll = net::S_A * o[1];
-    res.pitch = net::S_A * o[2];
-    res.risk = risk;
-    res.st = SEB_ST_VALID | SEB_ST_SURROGATE | (risk <= s.risk_max ? SEB_ST_TRAV : 0);
-    store(a, u, cell, res, false);
-    if (a.mirror) store(a, u + a.mirror, cell, res, true);
-}
+    const bool out_of_dist = !(kn > 0.f) || s.known[cell] < s.min_known;
 
-// The map with SENTINEL for unknown cells and an R-cell border, so the
-// fallback kernel reads footprint corners without bounds checks.
-__global__ void pad_kernel(const SurArgs s) {
-    const int Wp = s.W + 2 * s.R;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)(s.H + 2 * s.R) * Wp) return;
-    const int y = (int)(i / Wp) - s.R, x = (int)(i % Wp) - s.R;
-    float v = SENTINEL;
-    if (y >= 0 && x >= 0 && y < s.H && x < s.W) {
-        const float h = s.height[(int64_t)y * s.ld + x];
-        if (fabsf(h) < HEIGHT_LIMIT) v = h;
-    }
-    s.pad[i] = v;
-}
-
-// Plain-method re-assessment of the listed states of yaw unit blockIdx.y:
-// the same arithmetic as the tiled kernel, heights from the padded map.
-template <int NW, int FIT>
-__global__ __launch_bounds__(64) void fallback_kernel(const SurArgs s, const AssessArgs a) {
-    const int u = blockIdx.y;
-    const int count = s.counts[u];
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    if (blockIdx.x * 64 >= count) return;
-    const bool active = i < count;
-    const int64_t cells = (int64_t)s.H * s.W;
-    const int cell = active ? s.lists[(int64_t)u * cells + i] : 0;
-    const int ix = cell % s.W, iy = cell / s.W;
-    const int ldp = s.W + 2 * s.R;
-    PaddedSource src;
-    src.base = s.pad + (int64_t)(iy + s.R) * ldp + (ix + s.R);
-    src.ldp = ldp;
-    src.P = s.pitch;
-    const float hc = src.base[0];
-    const Result r = assess_state<NW, FIT>(a, src, u, hc, active);
-    if (active) {
-        store(a, u, cell, r, false);
-        if (a.mirror) store(a, u + a.mirror, cell, r, true);
-    }
-}
-
-__global__ void total_kernel(const SurArgs s, int32_t* out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int n = 0;
-    for (int u = 0; u < s.U; ++u) n += s.counts[u];
-    *out = n * (s.mirror ? 2 : 1);
-}
-
-template <int FIT>
-void launch_fallback(const SurArgs& s, const AssessArgs& a, dim3 fg, hipStream_t stream) {
-    switch (a.row_len) {
-        case 4: hipLaunchKernelGGL((fallback_kernel<4, FIT>), fg, dim3(64), 0, stream, s, a); break;
-        case 12: hipLaunchKernelGGL((fallback_kernel<12, FIT>), fg, dim3(64), 0, stream, s, a); break;
-        case 24: hipLaunchKernelGGL((fallback_kernel<24, FIT>), fg, dim3(64), 0, stream, s, a); break;
-        default: hipLaunchKernelGGL((fallback_kernel<0, FIT>), fg, dim3(64), 0, stream, s, a); break;
+    for (int u = 0; u < s.U; ++u) {
+        f32x4 acc[4];
+        for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < 4; ++ks) {
+            const float4* yp = (const float4*)(s.Y + u * net::H1 + 32 * ks + 8 * g);
+            const float4 y0 = yp[0], y1 = yp[1];
+            bf16x8 h;
+            h[0] = to_bf16(fmaxf(tv[ks][0] + y0.x, 0.f));
+            h[1] = to_bf16(fmaxf(tv[ks][1] + y0.y, 0.f));
+            h[2] = to_bf16(fmaxf(tv[ks][2] + y0.z, 0.f));
+            h[3] = to_bf16(fmaxf(tv[ks][3] + y0.w, 0.f));
+            h[4] = to_bf16(fmaxf(tv[ks][4] + y1.x, 0.f));
+            h[5] = to_bf16(fmaxf(tv[ks][5] + y1.y, 0.f));
+            h[6] = to_bf16(fmaxf(tv[ks][6] + y1.z, 0.f));
+            h[7] = to_bf16(fmaxf(tv[ks][7] + y1.w, 0.f));
+            for (int t = 0; t < 4; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4[t][ks], h, acc[t], 0, 0, 0);
+        }
+        f32x4 y3 = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < 2; ++ks) {
+            bf16x8 h2;
+            for (int e = 0; e < 4; ++e) {
+                h2[e] = to_bf16(fmaxf(acc[2 * ks][e] + b4v[2 * ks][e], 0.f));
+                h2[4 + e] = to_bf16(fmaxf(acc[2 * ks + 1][e] + b4v[2 * ks + 1][e], 0.f));
+            }
+            y3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w5[ks], h2, y3, 0, 0, 0);
+        }
+        // Lanes of group 0 hold the four outputs of state (cell, u).
+        if (g == 0 && real) {
+            const float o0 = y3[0] + s.theta[net::OFF_B5 + 0];
+            const float o1 = y3[1] + s.theta[net::OFF_B5 + 1];
+            const float o2 = y3[2] + s.theta[net::OFF_B5 + 2];
+            const float o3 = y3[3] + s.theta[net::OFF_B5 + 3];
+            const float risk = fminf(fmaxf(o3, 0.f), 1.f);
+            const bool fb = out_of_dist || fabsf(risk - s.risk_max) < s.band;
+            s.need[(int64_t)u * cells + cell] = fb ? 1 : 0;
+            if (!fb) {
+                Result res;
+                res.z = hc + net::S_Z * o0;
+                res.roll = net::S_A * o1;
+                res.pitch = net::S_A * o2;
+                res.risk = risk;
+                res.st = SEB_ST_VALID | SEB_ST_SURROGATE | (risk <= s.risk_max ? SEB_ST_TRAV : 0);
+                store(a, u, cell, res, false);
+                if (a.mirror) store(a, u + a.mirror, cell, res, true);
+            }
+        }
     }
 }
 
 }  // namespace
 
-hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, int32_t* n_fallback,
-                            hipStream_t stream) {
+hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, hipStream_t stream) {
     const int64_t cells = (int64_t)s.H * s.W;
     auto blocks = [](int64_t n, int b) { return (unsigned)((n + b - 1) / b); };
-    hipLaunchKernelGGL(yaw_kernel, dim3(blocks(std::max<int64_t>(s.U * net::H1, s.K), 256)),
-                       dim3(256), 0, stream, s);
-    hipLaunchKernelGGL(pad_kernel, dim3(blocks((int64_t)(s.H + 2 * s.R) * (s.W + 2 * s.R), 256)),
-                       dim3(256), 0, stream, s);
+    hipLaunchKernelGGL(yaw_kernel, dim3(blocks(s.U * net::H1, 256)), dim3(256), 0, stream, s);
     hipLaunchKernelGGL(known_rows_kernel, dim3(blocks(cells, 256)), dim3(256), 0, stream, s);
     hipLaunchKernelGGL(known_cols_kernel, dim3(blocks(cells, 256)), dim3(256), 0, stream, s);
     hipLaunchKernelGGL(conv1_map_kernel, dim3(blocks((int64_t)(s.H + 20) * (s.W + 20), 256)),
@@ -347,13 +308,7 @@ hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, int32_t* n_fa
     hipLaunchKernelGGL(conv2_map_kernel, dim3(blocks((int64_t)(s.H + 16) * (s.W + 16), 64)),
                        dim3(256), 0, stream, s);
     hipLaunchKernelGGL(fc1_map_kernel, dim3(blocks(cells, 64)), dim3(256), 0, stream, s);
-    hipLaunchKernelGGL(head_kernel, dim3(blocks(cells * s.U, 64)), dim3(256), 0, stream, s, a);
-    const dim3 fg(blocks(cells, 64), s.U);
-    if (a.fit == 1)
-        launch_fallback<1>(s, a, fg, stream);
-    else
-        launch_fallback<0>(s, a, fg, stream);
-    if (n_fallback) hipLaunchKernelGGL(total_kernel, dim3(1), dim3(64), 0, stream, s, n_fallback);
+    hipLaunchKernelGGL(head_kernel, dim3(blocks(cells, 64)), dim3(256), 0, stream, s, a);
     return hipGetLastError();
 }
 

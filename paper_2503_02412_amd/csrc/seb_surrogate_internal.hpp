@@ -28,16 +28,16 @@ struct SurArgs {
     float* Y;                    // [U][128]            fc1 yaw term
     float* rows;                 // [H*W]               known cells per 24-cell row run
     float* known;                // [H*W]               known fraction of the 24 x 24 window
-    int32_t* counts;             // [K]                 flagged states per yaw unit
-    int32_t* lists;              // [U][H*W]            flagged cells per yaw unit
-    float* pad;                  // [(H+2R)][(W+2R)]    map with SENTINEL for unknown / outside
-    int R;                       // halo of the padded map (the context's footprint reach)
+    uint8_t* need;               // [U][H*W]            1 = state falls back to the plain method
+    int32_t* n_fallback;         // optional device counter of fallen-back states
     // fallback rule
     float risk_max, band, min_known;
 };
 
-hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, int32_t* n_fallback,
-                            hipStream_t stream);
+// Network part: fills `a`'s outputs for the states it answers and s.need for
+// the others.  The caller then runs the tiled assessment kernel with
+// a.need = s.need over the whole map.
+hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, hipStream_t stream);
 
 }  // namespace sur
 }  // namespace seb
