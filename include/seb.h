@@ -246,9 +246,11 @@ const char* seb_net_last_error(void);
 
 /* Surrogate inference over a whole map with the plain method as fallback.
  * seb_surrogate_create allocates the workspace for ctx's map size (conv maps,
- * per-cell features, per-yaw fallback lists); release with
+ * per-cell features, a one-byte fallback mark per state); release with
  * seb_surrogate_destroy.  The network must have been trained for ctx's
- * configuration (resolution, footprint, yaw bins, constants). */
+ * configuration (resolution, footprint, yaw bins, constants).  Errors:
+ * SEB_ERR_INVALID, SEB_ERR_ALLOC, SEB_ERR_UNSUPPORTED (more than 128 yaw
+ * units, i.e. n_yaw > 256 when even, > 128 when odd). */
 typedef struct seb_surrogate seb_surrogate;
 int seb_surrogate_create(seb_ctx* ctx, seb_surrogate** out);
 void seb_surrogate_destroy(seb_surrogate* s);

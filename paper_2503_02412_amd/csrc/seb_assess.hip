@@ -23,6 +23,8 @@
 // least-squares plane is then a closed-form 2 x 2 solve.
 #include <cmath>
 
+#include <algorithm>
+
 #include "seb.h"
 #include "seb_internal.hpp"
 #include "seb_state_device.hpp"
@@ -90,81 +92,216 @@ void assess_kernel(const AssessArgs a) {
     }
 }
 
-// Re-assessment of the states flagged in a.need only.  The map is cut into
-// TF x TF blocks; a block's flagged cells of one yaw unit form a list in cell
-// order, and workgroup (block, slice, unit) assesses list entries
-// [256 slice, 256 slice + 256): it builds the list (ballot and prefix sum,
-// so every slice sees the same order), returns before staging when its slice
-// is empty, stages the block's heights once and lets each lane assess one
-// listed state.  No lane is spent on an unflagged state, no wave assesses more
-// than one state, and the footprint table stays wave-uniform.  The per-state
-// arithmetic is assess_kernel's, so results are identical.
-template <int P, int NW, int FIT>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FIT == 0 ? 8 : 1)))
-void assess_flagged_kernel(const AssessArgs a, const int TF) {
-    extern __shared__ float tile[];
-    __shared__ int wave_n[BLOCK / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int R = a.R;
-    const int tw = TF + 2 * R;
-    uint16_t* list = (uint16_t*)(tile + tw * P);
-    const int slices = TF * TF / BLOCK;
-    const int blk = blockIdx.x / slices, slice = blockIdx.x - blk * slices;
+// Re-assessment of the states flagged in a.need only, in two kernels.
+//
+// compact_kernel: the map is cut into TF x TF blocks.  A wave per (block,
+// unit) lists the block's flagged cells for that yaw unit in 16 x 4
+// micro-block order (so a full item has the tiled kernel's lane pattern) into
+// the block's own slots, with the count and the bounding box of every 64-cell
+// item.  scan_kernel turns the counts into a dense list of items (prefix sum,
+// no atomics, so the list is the same on every run).
+//
+// flagged_kernel: a fixed grid walks the queue.  For an item, the workgroup
+// stages the block's heights, and each of its four waves accumulates a
+// quarter of the footprint rows for the same 64 states; wave 0 adds the four
+// partial moment sets and finishes the states.  Four short waves per 64
+// states keep many more SIMDs busy than one long wave would, for the few
+// thousand states a map sends back.  A state whose own cell is unknown takes,
+// in each wave, the first valid sample of that wave's rows as reference; the
+// partial sums are shifted exactly onto the first wave's reference (the first
+// valid sample in table order):
+//   S(z - r) = S(z - r_w) + N_w d,  S q(z - r) = S q(z - r_w) + d S q,
+//   S (z - r)^2 = S (z - r_w)^2 + 2 d S(z - r_w) + N_w d^2,  d = r_w - r.
+template <int TF>
+__global__ __launch_bounds__(64) void compact_kernel(const AssessArgs a) {
+    constexpr int mbx = TF / 16;
+    constexpr int steps = TF * TF / 64;      // 16 (TF = 32) or 4 (TF = 16)
+    __shared__ int bb[steps][4];
+    const int lane = threadIdx.x;
+    const int blk = blockIdx.x, u = blockIdx.y;
     const int tiles_x = (a.W + TF - 1) / TF;
+    const int64_t slot = (int64_t)u * gridDim.x + blk;
     const int sx0 = (blk % tiles_x) * TF, sy0 = (blk / tiles_x) * TF;
-    const int u = blockIdx.y;
     const int64_t plane = (int64_t)a.W * a.H;
-
-    // Flagged cells of the block in cell order.
-    int n = 0;
-    for (int i0 = 0; i0 < TF * TF; i0 += BLOCK) {
-        const int i = i0 + tid;
-        const int ly = i / TF, lx = i - ly * TF;
+    // Step k covers micro-block k: ordinal 64 k + lane.  Unrolled, so the
+    // mask bytes of all steps are requested at once.
+    uint32_t flags = 0u;
+#pragma unroll
+    for (int k = 0; k < steps; ++k) {
+        const int ly = (k / mbx) * 4 + (lane >> 4), lx = (k % mbx) * 16 + (lane & 15);
         const int ix = sx0 + lx, iy = sy0 + ly;
         bool f = false;
         if (ix < a.W && iy < a.H) {
             const int64_t c = (int64_t)wrap(iy + a.ry, a.H) * a.W + wrap(ix + a.rx, a.W);
             f = a.need[(int64_t)u * plane + c] != 0;
         }
-        const uint64_t m = __ballot(f);
-        if (lane == 0) wave_n[wave] = __popcll(m);
-        __syncthreads();
-        int before = n;
-        for (int w = 0; w < wave; ++w) before += wave_n[w];
-        if (f) list[before + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)i;
-        for (int w = 0; w < BLOCK / 64; ++w) n += wave_n[w];
-        __syncthreads();
+        if (f) flags |= 1u << k;
     }
-    if (slice == 0 && tid == 0 && a.count && n > 0) atomicAdd(a.count, n * (a.mirror ? 2 : 1));
-    const int first = slice * BLOCK;
-    if (n <= first) return;
-
-    for (int i = tid; i < tw * tw; i += BLOCK) {
-        const int ly = i / tw;
-        const int lx = i - ly * tw;
-        const int gx = sx0 - R + lx, gy = sy0 - R + ly;
-        float v = SENTINEL;
-        if (gx >= 0 && gx < a.W && gy >= 0 && gy < a.H) {
-            const int px = wrap(gx + a.rx, a.W), py = wrap(gy + a.ry, a.H);
-            const float h = a.height[(int64_t)py * a.ld + px];
-            if (fabsf(h) < HEIGHT_LIMIT) v = h;
-        }
-        tile[ly * P + lx] = v;
+    if (lane < steps) {
+        bb[lane][0] = TF;
+        bb[lane][1] = TF;
+        bb[lane][2] = 0;
+        bb[lane][3] = 0;
     }
     __syncthreads();
+    int pos = 0;
+#pragma unroll
+    for (int k = 0; k < steps; ++k) {
+        const bool f = (flags >> k) & 1u;
+        const uint64_t m = __ballot(f);
+        if (f) {
+            const int i = pos + __popcll(m & ((1ull << lane) - 1ull));
+            const int ly = (k / mbx) * 4 + (lane >> 4), lx = (k % mbx) * 16 + (lane & 15);
+            a.work_cells[slot * (TF * TF) + i] = (uint16_t)(ly * TF + lx);
+            atomicMin(&bb[i >> 6][0], lx);
+            atomicMin(&bb[i >> 6][1], ly);
+            atomicMax(&bb[i >> 6][2], lx);
+            atomicMax(&bb[i >> 6][3], ly);
+        }
+        pos += __popcll(m);
+    }
+    __syncthreads();
+    if (lane == 0) a.block_count[slot] = pos;
+    if (lane < (pos + 63) / 64)
+        a.item_box[slot * steps + lane] =
+            bb[lane][0] | (bb[lane][1] << 5) | (bb[lane][2] << 10) | (bb[lane][3] << 15);
+}
 
-    const int i = first + tid;
-    const bool act = i < n;
-    if (!__ballot(act)) return;
-    const int li = list[act ? i : first];
-    const int ly = li / TF, lx = li - ly * TF;
-    const int ix = sx0 + lx, iy = sy0 + ly;
-    const float* tp0 = tile + (ly + R) * P + (lx + R);
-    const int64_t cell = (int64_t)wrap(iy + a.ry, a.H) * a.W + wrap(ix + a.rx, a.W);
-    const Result r = assess_state<NW, FIT>(a, LdsSource<P>{tp0}, u, tp0[0], act);
-    if (act) {
-        store(a, u, cell, r, false);
-        if (a.mirror) store(a, u + a.mirror, cell, r, true);
+// Dense list of work items from the per-(unit, block) counts: one workgroup,
+// each thread takes a contiguous run of slots, then an exclusive scan of the
+// runs' item counts in LDS.
+__global__ __launch_bounds__(1024) void scan_kernel(const AssessArgs a, const int nslots,
+                                                    const int blocks, const int steps) {
+    __shared__ int part[1024];
+    const int tid = threadIdx.x;
+    const int per = (nslots + 1023) / 1024;
+    const int s0 = min(nslots, tid * per), s1 = min(nslots, s0 + per);
+    int items = 0, states = 0;
+    for (int q = s0; q < s1; ++q) {
+        const int n = a.block_count[q];
+        items += (n + 63) / 64;
+        states += n;
+    }
+    part[tid] = items;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {     // inclusive Hillis-Steele scan
+        const int v = tid >= o ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int base = part[tid] - items;
+    for (int q = s0; q < s1; ++q) {
+        const int n = a.block_count[q];
+        for (int k = 0; k * 64 < n; ++k)
+            a.work_items[base++] = make_int4(q % blocks, q / blocks, a.item_box[(int64_t)q * steps + k],
+                                             min(64, n - 64 * k) | (k << 8));
+    }
+    // The last thread's run ends at the item total; the state total is a sum.
+    if (tid == 1023) *a.work_count = base;
+    __syncthreads();
+    part[tid] = states;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if (tid < o) part[tid] += part[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0 && a.count) *a.count = part[0] * (a.mirror ? 2 : 1);
+}
+
+template <int P, int NW, int FIT>
+__global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, const int TF) {
+    extern __shared__ float tile[];
+    __shared__ float part_f[3][5][64];       // waves 1..3: ref, Sz, Spz, Sqz, Szz
+    __shared__ int part_i[3][7][64];         // waves 1..3: has ref, N, Sp, Sq, Spp, Spq, Sqq
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int R = a.R;
+    const int tiles_x = (a.W + TF - 1) / TF;
+    const int nr = a.n_segs;
+    const int g0 = nr * wave / 4, g1 = nr * (wave + 1) / 4;
+    const int total = *a.work_count;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int4 it = a.work_items[t];
+        const int u = it.y;
+        const int bx0 = it.z & 31, by0 = (it.z >> 5) & 31;
+        const int bw = ((it.z >> 10) & 31) - bx0 + 1 + 2 * R;
+        const int bh = ((it.z >> 15) & 31) - by0 + 1 + 2 * R;
+        // Block origin moved to the bounding box of the item's cells.
+        const int sx0 = (it.x % tiles_x) * TF + bx0, sy0 = (it.x / tiles_x) * TF + by0;
+        __syncthreads();                     // previous item's reads of tile / parts done
+        for (int ly = wave; ly < bh; ly += BLOCK / 64) {
+            const int gy = sy0 - R + ly;
+            const bool row_in = gy >= 0 && gy < a.H;
+            const float* hrow = a.height + (int64_t)(row_in ? wrap(gy + a.ry, a.H) : 0) * a.ld;
+            for (int lx = lane; lx < bw; lx += 64) {
+                const int gx = sx0 - R + lx;
+                float v = SENTINEL;
+                if (row_in && gx >= 0 && gx < a.W) {
+                    const float h = hrow[wrap(gx + a.rx, a.W)];
+                    if (fabsf(h) < HEIGHT_LIMIT) v = h;      // false for NaN and +-Inf
+                }
+                tile[ly * P + lx] = v;
+            }
+        }
+        __syncthreads();
+        const bool act = lane < (it.w & 255);
+        // Lanes past the item's count take the box corner (staged, not stored).
+        const int64_t slot = (int64_t)u * ((a.W + TF - 1) / TF) * ((a.H + TF - 1) / TF) + it.x;
+        const int li = act ? a.work_cells[slot * (TF * TF) + 64 * (it.w >> 8) + lane]
+                           : by0 * TF + bx0;
+        const int ly = li / TF - by0, lx = li % TF - bx0;   // relative to the bounding box
+        const float* tp0 = tile + (ly + R) * P + (lx + R);
+        const float hc = tp0[0];
+        float ref = (fabsf(hc) < HEIGHT_LIMIT) ? hc : 0.f;
+        bool need = act && !(fabsf(hc) < HEIGHT_LIMIT);
+        Moments<float> m;
+        partial_moments<NW>(a, LdsSource<P>{tp0}, u, g0, g1, ref, need, m);
+        if (wave > 0) {
+            const int w = wave - 1;
+            part_f[w][0][lane] = ref;
+            part_f[w][1][lane] = m.Sz;
+            part_f[w][2][lane] = m.Spz;
+            part_f[w][3][lane] = m.Sqz;
+            part_f[w][4][lane] = m.Szz;
+            part_i[w][0][lane] = need ? 0 : 1;
+            part_i[w][1][lane] = m.N;
+            part_i[w][2][lane] = m.Sp;
+            part_i[w][3][lane] = m.Sq;
+            part_i[w][4][lane] = m.Spp;
+            part_i[w][5][lane] = m.Spq;
+            part_i[w][6][lane] = m.Sqq;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            bool has = !need;
+            for (int w = 0; w < 3; ++w) {
+                const float rw = part_f[w][0][lane];
+                const int nw = part_i[w][1][lane];
+                if (!has && part_i[w][0][lane]) {
+                    ref = rw;                // no valid sample so far: take this wave's reference
+                    has = true;
+                }
+                const float d = rw - ref;    // 0 whenever the own cell is known
+                const float sz = part_f[w][1][lane];
+                m.Sz += sz + (float)nw * d;
+                m.Spz += part_f[w][2][lane] + d * (float)part_i[w][2][lane];
+                m.Sqz += part_f[w][3][lane] + d * (float)part_i[w][3][lane];
+                m.Szz += part_f[w][4][lane] + 2.f * d * sz + (float)nw * d * d;
+                m.N += nw;
+                m.Sp += part_i[w][2][lane];
+                m.Sq += part_i[w][3][lane];
+                m.Spp += part_i[w][4][lane];
+                m.Spq += part_i[w][5][lane];
+                m.Sqq += part_i[w][6][lane];
+            }
+            const Result r = finish_state<FIT>(a, LdsSource<P>{tp0}, u, m, ref);
+            if (act) {
+                const int ix = sx0 + lx, iy = sy0 + ly;
+                const int64_t cell = (int64_t)wrap(iy + a.ry, a.H) * a.W + wrap(ix + a.rx, a.W);
+                store(a, u, cell, r, false);
+                if (a.mirror) store(a, u + a.mirror, cell, r, true);
+            }
+        }
     }
 }
 
@@ -246,38 +383,58 @@ hipError_t launch_assess(const AssessArgs& a, int pitch, hipStream_t stream) {
 template <int P, int FIT>
 static void launch_flagged_pf(const AssessArgs& a, int tf, dim3 grid, size_t lds, hipStream_t stream) {
     switch (a.row_len) {
-        case 4: hipLaunchKernelGGL((assess_flagged_kernel<P, 4, FIT>), grid, dim3(BLOCK), lds, stream, a, tf); break;
-        case 12: hipLaunchKernelGGL((assess_flagged_kernel<P, 12, FIT>), grid, dim3(BLOCK), lds, stream, a, tf); break;
-        case 24: hipLaunchKernelGGL((assess_flagged_kernel<P, 24, FIT>), grid, dim3(BLOCK), lds, stream, a, tf); break;
-        default: hipLaunchKernelGGL((assess_flagged_kernel<P, 0, FIT>), grid, dim3(BLOCK), lds, stream, a, tf); break;
+        case 4: hipLaunchKernelGGL((flagged_kernel<P, 4, FIT>), grid, dim3(BLOCK), lds, stream, a, tf); break;
+        case 12: hipLaunchKernelGGL((flagged_kernel<P, 12, FIT>), grid, dim3(BLOCK), lds, stream, a, tf); break;
+        case 24: hipLaunchKernelGGL((flagged_kernel<P, 24, FIT>), grid, dim3(BLOCK), lds, stream, a, tf); break;
+        default: hipLaunchKernelGGL((flagged_kernel<P, 0, FIT>), grid, dim3(BLOCK), lds, stream, a, tf); break;
     }
 }
 
 template <int P>
-static hipError_t launch_flagged_p(const AssessArgs& a, int tf, dim3 grid, size_t lds,
-                                   hipStream_t stream) {
+static void launch_flagged_p(const AssessArgs& a, int tf, dim3 grid, size_t lds, hipStream_t stream) {
     if (a.fit == 1)
         launch_flagged_pf<P, 1>(a, tf, grid, lds, stream);
     else
         launch_flagged_pf<P, 0>(a, tf, grid, lds, stream);
-    return hipGetLastError();
 }
 
-int flagged_tile(int R, int pitch) { return (32 + 2 * R <= pitch) ? 32 : 16; }
+static int flagged_tile(int R, int pitch) { return (32 + 2 * R <= pitch) ? 32 : 16; }
+
+int64_t flagged_blocks(int W, int H, int n_units, int R, int pitch) {
+    const int tf = flagged_tile(R, pitch);
+    return (int64_t)((W + tf - 1) / tf) * ((H + tf - 1) / tf) * n_units;
+}
+
+int64_t flagged_work_items(int W, int H, int n_units, int R, int pitch) {
+    const int tf = flagged_tile(R, pitch);
+    const int64_t blocks = (int64_t)((W + tf - 1) / tf) * ((H + tf - 1) / tf);
+    return blocks * n_units * (tf * tf / 64);
+}
 
 hipError_t launch_assess_flagged(const AssessArgs& a, int pitch, hipStream_t stream) {
-    if (!a.need || a.W <= 0 || a.H <= 0 || a.n_units <= 0) return hipErrorInvalidValue;
+    if (!a.need || !a.work_count || !a.work_items || !a.work_cells || !a.block_count ||
+        !a.item_box || a.W <= 0 || a.H <= 0 || a.n_units <= 0)
+        return hipErrorInvalidValue;
+    if (pitch != 48 && pitch != 80 && pitch != 112 && pitch != 144) return hipErrorInvalidValue;
     const int tf = flagged_tile(a.R, pitch);
-    const int tiles = ((a.W + tf - 1) / tf) * ((a.H + tf - 1) / tf);
-    const dim3 grid(tiles * (tf * tf / BLOCK), a.n_units);
-    const size_t lds = (size_t)(tf + 2 * a.R) * pitch * sizeof(float) + (size_t)tf * tf * 2;
+    const int blocks = ((a.W + tf - 1) / tf) * ((a.H + tf - 1) / tf);
+    if (tf == 32)
+        hipLaunchKernelGGL(compact_kernel<32>, dim3(blocks, a.n_units), dim3(64), 0, stream, a);
+    else
+        hipLaunchKernelGGL(compact_kernel<16>, dim3(blocks, a.n_units), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, a, blocks * a.n_units, blocks,
+                       tf * tf / 64);
+    // Enough workgroups to fill the GPU; each walks the queue.
+    const int64_t max_items = flagged_work_items(a.W, a.H, a.n_units, a.R, pitch);
+    const dim3 grid((unsigned)std::min<int64_t>(max_items, 2048));
+    const size_t lds = (size_t)(tf + 2 * a.R) * pitch * sizeof(float);
     switch (pitch) {
-        case 48: return launch_flagged_p<48>(a, tf, grid, lds, stream);
-        case 80: return launch_flagged_p<80>(a, tf, grid, lds, stream);
-        case 112: return launch_flagged_p<112>(a, tf, grid, lds, stream);
-        case 144: return launch_flagged_p<144>(a, tf, grid, lds, stream);
-        default: return hipErrorInvalidValue;
+        case 48: launch_flagged_p<48>(a, tf, grid, lds, stream); break;
+        case 80: launch_flagged_p<80>(a, tf, grid, lds, stream); break;
+        case 112: launch_flagged_p<112>(a, tf, grid, lds, stream); break;
+        default: launch_flagged_p<144>(a, tf, grid, lds, stream); break;
     }
+    return hipGetLastError();
 }
 
 hipError_t launch_insert(const InsertArgs& a, hipStream_t stream) {

@@ -682,6 +682,8 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
     if (!out) return fail(SEB_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (!c) return fail(SEB_ERR_INVALID, "ctx is NULL");
+    if (c->geo.n_units > 128)
+        return fail(SEB_ERR_UNSUPPORTED, "the surrogate supports at most 128 yaw units (256 bins)");
     seb_surrogate* s = new (std::nothrow) seb_surrogate();
     if (!s) return fail(SEB_ERR_ALLOC, "host allocation failed");
     s->ctx = c;
@@ -694,12 +696,18 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
     };
     seb::sur::SurArgs& w = s->ws;
     std::memset(&w, 0, sizeof(w));
+    const int64_t max_items = flagged_work_items((int)W, (int)H, U, c->geo.R, c->pitch);
+    const int64_t n_blocks = flagged_blocks((int)W, (int)H, U, c->geo.R, c->pitch);
     const bool ok =
         al((void**)&w.o1map, (size_t)(H + 20) * (W + 20) * seb::net::C1 * 2) &&
         al((void**)&w.o2map, (size_t)(H + 16) * (W + 16) * seb::net::C2 * 2) &&
         al((void**)&w.T, (size_t)cells * seb::net::H1 * 4) &&
-        al((void**)&w.Y, (size_t)U * seb::net::H1 * 4) && al((void**)&w.rows, (size_t)cells * 4) &&
-        al((void**)&w.known, (size_t)cells * 4) && al((void**)&w.need, (size_t)U * cells);
+        al((void**)&w.Y, (size_t)U * seb::net::H1 * 4) && al((void**)&w.known, (size_t)cells * 4) && al((void**)&w.need, (size_t)U * cells) &&
+        al((void**)&w.work_count, sizeof(int32_t)) &&
+        al((void**)&w.work_items, (size_t)max_items * sizeof(int4)) &&
+        al((void**)&w.work_cells, (size_t)max_items * 64 * 2) &&
+        al((void**)&w.block_count, (size_t)n_blocks * sizeof(int32_t)) &&
+        al((void**)&w.item_box, (size_t)max_items * sizeof(int32_t));
     if (!ok) {
         seb_surrogate_destroy(s);
         return fail(SEB_ERR_ALLOC, "device allocation failed");
@@ -753,6 +761,11 @@ int seb_surrogate_infer(seb_surrogate* s, const seb_net* net, const float* heigh
     // The plain method for the flagged states, compacted tile by tile.
     a.need = w.need;
     a.count = n_fallback_dev;
+    a.work_count = w.work_count;
+    a.work_items = w.work_items;
+    a.work_cells = w.work_cells;
+    a.block_count = w.block_count;
+    a.item_box = w.item_box;
     e = launch_assess_flagged(a, s->ctx->pitch, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fallback assessment launch");
     return SEB_OK;

@@ -83,8 +83,15 @@ struct AssessArgs {
     int32_t fit;                 // 0 least-squares plane, 1 principal-component plane
     const uint8_t* need;         // [n_units][H][W] (ring cells) for the flagged-state
                                  // kernel: assess the states whose byte is nonzero
-    int32_t* count;              // optional: the flagged-state kernel adds the number of
-                                 // states it assessed (both mirror bins)
+    int32_t* count;              // optional: receives the number of states the
+                                 // flagged-state kernels assess (both mirror bins)
+    // workspace of the flagged-state kernels (caller-owned, sized by
+    // flagged_work_items; see launch_assess_flagged)
+    int32_t* work_count;         // number of work items
+    int4* work_items;            // (block, yaw unit, bounding box, entries | item << 8)
+    uint16_t* work_cells;        // per (unit, block): its flagged cells, block-local
+    int32_t* block_count;        // per (unit, block): number of flagged cells
+    int32_t* item_box;           // per (unit, block, item): bounding box of the item's cells
     // state rectangles (logical coordinates) and their tile decomposition
     int32_t n_rects;
     int32_t rect[MAX_RECTS][4];
@@ -106,8 +113,12 @@ struct InsertArgs {
 
 // Launchers (seb_assess.hip).  Return hipSuccess or the launch error.
 hipError_t launch_assess(const AssessArgs& a, int pitch, hipStream_t stream);
-// Assess only the states whose a.need byte is set, anywhere in the map.
+// Assess only the states whose a.need byte is set, anywhere in the map.  The
+// workspace holds flagged_work_items(...) items, 64 cells per item, one count
+// per (unit, block) and one box per item.
 hipError_t launch_assess_flagged(const AssessArgs& a, int pitch, hipStream_t stream);
+int64_t flagged_work_items(int W, int H, int n_units, int R, int pitch);
+int64_t flagged_blocks(int W, int H, int n_units, int R, int pitch);   // units x blocks
 // Row lengths with a specialised (fully unrolled) inner loop.
 bool has_row_kernel(int row_len);
 hipError_t launch_insert(const InsertArgs& a, hipStream_t stream);

@@ -24,10 +24,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bf16 to_bf16(float f) {
-    // round to nearest even (inputs are finite)
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return __builtin_bit_cast(bf16, (uint16_t)(u >> 16));
+    return (bf16)f;   // round to nearest even (v_cvt_pk_bf16_f32)
 }
 __device__ __forceinline__ float from_bf16(bf16 h) {
     return __uint_as_float((uint32_t)__builtin_bit_cast(uint16_t, h) << 16);

@@ -243,10 +243,15 @@ constexpr int bits_for(int v) {
 // FP32 moments of one yaw bin when every segment is a full row of NW samples:
 // the row loop is unrolled, so q and the packed integer constants of each
 // sample are literals and only the weights and offsets are loaded.
-template <int NW, class Src>
+// SEARCH: some lanes have no reference height yet (need); such a lane takes
+// the raw value of its first valid sample in table order as its reference
+// (that sample then counts as z = 0), which is exactly the value a separate
+// search in table order would find, since no earlier sample contributes.
+template <int NW, bool SEARCH, class Src>
 __device__ __forceinline__ void accumulate_rows(const AssessArgs& a, const Src& src,
-                                                cptr<float4> W, cptr<int32_t> O, float ref,
-                                                Moments<float>& m) {
+                                                cptr<float4> W, cptr<int32_t> O, float& ref,
+                                                bool& need, Moments<float>& m, int row0,
+                                                int row1) {
     constexpr int kQoff = NW - 1;
     constexpr int kSh2 = 6 + bits_for(NW * 2 * kQoff);
     constexpr uint32_t kMask1 = (1u << (kSh2 - 6)) - 1u;
@@ -254,7 +259,7 @@ __device__ __forceinline__ void accumulate_rows(const AssessArgs& a, const Src& 
     m.Sz = m.Spz = m.Sqz = m.Szz = 0.f;
     m.N = m.Sp = m.Sq = m.Spp = m.Spq = m.Sqq = 0;
     const int nrows = a.n_segs;
-    int p = 1 - nrows;
+    int p = 1 - nrows + 2 * row0;
     // Samples go in chunks of four.  A chunk's table entries arrive in two
     // wide scalar loads, issued together with its eight LDS reads and the
     // next chunk's table prefetch, so a wave waits once per chunk instead of
@@ -264,8 +269,8 @@ __device__ __forceinline__ void accumulate_rows(const AssessArgs& a, const Src& 
     float4 wn[CH];
     int on[CH];
 #pragma unroll
-    for (int s = 0; s < CH; ++s) { wn[s] = W[s]; on[s] = O[s]; }
-    for (int i = 0; i < nrows; ++i, p += 2) {
+    for (int s = 0; s < CH; ++s) { wn[s] = W[row0 * NW + s]; on[s] = O[row0 * NW + s]; }
+    for (int i = row0; i < row1; ++i, p += 2) {
         float rz = 0.f;
         uint32_t pk = 0u;
 #pragma unroll
@@ -279,7 +284,7 @@ __device__ __forceinline__ void accumulate_rows(const AssessArgs& a, const Src& 
             for (int s = 0; s < CH; ++s) src.quad(o[s], h[s][0], h[s][1], h[s][2], h[s][3]);
             // prefetch the next chunk's table entries (the last chunk of the
             // unit re-loads itself, so no read leaves the unit's table)
-            const int nx = min(i * NW + c + CH, nrows * NW - CH);
+            const int nx = min(i * NW + c + CH, row1 * NW - CH);
 #pragma unroll
             for (int s = 0; s < CH; ++s) { wn[s] = W[nx + s]; on[s] = O[nx + s]; }
 #pragma unroll
@@ -290,6 +295,13 @@ __device__ __forceinline__ void accumulate_rows(const AssessArgs& a, const Src& 
                 z = fmaf(w[s].z, h[s][2], z);
                 z = fmaf(w[s].w, h[s][3], z);
                 if (fabsf(z) < VALID_LIMIT) {
+                    if constexpr (SEARCH) {
+                        if (need) {
+                            ref = z;
+                            z = 0.f;
+                            need = false;
+                        }
+                    }
                     const int q = 2 * j - kQoff;
                     rz += z;
                     m.Sqz = fmaf((float)q, z, m.Sqz);
@@ -303,22 +315,30 @@ __device__ __forceinline__ void accumulate_rows(const AssessArgs& a, const Src& 
 }
 
 // FP32 moments of one yaw bin, any footprint (segments of any length).
-template <class Src>
+template <bool SEARCH, class Src>
 __device__ __forceinline__ void accumulate_segments(const AssessArgs& a, const Src& src,
-                                                    cptr<float4> W, cptr<int32_t> O, float ref,
-                                                    Moments<float>& m) {
+                                                    cptr<float4> W, cptr<int32_t> O, float& ref,
+                                                    bool& need, Moments<float>& m, int seg0,
+                                                    int seg1) {
     m.Sz = m.Spz = m.Sqz = m.Szz = 0.f;
     m.N = m.Sp = m.Sq = m.Spp = m.Spq = m.Sqq = 0;
     const cptr<Segment> segs = as_const(a.segs);
     const cptr<float> qs = as_const(a.qs);
     const cptr<uint32_t> pks = as_const(a.pks);
-    for (int g = 0; g < a.n_segs; ++g) {
+    for (int g = seg0; g < seg1; ++g) {
         const Segment sg = segs[g];
         float rz = 0.f;
         uint32_t pk = 0u;
         for (int s = sg.first; s < sg.first + sg.count; ++s) {
-            const float z = sample(src, O[s], W[s], ref);
+            float z = sample(src, O[s], W[s], ref);
             if (fabsf(z) < VALID_LIMIT) {
+                if constexpr (SEARCH) {
+                    if (need) {
+                        ref = z;
+                        z = 0.f;
+                        need = false;
+                    }
+                }
                 rz += z;
                 m.Sqz = fmaf(qs[s], z, m.Sqz);
                 m.Szz = fmaf(z, z, m.Szz);
@@ -375,51 +395,62 @@ __device__ __forceinline__ void store(const AssessArgs& a, int k, int64_t cell, 
     a.status[o] = r.st;
 }
 
+// Result of a state from its FP32 moments; with precision 1, near-degenerate
+// states are recomputed from FP64 moments about the same reference.
+template <int FIT, class Src>
+__device__ __forceinline__ Result finish_state(const AssessArgs& a, const Src& src, int u,
+                                               const Moments<float>& m, float ref) {
+    Result r = finish<FIT>(a, m, ref);
+    if (a.precision == 1) {
+        const bool redo = (r.st & SEB_ST_DEGEN) != 0;
+        if (__ballot(redo) && redo) {
+            const int64_t ub = (int64_t)u * a.n_samples;
+            Moments<double> md;
+            accumulate64(a, src, as_const(a.offs) + ub, as_const(a.frac) + ub, (double)ref, md);
+            r = finish<FIT>(a, md, (double)ref);
+        }
+    }
+    return r;
+}
+
+// FP32 moments of rows (segments) [g0, g1) of yaw unit u.  On entry ref is
+// the own cell's height, or 0 with need set when that cell is unknown; a lane
+// with need adopts its first valid sample in table order (see accumulate_rows).
+template <int NW, class Src>
+__device__ __forceinline__ void partial_moments(const AssessArgs& a, const Src& src, int u, int g0,
+                                                int g1, float& ref, bool& need,
+                                                Moments<float>& m) {
+    const int64_t ub = (int64_t)u * a.n_samples;
+    const cptr<float4> W = as_const(a.wts) + ub;
+    const cptr<int32_t> O = as_const(a.offs) + ub;
+    if (__ballot(need)) {
+        if constexpr (NW > 0)
+            accumulate_rows<NW, true>(a, src, W, O, ref, need, m, g0, g1);
+        else
+            accumulate_segments<true>(a, src, W, O, ref, need, m, g0, g1);
+    } else {
+        if constexpr (NW > 0)
+            accumulate_rows<NW, false>(a, src, W, O, ref, need, m, g0, g1);
+        else
+            accumulate_segments<false>(a, src, W, O, ref, need, m, g0, g1);
+    }
+}
+
 // Reference height, moments, optional FP64 redo and result of one state for
 // yaw unit u.  hc = the state's own cell (SENTINEL if unknown); `active`
 // lanes take part in the reference search.
 template <int NW, int FIT, class Src>
 __device__ __forceinline__ Result assess_state(const AssessArgs& a, const Src& src, int u, float hc,
                                                bool active) {
-    const int64_t ub = (int64_t)u * a.n_samples;
-    const cptr<float4> W = as_const(a.wts) + ub;
-    const cptr<int32_t> O = as_const(a.offs) + ub;
-
-    // Reference height: own cell, else the first valid sample in table order.
-    // A state with no valid sample keeps ref = 0, so every sample stays invalid.
+    // Reference height: own cell, else the first valid sample in table order
+    // (adopted inside the sample loop).  A state with no valid sample keeps
+    // ref = 0, and every sample stays invalid.
     float ref = (fabsf(hc) < HEIGHT_LIMIT) ? hc : 0.f;
     bool need = active && !(fabsf(hc) < HEIGHT_LIMIT);
-    if (__ballot(need)) {
-        for (int s = 0; s < a.n_samples; ++s) {
-            if (!__ballot(need)) break;
-            const float4 w = W[s];
-            const int off = O[s];
-            if (need) {
-                const float h = sample(src, off, w, 0.f);
-                if (fabsf(h) < VALID_LIMIT) {
-                    ref = h;
-                    need = false;
-                }
-            }
-        }
-    }
 
     Moments<float> m;
-    if constexpr (NW > 0)
-        accumulate_rows<NW>(a, src, W, O, ref, m);
-    else
-        accumulate_segments(a, src, W, O, ref, m);
-    Result r = finish<FIT>(a, m, ref);
-
-    if (a.precision == 1) {
-        const bool redo = (r.st & SEB_ST_DEGEN) != 0;
-        if (__ballot(redo) && redo) {
-            Moments<double> md;
-            accumulate64(a, src, O, as_const(a.frac) + ub, (double)ref, md);
-            r = finish<FIT>(a, md, (double)ref);
-        }
-    }
-    return r;
+    partial_moments<NW>(a, src, u, 0, a.n_segs, ref, need, m);
+    return finish_state<FIT>(a, src, u, m, ref);
 }
 
 }  // namespace dev

@@ -31,9 +31,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bf16 to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return __builtin_bit_cast(bf16, (uint16_t)(u >> 16));
+    return (bf16)f;   // round to nearest even (v_cvt_pk_bf16_f32)
 }
 __device__ __forceinline__ float from_bf16(bf16 h) {
     return __uint_as_float((uint32_t)__builtin_bit_cast(uint16_t, h) << 16);
@@ -159,40 +157,51 @@ __global__ __launch_bounds__(256) void fc1_map_kernel(const SurArgs s) {
             }
 }
 
-// Yaw term of fc1 for the first U yaw bins: Y[u][n] = Wy[n] . (sin, cos)(2 pi u / K).
-__global__ void yaw_kernel(const SurArgs s) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0 && s.n_fallback) *s.n_fallback = 0;
-    if (i >= s.U * net::H1) return;
-    const int u = i / net::H1, n = i % net::H1;
-    const double th = 2.0 * 3.14159265358979323846 * (double)u / (double)s.K;
-    const float sn = (float)sin(th), cs = (float)cos(th);
-    s.Y[i] = sn * s.theta[net::OFF_WY + 2 * n] + cs * s.theta[net::OFF_WY + 2 * n + 1];
-}
-
-// Known cells in each cell's 24 x 24 window: row sums, then column sums.
-__global__ void known_rows_kernel(const SurArgs s) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (int64_t)s.H * s.W) return;
-    const int y = (int)(p / s.W), x = (int)(p % s.W);
-    float n = 0.f, v;
-    for (int dx = -net::HALF; dx < net::HALF; ++dx) {
-        height_at(s, y, x + dx, &v);
-        n += v;
+// Per-map preparation in one launch.  Workgroup (bx, by) computes, for its
+// 16 x 16 cells, the known fraction of each cell's 24 x 24 window
+// [c - 12, c + 12) from an LDS tile of known flags (row sums, then column
+// sums).  Workgroup (0, 0) also writes fc1's yaw term for the first U yaw
+// bins, Y[u][n] = Wy[n] . (sin, cos)(2 pi u / K), and clears the fallback
+// counters.
+__global__ __launch_bounds__(256) void prep_kernel(const SurArgs s) {
+    constexpr int T = 16, SPAN = T + net::PATCH - 1;     // 39 rows / columns of flags
+    __shared__ float kf[SPAN][SPAN + 1];
+    __shared__ float rs[SPAN][T + 1];
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+        if (tid == 0) {
+            *s.work_count = 0;
+            if (s.n_fallback) *s.n_fallback = 0;
+        }
+        for (int i = tid; i < s.U * net::H1; i += 256) {
+            const int u = i / net::H1, n = i % net::H1;
+            const double th = 2.0 * 3.14159265358979323846 * (double)u / (double)s.K;
+            const float sn = (float)sin(th), cs = (float)cos(th);
+            s.Y[i] = sn * s.theta[net::OFF_WY + 2 * n] + cs * s.theta[net::OFF_WY + 2 * n + 1];
+        }
     }
-    s.rows[p] = n;
-}
-
-__global__ void known_cols_kernel(const SurArgs s) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (int64_t)s.H * s.W) return;
-    const int y = (int)(p / s.W), x = (int)(p % s.W);
-    float n = 0.f;
-    for (int dy = -net::HALF; dy < net::HALF; ++dy) {
-        const int yy = y + dy;
-        if (yy >= 0 && yy < s.H) n += s.rows[(int64_t)yy * s.W + x];
+    for (int i = tid; i < SPAN * SPAN; i += 256) {
+        const int r = i / SPAN, c = i % SPAN;
+        float v;
+        height_at(s, y0 - net::HALF + r, x0 - net::HALF + c, &v);
+        kf[r][c] = v;
     }
-    s.known[p] = n * (1.f / (net::PATCH * net::PATCH));
+    __syncthreads();
+    for (int i = tid; i < SPAN * T; i += 256) {
+        const int r = i / T, c = i % T;
+        float n = 0.f;
+        for (int d = 0; d < net::PATCH; ++d) n += kf[r][c + d];
+        rs[r][c] = n;
+    }
+    __syncthreads();
+    const int c = tid % T, r = tid / T;
+    const int x = x0 + c, y = y0 + r;
+    if (x < s.W && y < s.H) {
+        float n = 0.f;
+        for (int d = 0; d < net::PATCH; ++d) n += rs[r + d][c];
+        s.known[(int64_t)y * s.W + x] = n * (1.f / (net::PATCH * net::PATCH));
+    }
 }
 
 // Head of every state (cell, yaw unit): a wave owns 16 cells and loops over
@@ -210,6 +219,9 @@ __global__ void known_cols_kernel(const SurArgs s) {
 // order, which leaves the sum unchanged and needs no trip through LDS.  Stores
 // go to 16 consecutive cells of one yaw plane.
 __global__ __launch_bounds__(256) void head_kernel(const SurArgs s, const AssessArgs a) {
+    extern __shared__ float ys[];            // [U][128] yaw term, shared by the workgroup
+    for (int i = threadIdx.x; i < s.U * net::H1; i += 256) ys[i] = s.Y[i];
+    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
     const int64_t cells = (int64_t)s.H * s.W;
@@ -249,7 +261,7 @@ __global__ __launch_bounds__(256) void head_kernel(const SurArgs s, const Assess
         f32x4 acc[4];
         for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
         for (int ks = 0; ks < 4; ++ks) {
-            const float4* yp = (const float4*)(s.Y + u * net::H1 + 32 * ks + 8 * g);
+            const float4* yp = (const float4*)(ys + u * net::H1 + 32 * ks + 8 * g);
             const float4 y0 = yp[0], y1 = yp[1];
             bf16x8 h;
             h[0] = to_bf16(fmaxf(tv[ks][0] + y0.x, 0.f));
@@ -300,15 +312,14 @@ __global__ __launch_bounds__(256) void head_kernel(const SurArgs s, const Assess
 hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, hipStream_t stream) {
     const int64_t cells = (int64_t)s.H * s.W;
     auto blocks = [](int64_t n, int b) { return (unsigned)((n + b - 1) / b); };
-    hipLaunchKernelGGL(yaw_kernel, dim3(blocks(s.U * net::H1, 256)), dim3(256), 0, stream, s);
-    hipLaunchKernelGGL(known_rows_kernel, dim3(blocks(cells, 256)), dim3(256), 0, stream, s);
-    hipLaunchKernelGGL(known_cols_kernel, dim3(blocks(cells, 256)), dim3(256), 0, stream, s);
+    hipLaunchKernelGGL(prep_kernel, dim3((s.W + 15) / 16, (s.H + 15) / 16), dim3(256), 0, stream, s);
     hipLaunchKernelGGL(conv1_map_kernel, dim3(blocks((int64_t)(s.H + 20) * (s.W + 20), 256)),
                        dim3(256), 0, stream, s);
     hipLaunchKernelGGL(conv2_map_kernel, dim3(blocks((int64_t)(s.H + 16) * (s.W + 16), 64)),
                        dim3(256), 0, stream, s);
     hipLaunchKernelGGL(fc1_map_kernel, dim3(blocks(cells, 64)), dim3(256), 0, stream, s);
-    hipLaunchKernelGGL(head_kernel, dim3(blocks(cells, 64)), dim3(256), 0, stream, s, a);
+    hipLaunchKernelGGL(head_kernel, dim3(blocks(cells, 64)), dim3(256),
+                       (size_t)s.U * net::H1 * sizeof(float), stream, s, a);
     return hipGetLastError();
 }
 

@@ -26,10 +26,14 @@ struct SurArgs {
     net::bf16* o2map;            // [(H+16)(W+16)][32]  conv2 at positions -12 .. H+3
     float* T;                    // [H*W][128]          fc1 without the yaw term
     float* Y;                    // [U][128]            fc1 yaw term
-    float* rows;                 // [H*W]               known cells per 24-cell row run
     float* known;                // [H*W]               known fraction of the 24 x 24 window
     uint8_t* need;               // [U][H*W]            1 = state falls back to the plain method
     int32_t* n_fallback;         // optional device counter of fallen-back states
+    int32_t* work_count;         // fallback work queue (see AssessArgs)
+    int4* work_items;
+    uint16_t* work_cells;
+    int32_t* block_count;
+    int32_t* item_box;
     // fallback rule
     float risk_max, band, min_known;
 };
