@@ -212,8 +212,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(const AssessArgs a, const in
 template <int P, int NW, int FIT>
 __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, const int TF) {
     extern __shared__ float tile[];
-    __shared__ float part_f[3][5][64];       // waves 1..3: ref, Sz, Spz, Sqz, Szz
-    __shared__ int part_i[3][7][64];         // waves 1..3: has ref, N, Sp, Sq, Spp, Spq, Sqq
+    __shared__ Parts parts;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int R = a.R;
     const int tiles_x = (a.W + TF - 1) / TF;
@@ -256,44 +255,10 @@ __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, cons
         bool need = act && !(fabsf(hc) < HEIGHT_LIMIT);
         Moments<float> m;
         partial_moments<NW>(a, LdsSource<P>{tp0}, u, g0, g1, ref, need, m);
-        if (wave > 0) {
-            const int w = wave - 1;
-            part_f[w][0][lane] = ref;
-            part_f[w][1][lane] = m.Sz;
-            part_f[w][2][lane] = m.Spz;
-            part_f[w][3][lane] = m.Sqz;
-            part_f[w][4][lane] = m.Szz;
-            part_i[w][0][lane] = need ? 0 : 1;
-            part_i[w][1][lane] = m.N;
-            part_i[w][2][lane] = m.Sp;
-            part_i[w][3][lane] = m.Sq;
-            part_i[w][4][lane] = m.Spp;
-            part_i[w][5][lane] = m.Spq;
-            part_i[w][6][lane] = m.Sqq;
-        }
+        if (wave > 0) put_part(parts, wave, lane, m, ref, need);
         __syncthreads();
         if (wave == 0) {
-            bool has = !need;
-            for (int w = 0; w < 3; ++w) {
-                const float rw = part_f[w][0][lane];
-                const int nw = part_i[w][1][lane];
-                if (!has && part_i[w][0][lane]) {
-                    ref = rw;                // no valid sample so far: take this wave's reference
-                    has = true;
-                }
-                const float d = rw - ref;    // 0 whenever the own cell is known
-                const float sz = part_f[w][1][lane];
-                m.Sz += sz + (float)nw * d;
-                m.Spz += part_f[w][2][lane] + d * (float)part_i[w][2][lane];
-                m.Sqz += part_f[w][3][lane] + d * (float)part_i[w][3][lane];
-                m.Szz += part_f[w][4][lane] + 2.f * d * sz + (float)nw * d * d;
-                m.N += nw;
-                m.Sp += part_i[w][2][lane];
-                m.Sq += part_i[w][3][lane];
-                m.Spp += part_i[w][4][lane];
-                m.Spq += part_i[w][5][lane];
-                m.Sqq += part_i[w][6][lane];
-            }
+            merge_parts(parts, 1, 3, lane, m, ref, need);
             const Result r = finish_state<FIT>(a, LdsSource<P>{tp0}, u, m, ref);
             if (act) {
                 const int ix = sx0 + lx, iy = sy0 + ly;

@@ -240,14 +240,64 @@ constexpr int bits_for(int v) {
     return b;
 }
 
-// FP32 moments of one yaw bin when every segment is a full row of NW samples:
-// the row loop is unrolled, so q and the packed integer constants of each
-// sample are literals and only the weights and offsets are loaded.
-// SEARCH: some lanes have no reference height yet (need); such a lane takes
-// the raw value of its first valid sample in table order as its reference
-// (that sample then counts as z = 0), which is exactly the value a separate
-// search in table order would find, since no earlier sample contributes.
+// One footprint row of NW samples (see accumulate_rows).  SEARCH: some lanes
+// have no reference height yet (need); such a lane takes the raw value of
+// its first valid sample in table order as its reference (that sample then
+// counts as z = 0), which is exactly the value a separate search in table
+// order would find, since no earlier sample contributes.
 template <int NW, bool SEARCH, class Src>
+__device__ __forceinline__ void accumulate_row(const Src& src, cptr<float4> W, cptr<int32_t> O,
+                                               int i, int row1, float4 (&wn)[4], int (&on)[4],
+                                               float& ref, bool& need, float& rz, uint32_t& pk,
+                                               Moments<float>& m) {
+    constexpr int kQoff = NW - 1;
+    constexpr int kSh2 = 6 + bits_for(NW * 2 * kQoff);
+    constexpr int CH = 4;
+#pragma unroll
+    for (int c = 0; c < NW; c += CH) {
+        float4 w[CH];
+        int o[CH];
+#pragma unroll
+        for (int s = 0; s < CH; ++s) { w[s] = wn[s]; o[s] = on[s]; }
+        float h[CH][4];
+#pragma unroll
+        for (int s = 0; s < CH; ++s) src.quad(o[s], h[s][0], h[s][1], h[s][2], h[s][3]);
+        // prefetch the next chunk's table entries (the last chunk of the
+        // range re-loads itself, so no read leaves the unit's table)
+        const int nx = min(i * NW + c + CH, row1 * NW - CH);
+#pragma unroll
+        for (int s = 0; s < CH; ++s) { wn[s] = W[nx + s]; on[s] = O[nx + s]; }
+#pragma unroll
+        for (int s = 0; s < CH; ++s) {
+            const int j = c + s;
+            float z = fmaf(w[s].x, h[s][0], -ref);
+            z = fmaf(w[s].y, h[s][1], z);
+            z = fmaf(w[s].z, h[s][2], z);
+            z = fmaf(w[s].w, h[s][3], z);
+            if (fabsf(z) < VALID_LIMIT) {
+                if constexpr (SEARCH) {
+                    if (need) {
+                        ref = z;
+                        z = 0.f;
+                        need = false;
+                    }
+                }
+                const int q = 2 * j - kQoff;
+                rz += z;
+                m.Sqz = fmaf((float)q, z, m.Sqz);
+                m.Szz = fmaf(z, z, m.Szz);
+                pk += 1u | ((uint32_t)(2 * j) << 6) | ((uint32_t)(q * q) << kSh2);
+            }
+        }
+    }
+}
+
+// FP32 moments of rows [row0, row1) of one yaw bin when every segment is a
+// full row of NW samples: the row loop is unrolled, so q and the packed
+// integer constants of each sample are compile-time values.  A row runs the
+// reference-adopting body only while some lane of the wave still lacks a
+// reference height (normally the first row or two).
+template <int NW, class Src>
 __device__ __forceinline__ void accumulate_rows(const AssessArgs& a, const Src& src,
                                                 cptr<float4> W, cptr<int32_t> O, float& ref,
                                                 bool& need, Moments<float>& m, int row0,
@@ -270,46 +320,17 @@ __device__ __forceinline__ void accumulate_rows(const AssessArgs& a, const Src& 
     int on[CH];
 #pragma unroll
     for (int s = 0; s < CH; ++s) { wn[s] = W[row0 * NW + s]; on[s] = O[row0 * NW + s]; }
-    for (int i = row0; i < row1; ++i, p += 2) {
+    int i = row0;
+    for (; i < row1 && __ballot(need); ++i, p += 2) {
         float rz = 0.f;
         uint32_t pk = 0u;
-#pragma unroll
-        for (int c = 0; c < NW; c += CH) {
-            float4 w[CH];
-            int o[CH];
-#pragma unroll
-            for (int s = 0; s < CH; ++s) { w[s] = wn[s]; o[s] = on[s]; }
-            float h[CH][4];
-#pragma unroll
-            for (int s = 0; s < CH; ++s) src.quad(o[s], h[s][0], h[s][1], h[s][2], h[s][3]);
-            // prefetch the next chunk's table entries (the last chunk of the
-            // unit re-loads itself, so no read leaves the unit's table)
-            const int nx = min(i * NW + c + CH, row1 * NW - CH);
-#pragma unroll
-            for (int s = 0; s < CH; ++s) { wn[s] = W[nx + s]; on[s] = O[nx + s]; }
-#pragma unroll
-            for (int s = 0; s < CH; ++s) {
-                const int j = c + s;
-                float z = fmaf(w[s].x, h[s][0], -ref);
-                z = fmaf(w[s].y, h[s][1], z);
-                z = fmaf(w[s].z, h[s][2], z);
-                z = fmaf(w[s].w, h[s][3], z);
-                if (fabsf(z) < VALID_LIMIT) {
-                    if constexpr (SEARCH) {
-                        if (need) {
-                            ref = z;
-                            z = 0.f;
-                            need = false;
-                        }
-                    }
-                    const int q = 2 * j - kQoff;
-                    rz += z;
-                    m.Sqz = fmaf((float)q, z, m.Sqz);
-                    m.Szz = fmaf(z, z, m.Szz);
-                    pk += 1u | ((uint32_t)(2 * j) << 6) | ((uint32_t)(q * q) << kSh2);
-                }
-            }
-        }
+        accumulate_row<NW, true>(src, W, O, i, row1, wn, on, ref, need, rz, pk, m);
+        add_segment(m, p, pk, kQoff, kMask1, kSh2, rz);
+    }
+    for (; i < row1; ++i, p += 2) {
+        float rz = 0.f;
+        uint32_t pk = 0u;
+        accumulate_row<NW, false>(src, W, O, i, row1, wn, on, ref, need, rz, pk, m);
         add_segment(m, p, pk, kQoff, kMask1, kSh2, rz);
     }
 }
@@ -423,16 +444,68 @@ __device__ __forceinline__ void partial_moments(const AssessArgs& a, const Src& 
     const int64_t ub = (int64_t)u * a.n_samples;
     const cptr<float4> W = as_const(a.wts) + ub;
     const cptr<int32_t> O = as_const(a.offs) + ub;
-    if (__ballot(need)) {
-        if constexpr (NW > 0)
-            accumulate_rows<NW, true>(a, src, W, O, ref, need, m, g0, g1);
-        else
-            accumulate_segments<true>(a, src, W, O, ref, need, m, g0, g1);
+    if constexpr (NW > 0) {
+        accumulate_rows<NW>(a, src, W, O, ref, need, m, g0, g1);
     } else {
-        if constexpr (NW > 0)
-            accumulate_rows<NW, false>(a, src, W, O, ref, need, m, g0, g1);
+        if (__ballot(need))
+            accumulate_segments<true>(a, src, W, O, ref, need, m, g0, g1);
         else
             accumulate_segments<false>(a, src, W, O, ref, need, m, g0, g1);
+    }
+}
+
+// Partial moments of the waves that share a state's footprint rows, kept in
+// LDS per wave and lane.
+struct Parts {
+    float f[BLOCK / 64][5][64];   // reference, Sz, Spz, Sqz, Szz
+    int i[BLOCK / 64][7][64];     // reference found, N, Sp, Sq, Spp, Spq, Sqq
+};
+
+__device__ __forceinline__ void put_part(Parts& pt, int wave, int lane, const Moments<float>& m,
+                                         float ref, bool need) {
+    pt.f[wave][0][lane] = ref;
+    pt.f[wave][1][lane] = m.Sz;
+    pt.f[wave][2][lane] = m.Spz;
+    pt.f[wave][3][lane] = m.Sqz;
+    pt.f[wave][4][lane] = m.Szz;
+    pt.i[wave][0][lane] = need ? 0 : 1;
+    pt.i[wave][1][lane] = m.N;
+    pt.i[wave][2][lane] = m.Sp;
+    pt.i[wave][3][lane] = m.Sq;
+    pt.i[wave][4][lane] = m.Spp;
+    pt.i[wave][5][lane] = m.Spq;
+    pt.i[wave][6][lane] = m.Sqq;
+}
+
+// Adds the partial moments of waves w0 .. w0 + n - 1 (the rows that follow
+// in table order) to m.  A state whose own cell is unknown has, per wave, the
+// first valid sample of that wave's rows as reference; the sums are shifted
+// exactly onto the first reference found in table order:
+//   S(z - r) = S(z - r_w) + N_w d,  S q(z - r) = S q(z - r_w) + d S q,
+//   S (z - r)^2 = S (z - r_w)^2 + 2 d S(z - r_w) + N_w d^2,  d = r_w - r.
+// d is 0 whenever the own cell is known (every wave then uses its height).
+__device__ __forceinline__ void merge_parts(const Parts& pt, int w0, int n, int lane,
+                                            Moments<float>& m, float& ref, bool& need) {
+    for (int k = 0; k < n; ++k) {
+        const int w = w0 + k;
+        const float rw = pt.f[w][0][lane];
+        const int nw = pt.i[w][1][lane];
+        if (need && pt.i[w][0][lane]) {
+            ref = rw;                    // no valid sample so far: take this wave's reference
+            need = false;
+        }
+        const float d = rw - ref;
+        const float sz = pt.f[w][1][lane];
+        m.Sz += sz + (float)nw * d;
+        m.Spz += pt.f[w][2][lane] + d * (float)pt.i[w][2][lane];
+        m.Sqz += pt.f[w][3][lane] + d * (float)pt.i[w][3][lane];
+        m.Szz += pt.f[w][4][lane] + 2.f * d * sz + (float)nw * d * d;
+        m.N += nw;
+        m.Sp += pt.i[w][2][lane];
+        m.Sq += pt.i[w][3][lane];
+        m.Spp += pt.i[w][4][lane];
+        m.Spq += pt.i[w][5][lane];
+        m.Sqq += pt.i[w][6][lane];
     }
 }
 

@@ -78,3 +78,23 @@ def prefill(out: dict, zval: float = 12345.0):
         out[k].fill_(zval)
     out["status"].fill_(255)
     return out
+
+
+def error_table(gpu: dict, orc, params, tol: float = 1e-4) -> dict:
+    """Max and mean |GPU - oracle| per output, over all valid states and over
+    the near-degenerate ones.  Risk leaves out states whose oracle curvature
+    or tilt lies within tol of its threshold (risk jumps to 1 there)."""
+    so = np.asarray(orc.status).astype(np.int64)
+    vo = (so & VALID) > 0
+    near = vo & ((np.abs(orc.phi_x - params.phi_x_max) <= tol) |
+                 (np.abs(orc.phi_y - params.phi_y_max) <= tol) |
+                 (np.abs(orc.kappa / params.kappa_max - 1.0) <= tol))
+    out = {}
+    for subset, m in (("valid", vo), ("near-degenerate", vo & ((so & DEGEN) > 0))):
+        row = {"states": int(m.sum())}
+        for f in ("z", "roll", "pitch", "risk"):
+            mm = m & ~near if f == "risk" else m
+            d = np.abs(np.asarray(gpu[f])[mm].astype(np.float64) - getattr(orc, f)[mm])
+            row[f] = (float(d.max(initial=0.0)), float(d.mean()) if d.size else 0.0)
+        out[subset] = row
+    return out
