@@ -77,6 +77,7 @@ void assess_kernel(const AssessArgs a) {
     const int ly = (tid >> 6) * 4 + (lane >> 4);
     const int ix = sx0 + lx, iy = sy0 + ly;
     const bool active = ix < sx1 && iy < sy1;
+    if (!__ballot(active)) return;                 // wave entirely past the rectangle's edge
     const float* tp0 = tile + (ly + R) * P + (lx + R);
     const float hc = tp0[0];
     const int64_t cell = (int64_t)wrap(iy + a.ry, a.H) * a.W + wrap(ix + a.rx, a.W);
