@@ -299,6 +299,11 @@ void base_args(const seb_ctx* c, AssessArgs* a) {
     a->sh2 = c->geo.sh2;
     a->hu = (float)(0.5 * g.fp_length / g.fp_nl);
     a->hv = (float)(0.5 * g.fp_width / g.fp_nw);
+    a->inv_hu = (float)(2.0 * g.fp_nl / g.fp_length);
+    a->inv_hv = (float)(2.0 * g.fp_nw / g.fp_width);
+    a->c_kappa = (float)(g.w_kappa / g.kappa_max);
+    a->c_phi_x = (float)(g.w_phi_x / g.phi_x_max);
+    a->c_phi_y = (float)(g.w_phi_y / g.phi_y_max);
     a->rho16 = c->geo.rho_full / 16.0;
     a->n_total = (int)c->geo.samples.size();
     a->kappa_max = (float)g.kappa_max;

@@ -75,9 +75,11 @@ struct AssessArgs {
     uint32_t mask1;
     int32_t sh2;
     float hu, hv;                // metres per unit of p and of q
+    float inv_hu, inv_hv;        // 1 / hu, 1 / hv
     double rho16;                // near-degenerate threshold (rho of full footprint / 16)
     int32_t n_total;             // samples in the full footprint
     float kappa_max, phi_x_max, phi_y_max, w_kappa, w_phi_x, w_phi_y, risk_max;
+    float c_kappa, c_phi_x, c_phi_y;   // w_kappa / kappa_max, w_phi_x / phi_x_max, w_phi_y / phi_y_max
     int32_t min_valid;
     int32_t precision;
     int32_t fit;                 // 0 least-squares plane, 1 principal-component plane

@@ -55,8 +55,7 @@ __device__ __forceinline__ float weigh_risk(const AssessArgs& a, float kappa, fl
         risk = 1.f;
         st |= SEB_ST_TILT;
     } else {
-        risk = a.w_kappa * kappa / a.kappa_max + a.w_phi_x * phx / a.phi_x_max +
-               a.w_phi_y * phy / a.phi_y_max;
+        risk = a.c_kappa * kappa + a.c_phi_x * phx + a.c_phi_y * phy;
     }
     if (risk <= a.risk_max) st |= SEB_ST_TRAV;
     return risk;
@@ -121,6 +120,10 @@ __device__ inline PcaPlane pca_plane(double suu, double svv, double szz, double 
     return pl;
 }
 
+// 1 / x: the hardware reciprocal (within 1 ulp) in FP32, exact division in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // Plane from the moments, then Eq. 1-3 and Algorithm 1.  u = hu p, v = hv q
 // are the body-frame sample coordinates.  fit 0: least-squares plane
 // z = a + b u + c v; fit 1: principal-component plane.
@@ -142,7 +145,7 @@ __device__ Result finish(const AssessArgs& a, const Moments<T>& m, T ref) {
     const double de = (double)(D + E);
     if (2 * N < a.n_total || (4.0 * (double)det) / (de * de) < a.rho16) st |= SEB_ST_DEGEN;
 
-    const T invN = T(1) / T(N);
+    const T invN = recip(T(N));
     const T zb = m.Sz * invN;
     const T pz = m.Spz - T(m.Sp) * zb;      // sum (p - pbar)(z - zbar)
     const T qz = m.Sqz - T(m.Sq) * zb;
@@ -165,16 +168,23 @@ __device__ Result finish(const AssessArgs& a, const Moments<T>& m, T ref) {
         r.st = st;
         return r;
     }
-    const T tdet = T(det);
-    const T bp = T(N) * (T(E) * pz - T(F) * qz) / tdet;   // dz/dp
-    const T bq = T(N) * (T(D) * qz - T(F) * pz) / tdet;   // dz/dq
-    const T b = bp / T(a.hu), c = bq / T(a.hv);           // dz/du, dz/dv
+    const T ndet = T(N) * recip(T(det));
+    const T bp = (T(E) * pz - T(F) * qz) * ndet;          // dz/dp
+    const T bq = (T(D) * qz - T(F) * pz) * ndet;          // dz/dq
+    T b, c;                                               // dz/du, dz/dv
+    if constexpr (sizeof(T) == 4) {
+        b = bp * a.inv_hu;
+        c = bq * a.inv_hv;
+    } else {
+        b = bp / T(a.hu);
+        c = bq / T(a.hv);
+    }
     const T zc = ref + zb - bp * (T(m.Sp) * invN) - bq * (T(m.Sq) * invN);
     T sse = zz - bp * pz - bq * qz;
     if (sse < T(0)) sse = T(0);
     const T s2 = T(1) + b * b + c * c;
     const T tr = T(a.hu) * T(a.hu) * T(D) * invN + T(a.hv) * T(a.hv) * T(E) * invN + zz;
-    const float kappa = (tr > T(0)) ? (float)(sse / (s2 * tr)) : 0.f;
+    const float kappa = (tr > T(0)) ? (float)(sse * recip(s2 * tr)) : 0.f;
 
     const float bf = (float)b, cf = (float)c;
     const float c1 = 1.f + cf * cf;
