@@ -102,7 +102,7 @@ void assess_kernel(const AssessArgs a) {
 // item.  scan_kernel turns the counts into a dense list of items (prefix sum,
 // no atomics, so the list is the same on every run).
 //
-// flagged_kernel: a fixed grid walks the queue.  For an item, the workgroup
+// flagged_kernel: one workgroup per item.  For its item, the workgroup
 // stages the block's heights, and each of its four waves accumulates a
 // quarter of the footprint rows for the same 64 states; wave 0 adds the four
 // partial moment sets and finishes the states.  Four short waves per 64
@@ -219,8 +219,9 @@ __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, cons
     const int tiles_x = (a.W + TF - 1) / TF;
     const int nr = a.n_segs;
     const int g0 = nr * wave / 4, g1 = nr * (wave + 1) / 4;
-    const int total = *a.work_count;
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    {
+        const int t = blockIdx.x;            // one item per workgroup
+        if (t >= *a.work_count) return;
         const int4 it = a.work_items[t];
         const int u = it.y;
         const int bx0 = it.z & 31, by0 = (it.z >> 5) & 31;
@@ -228,7 +229,6 @@ __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, cons
         const int bh = ((it.z >> 15) & 31) - by0 + 1 + 2 * R;
         // Block origin moved to the bounding box of the item's cells.
         const int sx0 = (it.x % tiles_x) * TF + bx0, sy0 = (it.x / tiles_x) * TF + by0;
-        __syncthreads();                     // previous item's reads of tile / parts done
         for (int ly = wave; ly < bh; ly += BLOCK / 64) {
             const int gy = sy0 - R + ly;
             const bool row_in = gy >= 0 && gy < a.H;
@@ -390,9 +390,9 @@ hipError_t launch_assess_flagged(const AssessArgs& a, int pitch, hipStream_t str
         hipLaunchKernelGGL(compact_kernel<16>, dim3(blocks, a.n_units), dim3(64), 0, stream, a);
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, a, blocks * a.n_units, blocks,
                        tf * tf / 64);
-    // Enough workgroups to fill the GPU; each walks the queue.
+    // One workgroup per possible item; those past the list's length return.
     const int64_t max_items = flagged_work_items(a.W, a.H, a.n_units, a.R, pitch);
-    const dim3 grid((unsigned)std::min<int64_t>(max_items, 2048));
+    const dim3 grid((unsigned)max_items);
     const size_t lds = (size_t)(tf + 2 * a.R) * pitch * sizeof(float);
     switch (pitch) {
         case 48: launch_flagged_p<48>(a, tf, grid, lds, stream); break;

@@ -88,3 +88,33 @@ def test_forced_fallback_matches_plain_kernel(orc):
     # obstacle / traversable bits: identical but at a threshold
     assert np.count_nonzero(a["status"] != b["status"]) <= 1e-4 * p.n_states
 
+
+
+@pytest.mark.parametrize("case", ["large_footprint", "odd_yaws"])
+def test_forced_fallback_other_geometries(orc, case):
+    """Forced fallback where the fallback kernels take other paths: the
+    2.0 x 1.2 m footprint on 40 x 24 samples (halo 25 cells, so 16 x 16 cell
+    blocks and 24-sample rows) on a ragged map, and an odd yaw count (no
+    mirrored bins)."""
+    import torch
+    if case == "large_footprint":
+        p = I.CONFIG5.with_(width=90, height=77)
+        h = I.config5_map(5)[300:377, 300:390].copy()
+    else:
+        p = I.CONFIG1.with_(n_yaw=15, width=50, height=45)
+        h = I.config1_map(3)[:45, :50].copy()
+    net = seb.Net(seed=7, max_batch=256)
+    with seb.Context(p) as ctx:
+        sur = seb.Surrogate(ctx)
+        dh = torch.from_numpy(h).cuda()
+        nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+        a = to_numpy(sur.infer(net, dh, band=10.0, min_known=0.0, n_fallback=nf))
+        b = to_numpy(ctx.assess(dh))
+        torch.cuda.synchronize()
+        assert int(nf.item()) == p.n_states
+    print(compare(a, orc.assess_rect(p, h), p))
+    assert np.array_equal(a["status"] & 9, b["status"] & 9)
+    v = (b["status"] & 1) > 0
+    for f in ("z", "roll", "pitch", "risk"):
+        assert np.array_equal(np.isnan(a[f]), np.isnan(b[f])), f
+        assert np.abs(a[f][v].astype(np.float64) - b[f][v]).max(initial=0.0) <= 2e-5, f
