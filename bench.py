@@ -144,6 +144,37 @@ def bench_large(torch, seb):
             "frac_of_vendor_fp32": f / (ms * 1e-3) / 1e12 / VENDOR_FP32_PEAK_TFLOPS}
 
 
+def bench_sdf(torch, seb, n_poses: int = 1 << 20):
+    """The planner-side fields on the assessed maps: the SE(2) signed distance
+    field (2 m cap) of the 200 x 200 x 36 and 800 x 800 x 72 maps, and the
+    trilinear SDF + risk query at 2^20 random poses."""
+    res = {}
+    for name, p, hmap, cap in (("config2", I.CONFIG2, I.config2_map(2), 20),
+                               ("config5", I.CONFIG5, I.config5_map(5), 40)):
+        ctx = seb.Context(p)
+        out = ctx.assess(torch.from_numpy(hmap).cuda())
+        sdf = torch.empty_like(out["risk"])
+        ms = time_launches(torch, lambda: ctx.sdf(out["status"], cap, True, out=sdf), 50, 5)
+        poses = torch.from_numpy(I.query_poses(n_poses, p.width, p.height, p.resolution,
+                                               seed=11)).cuda()
+        q = torch.empty((n_poses, 8), dtype=torch.float32, device="cuda")
+        qms = time_launches(torch, lambda: ctx.query(poses, sdf=sdf, risk=out["risk"], out=q),
+                            50, 5)
+        obst = ((out["status"] & 6) != 0) | ((out["status"] & 1) == 0)
+        res[name] = {
+            "workload": f"{p.width}x{p.height} @{p.resolution} m, {p.n_yaw} yaw bins, "
+                        f"cap {cap} cells; {n_poses} query poses",
+            "obstacle_fraction": float(obst.float().mean()),
+            "sdf_ms": ms, "sdf_states_per_s": p.n_states / (ms * 1e-3),
+            # algorithmic bytes: one status byte in, one float out per state
+            "sdf_gbps": 5 * p.n_states / (ms * 1e-3) / 1e9,
+            "query_ms": qms, "query_poses_per_s": n_poses / (qms * 1e-3),
+            # algorithmic bytes per pose: 12 in, 32 out (corner reads hit the caches)
+            "query_gbps": 44 * n_poses / (qms * 1e-3) / 1e9,
+        }
+    return res
+
+
 def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4):
     """Train the surrogate on plain-kernel labels, then time inference with the
     plain fallback on 200x200x36 evaluation maps against the plain kernel, and
@@ -290,6 +321,7 @@ def main():
         result["rolling"] = bench_rolling(torch, seb)
         result["large_map"] = bench_large(torch, seb)
         result["surrogate"] = bench_surrogate(torch, seb)
+        result["sdf_query"] = bench_sdf(torch, seb)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(p, hmap)
     # The paper's only timing for this path, for context (not comparable: it

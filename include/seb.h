@@ -268,6 +268,47 @@ int seb_surrogate_infer(seb_surrogate* s, const seb_net* net, const float* heigh
                         const seb_out* out, float band, float min_known, int32_t* n_fallback_dev,
                         void* stream);
 
+/* ------------------------------------------- planner-side fields */
+
+/* Signed distance field over the SE(2) states (Sec. V, and the safety
+ * constraint of the trajectory optimisation, Sec. VI-B): for every state, the
+ * distance in metres from its cell centre to the edge of the nearest obstacle
+ * region within its own yaw plane, negative for states inside an obstacle.
+ * Obstacle states are those with SEB_ST_CURV or SEB_ST_TILT set (Algorithm 1's
+ * explicit obstacles), plus, when unknown_is_obstacle != 0, UNKNOWN states
+ * (SEB_ST_VALID clear).  With d the Euclidean distance between cell centres
+ * (in cells) to the nearest obstacle state (for a free state) or nearest free
+ * state (for an obstacle state), and C = cap_cells,
+ *     sdf = +(min(d, C) - 0.5) res   (free),   -(min(d, C) - 0.5) res   (obstacle);
+ * a plane with no obstacle (or no free) state gives the capped value.  Cells
+ * outside the map are neither.
+ * status / sdf: device [K][H][W] of ctx's map, both in ring storage: logical
+ * cell (x, y) at position ((x + ring_x) mod W, (y + ring_y) mod H), so the
+ * arrays of a rolling window can be passed as they are (ring_x = ring_y = 0
+ * for a plain map).  Errors (host-side, nothing launched): SEB_ERR_INVALID
+ * (NULL array, ring offset outside [0, W) x [0, H), cap_cells < 1),
+ * SEB_ERR_UNSUPPORTED (cap_cells > 64).  Enqueues one kernel; allocates
+ * nothing. */
+int seb_sdf_se2(seb_ctx* ctx, const uint8_t* status, int32_t ring_x, int32_t ring_y,
+                int32_t cap_cells, int32_t unknown_is_obstacle, float* sdf, void* stream);
+
+/* Trilinear interpolation of the SDF and of the risk at arbitrary poses, with
+ * the yaw axis on SO(2) (Sec. VI-B/VI-C: the planner reads both fields and
+ * their gradients along the trajectory).  poses: device [n][3] float32
+ * (x, y, theta) in logical map metres, the corner of cell (0, 0) at the
+ * origin (cell (i, j)'s centre at ((i + 0.5) res, (j + 0.5) res)), yaw bin k
+ * at theta = 2 pi k / K.  out: device [n][8] float32 = (sdf, dsdf/dx,
+ * dsdf/dy, dsdf/dtheta, risk, drisk/dx, drisk/dy, drisk/dtheta).  A position
+ * outside the cell centres' range is clamped onto it (the derivative along a
+ * clamped axis is 0); theta wraps; derivatives are those of the trilinear
+ * cell [floor, floor + 1] that holds the pose.  NaN coordinates read as the
+ * clamped lower edge and yaw bin 0.  sdf and risk: device [K][H][W] in the
+ * ring storage of seb_sdf_se2; either may be NULL (its four outputs are then
+ * 0), not both.  n == 0 is a no-op.  Errors: SEB_ERR_INVALID.  Allocates
+ * nothing. */
+int seb_query_se2(seb_ctx* ctx, const float* sdf, const float* risk, int32_t ring_x, int32_t ring_y,
+                  const float* poses, int64_t n, float* out, void* stream);
+
 /* --------------------------------------------------------------- misc */
 
 const char* seb_strerror(int status);

@@ -73,6 +73,24 @@ def sdf_plane(obst: np.ndarray, res: float, cap: int) -> np.ndarray:
     return out.reshape(H, W)
 
 
+def sdf_cells(obst: np.ndarray, res: float, cap: int, ys, xs) -> np.ndarray:
+    """Signed distance of the listed cells (ys[i], xs[i]) of one [H][W] plane,
+    each by brute force over every cell of the plane (for sampled checks of
+    large maps)."""
+    H, W = obst.shape
+    gy, gx = np.mgrid[0:H, 0:W]
+    out = np.empty(len(ys))
+    for n, (y, x) in enumerate(zip(ys, xs)):
+        inside = bool(obst[y, x])
+        tgt = ~obst if inside else obst
+        if not tgt.any():
+            d = float(cap)
+        else:
+            d = min(math.sqrt(float(np.min((gx[tgt] - x) ** 2 + (gy[tgt] - y) ** 2))), float(cap))
+        out[n] = (-1.0 if inside else 1.0) * (d - 0.5) * res
+    return out
+
+
 def sdf_planes(status: np.ndarray, res: float, cap: int, unknown_is_obstacle: bool = True):
     """SDF of every yaw plane of status [K][H][W] (logical layout)."""
     obst = obstacle_mask(status, unknown_is_obstacle)

@@ -14,6 +14,7 @@
 #include "seb.h"
 #include "seb_internal.hpp"
 #include "seb_net_internal.hpp"
+#include "seb_sdf_internal.hpp"
 #include "seb_surrogate_internal.hpp"
 
 using namespace seb;
@@ -773,6 +774,38 @@ int seb_surrogate_infer(seb_surrogate* s, const seb_net* net, const float* heigh
     a.item_box = w.item_box;
     e = launch_assess_flagged(a, s->ctx->pitch, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fallback assessment launch");
+    return SEB_OK;
+}
+
+int seb_sdf_se2(seb_ctx* c, const uint8_t* status, int32_t ring_x, int32_t ring_y,
+                int32_t cap_cells, int32_t unknown_is_obstacle, float* sdf, void* stream) {
+    if (!c || !status || !sdf) return fail(SEB_ERR_INVALID, "ctx, status and sdf must be non-NULL");
+    const seb_config& g = c->cfg;
+    if (ring_x < 0 || ring_x >= g.width || ring_y < 0 || ring_y >= g.height)
+        return fail(SEB_ERR_INVALID, "ring offset outside the map");
+    if (cap_cells < 1) return fail(SEB_ERR_INVALID, "cap_cells must be >= 1");
+    if (cap_cells > sdf_max_cap())
+        return fail(SEB_ERR_UNSUPPORTED, "cap_cells above " + std::to_string(sdf_max_cap()));
+    hipError_t e = launch_sdf(status, sdf, g.width, g.height, g.n_yaw, ring_x, ring_y, cap_cells,
+                              (float)g.resolution, unknown_is_obstacle != 0, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "sdf launch");
+    return SEB_OK;
+}
+
+int seb_query_se2(seb_ctx* c, const float* sdf, const float* risk, int32_t ring_x, int32_t ring_y,
+                  const float* poses, int64_t n, float* out, void* stream) {
+    if (!c) return fail(SEB_ERR_INVALID, "ctx is NULL");
+    if (n < 0) return fail(SEB_ERR_INVALID, "n must be >= 0");
+    if (!sdf && !risk) return fail(SEB_ERR_INVALID, "sdf and risk are both NULL");
+    const seb_config& g = c->cfg;
+    if (ring_x < 0 || ring_x >= g.width || ring_y < 0 || ring_y >= g.height)
+        return fail(SEB_ERR_INVALID, "ring offset outside the map");
+    if (n == 0) return SEB_OK;
+    if (!poses || !out) return fail(SEB_ERR_INVALID, "poses and out must be non-NULL");
+    if (n > (int64_t(1) << 40)) return fail(SEB_ERR_INVALID, "n too large");
+    hipError_t e = launch_query(sdf, risk, poses, out, n, g.width, g.height, g.n_yaw, ring_x,
+                                ring_y, g.resolution, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "query launch");
     return SEB_OK;
 }
 

@@ -301,3 +301,80 @@ def surrogate_samples(n_maps: int, size: int, n_yaw: int, seed: int, count: int 
     perm = _rng(seed).permutation(len(s))
     s = s[perm]
     return s if count is None else s[:count]
+
+
+# --------------------------------------------------------------------------
+# Planner-side fields: status bytes and query poses.  The status bits are those
+# of the library's output (1 valid, 2 curvature obstacle, 4 tilt obstacle,
+# 8 near-degenerate, 16 traversable, 32 surrogate); here they are drawn as
+# shapes, not computed from terrain.
+# --------------------------------------------------------------------------
+
+
+def synthetic_status(width: int, height: int, n_yaw: int, seed: int, *,
+                     n_obstacles: int | None = None, n_unknown: int | None = None,
+                     max_radius: int = 9) -> np.ndarray:
+    """uint8 [K][H][W] status planes: elliptical obstacle blobs whose extent
+    changes with the yaw bin (obstacles of a yawed footprint grow along the
+    body's long axis), elliptical unknown patches shared by every yaw bin, and
+    random near-degenerate / traversable / surrogate bits elsewhere."""
+    rng = _rng(seed)
+    area = width * height
+    n_obstacles = max(1, area // 700) if n_obstacles is None else n_obstacles
+    n_unknown = max(1, area // 2500) if n_unknown is None else n_unknown
+
+    def blobs(n):
+        return (rng.uniform(0, width, n), rng.uniform(0, height, n),
+                rng.uniform(0.5, max_radius, n), rng.uniform(0.5, max_radius, n),
+                rng.uniform(0, math.pi, n))
+
+    unknown = np.zeros((height, width), dtype=bool)
+    for cx, cy, ra, rb, ang in zip(*blobs(n_unknown)):
+        e = _ellipse(unknown.shape, cx, cy, ra, rb, ang)
+        if e is not None:
+            unknown[e[0]] |= e[1]
+    ox, oy, oa, ob, oang = blobs(n_obstacles)
+    kind = rng.integers(0, 3, n_obstacles)              # curvature, tilt or both
+    extra = rng.integers(0, 64, (n_yaw, height, width)).astype(np.uint8) & (8 | 16 | 32)
+    out = np.empty((n_yaw, height, width), dtype=np.uint8)
+    for k in range(n_yaw):
+        th = 2.0 * math.pi * k / n_yaw
+        bits = np.zeros((height, width), dtype=np.uint8)
+        for i in range(n_obstacles):
+            grow = 1.0 + 0.5 * abs(math.cos(th - oang[i]))
+            e = _ellipse(bits.shape, ox[i], oy[i], oa[i] * grow, ob[i], th)
+            if e is not None:
+                bits[e[0]] |= np.where(e[1], (2, 4, 6)[kind[i]], 0).astype(np.uint8)
+        plane = np.where(bits != 0, 1 | bits, 1 | extra[k]).astype(np.uint8)
+        plane[bits != 0] |= extra[k][bits != 0] & 8
+        plane[unknown] = extra[k][unknown] & 8
+        out[k] = plane
+    return out
+
+
+def _ellipse(shape, cx: float, cy: float, ra: float, rb: float, ang: float):
+    """(window slices, boolean mask over the window) of the cells whose centres
+    lie in the rotated ellipse, or None if the window is empty."""
+    height, width = shape
+    r = int(math.ceil(max(ra, rb))) + 1
+    x0, x1 = max(0, int(cx) - r), min(width, int(cx) + r + 1)
+    y0, y1 = max(0, int(cy) - r), min(height, int(cy) + r + 1)
+    if x0 >= x1 or y0 >= y1:
+        return None
+    ys, xs = np.mgrid[y0:y1, x0:x1]
+    dx, dy = xs + 0.5 - cx, ys + 0.5 - cy
+    c, s = math.cos(ang), math.sin(ang)
+    u, v = dx * c + dy * s, -dx * s + dy * c
+    return (slice(y0, y1), slice(x0, x1)), (u / ra) ** 2 + (v / rb) ** 2 <= 1.0
+
+
+def query_poses(n: int, width: int, height: int, res: float, seed: int,
+                margin_cells: float = 3.0) -> np.ndarray:
+    """float32 [n][3] poses (x, y, theta): positions uniform over the map plus a
+    margin on every side (so some fall outside and are clamped), yaw uniform
+    over several turns either way."""
+    rng = _rng(seed)
+    x = rng.uniform(-margin_cells * res, (width + margin_cells) * res, n)
+    y = rng.uniform(-margin_cells * res, (height + margin_cells) * res, n)
+    th = rng.uniform(-6.0 * math.pi, 6.0 * math.pi, n)
+    return np.stack([x, y, th], 1).astype(np.float32)

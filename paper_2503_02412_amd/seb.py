@@ -72,6 +72,10 @@ _SIGS = {
                                        C.c_double, C.POINTER(WindowPlan)]),
     "seb_update_window": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
                                     C.POINTER(C.c_int64)]),
+    "seb_sdf_se2": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                              C.c_void_p, C.c_void_p]),
+    "seb_query_se2": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "seb_strerror": (C.c_char_p, [C.c_int]),
     "seb_last_error": (C.c_char_p, []),
     "seb_version": (C.c_char_p, []),
@@ -197,6 +201,47 @@ class Context:
         _check(lib().seb_assess_se2(self._h, C.c_void_p(height.data_ptr()), height.stride(0),
                                     x0, y0, nx, ny, C.byref(o), _stream_handle(stream)),
                "seb_assess_se2")
+        return out
+
+    def _field(self, t, name, dtype):
+        import torch
+        p = self.params
+        if (t is None or not t.is_cuda or t.dtype != dtype or not t.is_contiguous()
+                or tuple(t.shape) != (p.n_yaw, p.height, p.width)):
+            raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor [K, H, W]")
+        return C.c_void_p(t.data_ptr())
+
+    def sdf(self, status, cap_cells: int, unknown_is_obstacle: bool = True, ring=(0, 0),
+            out=None, stream=None):
+        """seb_sdf_se2: signed distance field [K, H, W] (float32, metres) of `status`."""
+        import torch
+        st = self._field(status, "status", torch.uint8)
+        if out is None:
+            out = torch.empty(tuple(status.shape), dtype=torch.float32, device=status.device)
+        o = self._field(out, "out", torch.float32)
+        _check(lib().seb_sdf_se2(self._h, st, int(ring[0]), int(ring[1]), int(cap_cells),
+                                 int(bool(unknown_is_obstacle)), o, _stream_handle(stream)),
+               "seb_sdf_se2")
+        return out
+
+    def query(self, poses, sdf=None, risk=None, ring=(0, 0), out=None, stream=None):
+        """seb_query_se2: [n, 8] = (sdf, d/dx, d/dy, d/dtheta, risk, d/dx, d/dy, d/dtheta)
+        at poses [n, 3] = (x, y, theta) (float32, logical map metres)."""
+        import torch
+        if not (poses.is_cuda and poses.dtype == torch.float32 and poses.is_contiguous()
+                and poses.dim() == 2 and poses.shape[1] == 3):
+            raise ValueError("poses must be a contiguous float32 CUDA tensor [n, 3]")
+        fa = None if sdf is None else self._field(sdf, "sdf", torch.float32)
+        fb = None if risk is None else self._field(risk, "risk", torch.float32)
+        n = poses.shape[0]
+        if out is None:
+            out = torch.empty((n, 8), dtype=torch.float32, device=poses.device)
+        if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+                and tuple(out.shape) == (n, 8)):
+            raise ValueError("out must be a contiguous float32 CUDA tensor [n, 8]")
+        _check(lib().seb_query_se2(self._h, fa, fb, int(ring[0]), int(ring[1]),
+                                   C.c_void_p(poses.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                   _stream_handle(stream)), "seb_query_se2")
         return out
 
 

@@ -1,0 +1,195 @@
+"""SE(2) signed distance field and trilinear Risk / SDF query on the GPU,
+against the FP64 reference (oracle/sdf.py) on seeded synthetic status planes
+and fields.
+
+Bars: the sign (obstacle or free) and the squared distance in cells are exact
+(integers); the value agrees to 4 float32 ulps of the largest value (cap x res)
+-- the kernel rounds sqrt, the subtraction and the scaling once each.  Query
+outputs agree to 8 ulps of the field's largest magnitude (seven lerps) and the
+gradients to the same over the axis spacing."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sdf as S
+from paper_2503_02412_amd import inputs as I
+from paper_2503_02412_amd import seb
+
+pytestmark = pytest.mark.gpu
+
+ULP = 2.0 ** -23
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu-case] {request.node.nodeid}", flush=True)
+
+
+def small(W, H, res, K):
+    return I.Params(W, H, res, K, 0.6, 0.4, 6, 4)
+
+
+def to_storage(a, ring):
+    rx, ry = ring
+    return np.roll(a, (ry, rx), axis=(-2, -1))
+
+
+def to_logical(a, ring):
+    rx, ry = ring
+    return np.roll(a, (-ry, -rx), axis=(-2, -1))
+
+
+def check_sdf(got, want, res, cap):
+    got = np.asarray(got, dtype=np.float64)
+    assert got.shape == want.shape
+    assert np.array_equal(got < 0, want < 0), "obstacle / free side differs"
+    d2g = np.rint((np.abs(got) / res + 0.5) ** 2)
+    d2w = np.rint((np.abs(want) / res + 0.5) ** 2)
+    bad = np.argwhere(d2g != d2w)
+    assert bad.size == 0, f"squared distance differs at {bad[:5].tolist()}"
+    err = np.max(np.abs(got - want)) if got.size else 0.0
+    assert err <= 4 * ULP * cap * res + 1e-12, err
+
+
+def gpu_sdf(ctx, status_logical, cap, unknown, ring):
+    import torch
+    st = torch.from_numpy(np.ascontiguousarray(to_storage(status_logical, ring))).cuda()
+    out = ctx.sdf(st, cap, unknown, ring=ring)
+    torch.cuda.synchronize()
+    return to_logical(out.cpu().numpy(), ring)
+
+
+@pytest.mark.parametrize("W,H,K,res,cap,unknown,ring", [
+    (64, 64, 16, 0.1, 20, True, (0, 0)),         # 64 x 64 @ 0.1 m, 16 yaw bins, 2 m cap
+    (100, 70, 8, 0.05, 7, False, (37, 11)),      # ragged tiles, ring offset
+    (33, 97, 3, 0.1, 64, True, (5, 96)),         # the largest cap, taller than wide
+    (5, 3, 2, 0.1, 2, True, (4, 2)),             # smaller than one tile
+    (1, 7, 1, 0.2, 3, False, (0, 6)),            # one column, one yaw bin
+])
+def test_sdf_matches_oracle(W, H, K, res, cap, unknown, ring):
+    p = small(W, H, res, K)
+    status = I.synthetic_status(W, H, K, seed=W * 131 + H, max_radius=4 if W < 10 else 9)
+    want = S.sdf_planes(status, res, cap, unknown)
+    with seb.Context(p) as ctx:
+        got = gpu_sdf(ctx, status, cap, unknown, ring)
+    check_sdf(got, want, res, cap)
+
+
+@pytest.mark.parametrize("name,cap", [("config2", 20), ("config5", 64)])
+def test_sdf_full_size_sampled(name, cap):
+    """The benchmarked 200 x 200 x 36 map (2 m cap) and the 800 x 800 x 72 map
+    at the largest cap, checked on sampled states against the one-by-one
+    reference."""
+    p = I.PRESETS[name]
+    status = I.synthetic_status(p.width, p.height, p.n_yaw, seed=17)
+    ring = (p.width // 3, p.height - 5)
+    with seb.Context(p) as ctx:
+        got = gpu_sdf(ctx, status, cap, True, ring)
+    rng = np.random.default_rng(5)
+    obst = S.obstacle_mask(status, True)
+    for k in rng.choice(p.n_yaw, 3, replace=False):
+        ys, xs = rng.integers(0, p.height, 400), rng.integers(0, p.width, 400)
+        # near the map's edges too, where the halo leaves the map
+        ys[:40], xs[40:80] = rng.integers(0, 3, 40), rng.integers(p.width - 3, p.width, 40)
+        want = S.sdf_cells(obst[k], p.resolution, cap, ys, xs)
+        check_sdf(got[k, ys, xs], want, p.resolution, cap)
+
+
+def test_sdf_degenerate_planes():
+    W, H, K, res, cap = 45, 40, 3, 0.1, 6
+    p = small(W, H, res, K)
+    free = np.full((K, H, W), 1 | 16, np.uint8)
+    obst = np.full((K, H, W), 1 | 2, np.uint8)
+    unknown = np.zeros((K, H, W), np.uint8)
+    single = free.copy()
+    single[1, 17, 29] = 1 | 4
+    with seb.Context(p) as ctx:
+        assert np.all(gpu_sdf(ctx, free, cap, True, (0, 0)) == np.float32((cap - 0.5) * res))
+        assert np.all(gpu_sdf(ctx, obst, cap, True, (3, 4)) == -np.float32((cap - 0.5) * res))
+        # unknown states are free when not counted as obstacles, obstacles otherwise
+        assert np.all(gpu_sdf(ctx, unknown, cap, False, (0, 0)) > 0)
+        assert np.all(gpu_sdf(ctx, unknown, cap, True, (0, 0)) < 0)
+        got = gpu_sdf(ctx, single, cap, True, (0, 0))
+    ys, xs = np.mgrid[0:H, 0:W]
+    d = np.minimum(np.hypot(xs - 29, ys - 17), cap)
+    want = np.where(np.arange(K)[:, None, None] == 1, (d - 0.5) * res, (cap - 0.5) * res)
+    want[1, 17, 29] = -0.5 * res
+    check_sdf(got, want, res, cap)
+
+
+def test_sdf_rejects_bad_arguments():
+    import torch
+    p = small(40, 30, 0.1, 4)
+    st = torch.zeros((4, 30, 40), dtype=torch.uint8, device="cuda")
+    with seb.Context(p) as ctx:
+        for cap, ring, code in [(0, (0, 0), seb.SEB_ERR_INVALID), (65, (0, 0), seb.SEB_ERR_UNSUPPORTED),
+                                (4, (40, 0), seb.SEB_ERR_INVALID), (4, (0, -1), seb.SEB_ERR_INVALID)]:
+            with pytest.raises(seb.SebError) as e:
+                ctx.sdf(st, cap, True, ring=ring)
+            assert e.value.code == code
+        with pytest.raises(ValueError):
+            ctx.sdf(st[:3], 4)
+
+
+def special_poses(W, H, K, res):
+    dth = 2 * math.pi / K
+    xs = [0.5 * res, (W - 0.5) * res, (W // 2 + 0.5) * res, 0.0, W * res, -1.0, W * res + 1.0]
+    ys = [0.5 * res, (H - 0.5) * res, (H // 3 + 0.5) * res, 0.0, H * res]
+    ths = [0.0, dth, (K - 1) * dth, 2 * math.pi, -2 * math.pi, -1e-7, 0.5 * dth, 1000.0]
+    g = np.array(np.meshgrid(xs, ys, ths, indexing="ij")).reshape(3, -1).T
+    return g.astype(np.float32)
+
+
+@pytest.mark.parametrize("W,H,K,res,ring", [
+    (64, 64, 16, 0.1, (0, 0)),
+    (100, 70, 72, 0.05, (99, 1)),
+    (1, 7, 1, 0.2, (0, 3)),
+])
+def test_query_matches_oracle(W, H, K, res, ring):
+    import torch
+    p = small(W, H, res, K)
+    status = I.synthetic_status(W, H, K, seed=3 + W, max_radius=4 if W < 10 else 9)
+    sdf = S.sdf_planes(status, res, 12, True).astype(np.float32)
+    risk = I._rng(W + H).uniform(0.0, 1.0, (K, H, W)).astype(np.float32)
+    poses = np.concatenate([I.query_poses(4000, W, H, res, seed=K), special_poses(W, H, K, res)])
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    with seb.Context(p) as ctx:
+        out = ctx.query(dev(poses), sdf=dev(to_storage(sdf, ring)), risk=dev(to_storage(risk, ring)),
+                        ring=ring)
+        only_risk = ctx.query(dev(poses), risk=dev(to_storage(risk, ring)), ring=ring)
+        torch.cuda.synchronize()
+        out, only_risk = out.cpu().numpy(), only_risk.cpu().numpy()
+    dth = 2 * math.pi / K
+    for f, grid in ((0, sdf), (1, risk)):
+        want = S.query(grid.astype(np.float64), res, poses)
+        got = out[:, 4 * f:4 * f + 4].astype(np.float64)
+        M = float(np.max(np.abs(grid)))
+        tol = 8 * ULP * M * np.array([1.0, 1.0 / res, 1.0 / res, 1.0 / dth]) + 1e-12
+        err = np.abs(got - want)
+        worst = np.argmax(np.max(err / tol, axis=1))
+        assert np.all(err <= tol), (f, poses[worst], got[worst], want[worst])
+    assert np.all(only_risk[:, :4] == 0.0)
+    assert np.array_equal(only_risk[:, 4:], out[:, 4:])
+
+
+def test_query_edge_inputs():
+    import torch
+    W, H, K, res = 30, 20, 8, 0.1
+    p = small(W, H, res, K)
+    risk = torch.from_numpy(I._rng(4).uniform(0, 1, (K, H, W)).astype(np.float32)).cuda()
+    nan = float("nan")
+    poses = torch.tensor([[nan, 1.0, 0.3], [-5.0, 1.0, 0.3],
+                          [1.0, 1.0, nan], [1.0, 1.0, 0.0],
+                          [1.0, 1.0, float("inf")]], dtype=torch.float32, device="cuda")
+    with seb.Context(p) as ctx:
+        out = ctx.query(poses, risk=risk).cpu().numpy()
+        empty = ctx.query(torch.empty((0, 3), dtype=torch.float32, device="cuda"), risk=risk)
+        with pytest.raises(seb.SebError):
+            ctx.query(poses)                       # neither field
+        with pytest.raises(seb.SebError):
+            ctx.query(poses, risk=risk, ring=(W, 0))
+    assert empty.shape == (0, 8)
+    assert np.array_equal(out[0], out[1])          # NaN x reads as the clamped lower edge
+    assert np.array_equal(out[2], out[3])          # NaN / Inf yaw reads as bin 0
+    assert np.array_equal(out[4], out[3])

@@ -123,3 +123,13 @@ def test_query_clamps_outside_the_map():
     outside = S.query(g, res, np.array([[-2.0, 3.2 * res, 0.4]]))[0]
     assert abs(outside[0] - inside[0]) < 1e-12 and outside[1] == 0.0
     assert abs(outside[2] - inside[2]) < 1e-12 and abs(outside[3] - inside[3]) < 1e-12
+
+
+def test_sampled_cells_match_whole_plane():
+    rng = np.random.default_rng(9)
+    obst = rng.random((37, 52)) < 0.07
+    full = S.sdf_plane(obst, 0.1, 9)
+    ys, xs = rng.integers(0, 37, 300), rng.integers(0, 52, 300)
+    assert np.array_equal(S.sdf_cells(obst, 0.1, 9, ys, xs), full[ys, xs])
+    none = np.zeros((5, 6), bool)
+    assert np.all(S.sdf_cells(none, 0.1, 4, [0, 4], [0, 5]) == (4 - 0.5) * 0.1)
