@@ -155,22 +155,29 @@ def bench_sdf(torch, seb, n_poses: int = 1 << 20):
         out = ctx.assess(torch.from_numpy(hmap).cuda())
         sdf = torch.empty_like(out["risk"])
         ms = time_launches(torch, lambda: ctx.sdf(out["status"], cap, True, out=sdf), 50, 5)
-        poses = torch.from_numpy(I.query_poses(n_poses, p.width, p.height, p.resolution,
-                                               seed=11)).cuda()
+        rand = torch.from_numpy(I.query_poses(n_poses, p.width, p.height, p.resolution,
+                                              seed=11)).cuda()
+        paths = torch.from_numpy(I.trajectory_query_poses(n_poses >> 10, 1024, p.width,
+                                                          p.height, p.resolution, seed=12)).cuda()
         q = torch.empty((n_poses, 8), dtype=torch.float32, device="cuda")
-        qms = time_launches(torch, lambda: ctx.query(poses, sdf=sdf, risk=out["risk"], out=q),
+        qms = time_launches(torch, lambda: ctx.query(rand, sdf=sdf, risk=out["risk"], out=q),
+                            50, 5)
+        tms = time_launches(torch, lambda: ctx.query(paths, sdf=sdf, risk=out["risk"], out=q),
                             50, 5)
         obst = ((out["status"] & 6) != 0) | ((out["status"] & 1) == 0)
         res[name] = {
             "workload": f"{p.width}x{p.height} @{p.resolution} m, {p.n_yaw} yaw bins, "
-                        f"cap {cap} cells; {n_poses} query poses",
+                        f"cap {cap} cells; {n_poses} query poses, uniform random or along "
+                        f"{n_poses >> 10} paths of 1024 samples",
             "obstacle_fraction": float(obst.float().mean()),
             "sdf_ms": ms, "sdf_states_per_s": p.n_states / (ms * 1e-3),
             # algorithmic bytes: one status byte in, one float out per state
             "sdf_gbps": 5 * p.n_states / (ms * 1e-3) / 1e9,
-            "query_ms": qms, "query_poses_per_s": n_poses / (qms * 1e-3),
             # algorithmic bytes per pose: 12 in, 32 out (corner reads hit the caches)
-            "query_gbps": 44 * n_poses / (qms * 1e-3) / 1e9,
+            "query_random_ms": qms, "query_random_poses_per_s": n_poses / (qms * 1e-3),
+            "query_random_gbps": 44 * n_poses / (qms * 1e-3) / 1e9,
+            "query_paths_ms": tms, "query_paths_poses_per_s": n_poses / (tms * 1e-3),
+            "query_paths_gbps": 44 * n_poses / (tms * 1e-3) / 1e9,
         }
     return res
 

@@ -287,8 +287,8 @@ int seb_surrogate_infer(seb_surrogate* s, const seb_net* net, const float* heigh
  * arrays of a rolling window can be passed as they are (ring_x = ring_y = 0
  * for a plain map).  Errors (host-side, nothing launched): SEB_ERR_INVALID
  * (NULL array, ring offset outside [0, W) x [0, H), cap_cells < 1),
- * SEB_ERR_UNSUPPORTED (cap_cells > 64).  Enqueues one kernel; allocates
- * nothing. */
+ * SEB_ERR_UNSUPPORTED (cap_cells > 64, or W * H >= 2^31).  Enqueues one
+ * kernel; allocates nothing. */
 int seb_sdf_se2(seb_ctx* ctx, const uint8_t* status, int32_t ring_x, int32_t ring_y,
                 int32_t cap_cells, int32_t unknown_is_obstacle, float* sdf, void* stream);
 

@@ -786,6 +786,8 @@ int seb_sdf_se2(seb_ctx* c, const uint8_t* status, int32_t ring_x, int32_t ring_
     if (cap_cells < 1) return fail(SEB_ERR_INVALID, "cap_cells must be >= 1");
     if (cap_cells > sdf_max_cap())
         return fail(SEB_ERR_UNSUPPORTED, "cap_cells above " + std::to_string(sdf_max_cap()));
+    if ((int64_t)g.width * g.height >= (int64_t(1) << 31))
+        return fail(SEB_ERR_UNSUPPORTED, "sdf planes of 2^31 cells or more");
     hipError_t e = launch_sdf(status, sdf, g.width, g.height, g.n_yaw, ring_x, ring_y, cap_cells,
                               (float)g.resolution, unknown_is_obstacle != 0, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "sdf launch");

@@ -6,13 +6,20 @@
 // reads that field and the risk at arbitrary poses by trilinear interpolation
 // with the yaw on SO(2).
 //
-// sdf_kernel: a workgroup owns a 32 x 32 block of cells of one yaw plane.  With
-// distances capped at C cells, every target that matters lies within C cells
-// in x and in y, so the block's flags with a C-cell halo are staged in LDS and
-// the exact two-pass transform runs there: per column, the squared distance to
-// the nearest obstacle (and nearest free) cell in that column within C rows;
-// then per cell, the minimum over |dx| <= C of dx^2 plus the column value at
-// x + dx.  Distances beyond C come out as C, as the cap asks.
+// sdf_kernel: a workgroup owns a strip of R rows of one yaw plane and 256 - 2C
+// of its columns; its 256 threads stand for those columns plus C more on each
+// side.  With distances capped at C cells every target that matters lies
+// within C cells in x and in y, so the exact two-pass transform runs on that
+// window alone:
+//   column pass -- each thread sweeps its column from C rows below the strip
+//     up, then from C rows above it down, and keeps, for each strip row, the
+//     squared distance to the nearest obstacle and the nearest free cell of
+//     the column (none beyond C);
+//   row pass -- for each cell, the minimum over |dx| <= C of dx^2 plus the
+//     column value at x + dx of the opposite class.  A 64-bit ballot per word
+//     of each row marks the columns holding any target; the nearest marked
+//     column starts the scan, and a cell with none within C takes the cap at
+//     once.  The scan ends once dx^2 alone reaches the best so far.
 #include <cmath>
 #include <cstdint>
 
@@ -24,83 +31,172 @@
 namespace seb {
 namespace {
 
-constexpr int ST = 32;                    // block side (cells)
+constexpr int NT = 256;                   // threads = window columns
+constexpr int NWORD = NT / 64;            // 64-bit column masks per row
 constexpr uint16_t FAR = 0xFFFF;          // no target within C rows
-enum : uint8_t { FREE = 0, OBST = 1, OUTSIDE = 2 };
+constexpr int BIG = 1 << 20;
+constexpr int DU = 4;                     // row-scan unroll; also the LDS row padding
 
 struct SdfArgs {
     const uint8_t* status;                // [K][H][W], ring layout
     float* sdf;                           // [K][H][W], ring layout
     int W, H, K, rx, ry;
     int cap;                              // C, cells
+    int tiles_x;                          // column blocks of NT - 2C
     float res;
     int unknown_is_obstacle;
 };
 
 __device__ __forceinline__ int wrap(int v, int n) { return v >= n ? v - n : v; }
 
-__global__ __launch_bounds__(256) void sdf_kernel(const SdfArgs a) {
-    extern __shared__ uint8_t lds[];
-    const int C = a.cap;
-    const int span = ST + 2 * C;
-    uint8_t* flag = lds;                                          // [span][span]
-    uint16_t* g_obs = (uint16_t*)(lds + ((span * span + 3) & ~3));  // [ST][span]
-    uint16_t* g_free = g_obs + ST * span;                         // [ST][span]
-    const int tid = threadIdx.x;
-    const int bx = blockIdx.x, k = blockIdx.y;
-    const int tiles_x = (a.W + ST - 1) / ST;
-    const int x0 = (bx % tiles_x) * ST, y0 = (bx / tiles_x) * ST;
-    const uint8_t* plane = a.status + (int64_t)k * a.W * a.H;
+// Distance from column t to the nearest set bit of the row mask m (NT bits),
+// looking at most one word to either side (enough for C <= 64); > 64 if none.
+__device__ __forceinline__ int nearest_marked(const uint64_t* m, int t) {
+    const int w = t >> 6, b = t & 63;
+    int left = -BIG, right = BIG;
+    const uint64_t lo = m[w] & ((2ull << b) - 1ull);          // bits 0..b
+    if (lo) left = (w << 6) + 63 - __clzll(lo);
+    else if (w > 0 && m[w - 1]) left = ((w - 1) << 6) + 63 - __clzll(m[w - 1]);
+    const uint64_t hi = m[w] & (~0ull << b);                  // bits b..63
+    if (hi) right = (w << 6) + __ffsll((unsigned long long)hi) - 1;
+    else if (w < NWORD - 1 && m[w + 1])
+        right = ((w + 1) << 6) + __ffsll((unsigned long long)m[w + 1]) - 1;
+    return min(t - left, right - t);
+}
 
-    for (int i = tid; i < span * span; i += 256) {
-        const int r = i / span, c = i - r * span;
-        const int y = y0 - C + r, x = x0 - C + c;
-        uint8_t f = OUTSIDE;
-        if (x >= 0 && x < a.W && y >= 0 && y < a.H) {
-            const uint8_t st = plane[(int64_t)wrap(y + a.ry, a.H) * a.W + wrap(x + a.rx, a.W)];
-            const bool obst = (st & (SEB_ST_CURV | SEB_ST_TILT)) != 0 ||
-                              (a.unknown_is_obstacle && (st & SEB_ST_VALID) == 0);
-            f = obst ? OBST : FREE;
+template <int R>
+__global__ __launch_bounds__(NT) void sdf_kernel(const SdfArgs a) {
+    // Column values, DU padding entries (never a target) at both ends of a row.
+    __shared__ uint16_t g_obs_p[R][NT + 2 * DU], g_free_p[R][NT + 2 * DU];
+    __shared__ uint64_t m_obs[R][NWORD], m_free[R][NWORD];
+    const int C = a.cap, TX = NT - 2 * C;
+    const int t = threadIdx.x;
+    const int bx = blockIdx.x % a.tiles_x, by = blockIdx.x / a.tiles_x, k = blockIdx.y;
+    const int xs = bx * TX - C + t;                          // this thread's column
+    const int y0 = by * R, ny = min(R, a.H - y0);
+    auto g_obs = [&](int j) { return &g_obs_p[j][DU]; };
+    auto g_free = [&](int j) { return &g_free_p[j][DU]; };
+    if (t < 2 * DU) {
+        const int pc = t < DU ? t : NT + t;
+        for (int j = 0; j < ny; ++j) g_obs_p[j][pc] = g_free_p[j][pc] = FAR;
+    }
+
+    if (xs >= 0 && xs < a.W) {
+        const uint8_t* plane = a.status + (int64_t)k * a.W * a.H;
+        const int cx = wrap(xs + a.rx, a.W);
+        const int unk = a.unknown_is_obstacle;
+        // Loads are unconditional, from rows clamped into the map, into plain
+        // integers (one plane holds fewer than 2^31 cells); the guards and the
+        // obstacle test come afterwards, so each batch of loads is in flight
+        // at once.
+        auto load = [&](int y) -> int { return plane[wrap(y + a.ry, a.H) * a.W + cx]; };
+        auto obstacle = [&](int st) {           // 1: CURV or TILT, or UNKNOWN if counted
+            return ((st >> 1) | (st >> 2) | (unk & ~st)) & 1;
+        };
+        // The halos only contribute the nearest obstacle / free row beyond the
+        // strip: a min (below) and a max (above), HB rows at a time.
+        constexpr int HB = 16;
+        int no = BIG, nf = BIG;
+        for (int yb = y0 + ny, ye = min(a.H, y0 + ny + C); yb < ye; yb += HB) {
+            int sv[HB];
+#pragma unroll
+            for (int u = 0; u < HB; ++u) sv[u] = load(min(yb + u, ye - 1));
+#pragma unroll
+            for (int u = 0; u < HB; ++u) {
+                const int y = yb + u < ye ? yb + u : BIG;
+                if (obstacle(sv[u])) no = min(no, y); else nf = min(nf, y);
+            }
         }
-        flag[i] = f;
+        int sv[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) sv[j] = load(min(y0 + j, a.H - 1));
+        uint32_t ob = 0;                         // bit j: strip row j is an obstacle
+#pragma unroll
+        for (int j = 0; j < R; ++j) ob |= (uint32_t)obstacle(sv[j]) << j;
+#pragma unroll
+        for (int j = R - 1; j >= 0; --j) {
+            if (j < ny) {
+                if ((ob >> j) & 1) no = y0 + j; else nf = y0 + j;
+                g_obs(j)[t] = (uint16_t)min(no - (y0 + j), C + 1);
+                g_free(j)[t] = (uint16_t)min(nf - (y0 + j), C + 1);
+            }
+        }
+        int ao = -BIG, af = -BIG;
+        for (int yb = max(0, y0 - C); yb < y0; yb += HB) {
+            int hv[HB];
+#pragma unroll
+            for (int u = 0; u < HB; ++u) hv[u] = load(min(yb + u, y0 - 1));
+#pragma unroll
+            for (int u = 0; u < HB; ++u) {
+                const int y = yb + u < y0 ? yb + u : -BIG;
+                if (obstacle(hv[u])) ao = max(ao, y); else af = max(af, y);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (j < ny) {
+                if ((ob >> j) & 1) ao = y0 + j; else af = y0 + j;
+                const int d_o = min((int)g_obs(j)[t], y0 + j - ao);
+                const int d_f = min((int)g_free(j)[t], y0 + j - af);
+                g_obs(j)[t] = d_o <= C ? (uint16_t)(d_o * d_o) : FAR;
+                g_free(j)[t] = d_f <= C ? (uint16_t)(d_f * d_f) : FAR;
+            }
+        }
+    } else {
+        for (int j = 0; j < ny; ++j) g_obs(j)[t] = g_free(j)[t] = FAR;   // outside the map
+    }
+    __syncthreads();
+    // Column masks: wave w holds columns 64w .. 64w + 63.
+    for (int j = 0; j < ny; ++j) {
+        const uint64_t bo = __ballot(g_obs(j)[t] != FAR);
+        const uint64_t bf = __ballot(g_free(j)[t] != FAR);
+        if ((t & 63) == 0) {
+            m_obs[j][t >> 6] = bo;
+            m_free[j][t >> 6] = bf;
+        }
     }
     __syncthreads();
 
-    // Column pass over the block's rows: nearest obstacle / free cell in the
-    // same column within C rows, searched outwards.
-    for (int i = tid; i < ST * span; i += 256) {
-        const int r = i / span, c = i - r * span;
-        const int rr = r + C;
-        int dob = -1, dfr = -1;
-        for (int d = 0; d <= C && (dob < 0 || dfr < 0); ++d) {
-            const uint8_t up = flag[(rr - d) * span + c];
-            const uint8_t dn = flag[(rr + d) * span + c];
-            if (dob < 0 && (up == OBST || dn == OBST)) dob = d;
-            if (dfr < 0 && (up == FREE || dn == FREE)) dfr = d;
+    const int x_lo = bx * TX;                                 // first output column
+    const int n_cols = min(TX, a.W - x_lo);
+    const float res = a.res;
+    for (int i = t; i < ny * n_cols; i += NT) {
+        const int j = i / n_cols, c = i - j * n_cols;
+        const int tc = C + c;                                 // window column of the cell
+        const bool obst = g_obs(j)[tc] == 0;
+        const uint16_t* g = obst ? g_free(j) : g_obs(j);
+        const int dmin = nearest_marked(obst ? m_free[j] : m_obs[j], tc);
+        int best = C * C;
+        if (dmin <= C) {
+            int dx = dmin;
+            best = BIG;
+            if (dx == 0) {
+                best = g[tc];
+                dx = 1;
+            }
+            // DU steps at a time: the 2 DU reads stay inside the padded row
+            // (|dx| <= C + DU - 1) and are issued together; steps past C are
+            // ignored.
+            for (; dx <= C && dx * dx < best; dx += DU) {
+                int gl[DU], gr[DU];
+#pragma unroll
+                for (int u = 0; u < DU; ++u) {
+                    gl[u] = g[tc - dx - u];
+                    gr[u] = g[tc + dx + u];
+                }
+#pragma unroll
+                for (int u = 0; u < DU; ++u) {
+                    const int e = dx + u, e2 = e <= C ? e * e : BIG;
+                    if (gl[u] != FAR) best = min(best, e2 + gl[u]);
+                    if (gr[u] != FAR) best = min(best, e2 + gr[u]);
+                }
+            }
+            best = min(best, C * C);
         }
-        g_obs[r * span + c] = dob < 0 ? FAR : (uint16_t)(dob * dob);
-        g_free[r * span + c] = dfr < 0 ? FAR : (uint16_t)(dfr * dfr);
-    }
-    __syncthreads();
-
-    // Row pass: per cell of the block, the nearest target among columns
-    // x + dx, |dx| <= C, stopping once dx^2 alone reaches the best so far.
-    for (int i = tid; i < ST * ST; i += 256) {
-        const int r = i / ST, c = i - r * ST;
-        const int x = x0 + c, y = y0 + r;
-        if (x >= a.W || y >= a.H) continue;
-        const uint8_t f = flag[(r + C) * span + (c + C)];
-        const uint16_t* g = (f == OBST ? g_free : g_obs) + r * span + (c + C);
-        int best = g[0] == FAR ? 0x7FFFFFFF : (int)g[0];
-        for (int dx = 1; dx <= C && dx * dx < best; ++dx) {
-            const int gl = g[-dx], gr = g[dx];
-            if (gl != FAR) best = min(best, dx * dx + gl);
-            if (gr != FAR) best = min(best, dx * dx + gr);
-        }
-        const float d = fminf(sqrtf((float)min(best, C * C)), (float)C);
-        const float v = (d - 0.5f) * a.res;
+        const float v = (sqrtf((float)best) - 0.5f) * res;
+        const int x = x_lo + c, y = y0 + j;
         a.sdf[(int64_t)k * a.W * a.H + (int64_t)wrap(y + a.ry, a.H) * a.W + wrap(x + a.rx, a.W)] =
-            f == OBST ? -v : v;
+            obst ? -v : v;
     }
 }
 
@@ -195,10 +291,16 @@ hipError_t launch_sdf(const uint8_t* status, float* sdf, int W, int H, int K, in
     a.cap = cap;
     a.res = res;
     a.unknown_is_obstacle = unknown_is_obstacle;
-    const int span = ST + 2 * cap;
-    const size_t lds = (size_t)((span * span + 3) & ~3) + (size_t)2 * ST * span * sizeof(uint16_t);
-    const dim3 grid(((W + ST - 1) / ST) * ((H + ST - 1) / ST), K);
-    hipLaunchKernelGGL(sdf_kernel, grid, dim3(256), lds, stream, a);
+    const int TX = NT - 2 * cap;
+    a.tiles_x = (W + TX - 1) / TX;
+    // Taller strips share the column halo among more rows; shorter ones give
+    // small maps enough workgroups.
+    auto blocks = [&](int R) { return (int64_t)a.tiles_x * ((H + R - 1) / R); };
+    const int R = blocks(32) * K >= 2048 ? 32 : blocks(16) * K >= 1024 ? 16 : 8;
+    const dim3 grid((unsigned)blocks(R), K);
+    if (R == 32) hipLaunchKernelGGL(sdf_kernel<32>, grid, dim3(NT), 0, stream, a);
+    else if (R == 16) hipLaunchKernelGGL(sdf_kernel<16>, grid, dim3(NT), 0, stream, a);
+    else hipLaunchKernelGGL(sdf_kernel<8>, grid, dim3(NT), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -378,3 +378,24 @@ def query_poses(n: int, width: int, height: int, res: float, seed: int,
     y = rng.uniform(-margin_cells * res, (height + margin_cells) * res, n)
     th = rng.uniform(-6.0 * math.pi, 6.0 * math.pi, n)
     return np.stack([x, y, th], 1).astype(np.float32)
+
+
+def trajectory_query_poses(n_traj: int, n_per: int, width: int, height: int, res: float,
+                           seed: int) -> np.ndarray:
+    """float32 [n_traj * n_per][3] poses sampled along smooth paths, the way a
+    trajectory optimiser reads the fields: each path starts at a uniform
+    position with a uniform heading, turns at a constant curvature drawn from
+    [-1, 1] 1/m and advances half a cell per sample; theta is the heading."""
+    rng = _rng(seed)
+    x0 = rng.uniform(0.0, width * res, n_traj)[:, None]
+    y0 = rng.uniform(0.0, height * res, n_traj)[:, None]
+    h0 = rng.uniform(-math.pi, math.pi, n_traj)[:, None]
+    kap = rng.uniform(-1.0, 1.0, n_traj)[:, None]
+    s = (np.arange(n_per) * 0.5 * res)[None, :]
+    th = h0 + kap * s
+    # closed form of the arc (straight-line limit for tiny curvature)
+    small_k = np.abs(kap) < 1e-9
+    safe_k = np.where(small_k, 1.0, kap)
+    x = np.where(small_k, x0 + s * np.cos(h0), x0 + (np.sin(th) - np.sin(h0)) / safe_k)
+    y = np.where(small_k, y0 + s * np.sin(h0), y0 - (np.cos(th) - np.cos(h0)) / safe_k)
+    return np.stack([x.ravel(), y.ravel(), th.ravel()], 1).astype(np.float32)

@@ -76,12 +76,14 @@ def test_sdf_matches_oracle(W, H, K, res, cap, unknown, ring):
     check_sdf(got, want, res, cap)
 
 
-@pytest.mark.parametrize("name,cap", [("config2", 20), ("config5", 64)])
+@pytest.mark.parametrize("name,cap", [("config2", 20), ("config5", 64), ("config5", 40),
+                                      ("500x256x24", 20)])
 def test_sdf_full_size_sampled(name, cap):
-    """The benchmarked 200 x 200 x 36 map (2 m cap) and the 800 x 800 x 72 map
-    at the largest cap, checked on sampled states against the one-by-one
-    reference."""
-    p = I.PRESETS[name]
+    """The benchmarked 200 x 200 x 36 map (2 m cap), the 800 x 800 x 72 map at
+    the largest cap and at 2 m, and a 500 x 256 x 24 map (the kernel's three
+    strip heights between them), checked on sampled states against the
+    one-by-one reference."""
+    p = I.PRESETS[name] if name in I.PRESETS else small(500, 256, 0.1, 24)
     status = I.synthetic_status(p.width, p.height, p.n_yaw, seed=17)
     ring = (p.width // 3, p.height - 5)
     with seb.Context(p) as ctx:
