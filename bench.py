@@ -278,6 +278,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="rolling,large_map,surrogate,sdf_query",
+                    help="comma-separated extra legs to run (default: all)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 256 MiB device copy (for HBM counter scaling)")
@@ -325,10 +327,12 @@ def main():
                      "traffic": traffic},
     }
     if not args.no_extras:
-        result["rolling"] = bench_rolling(torch, seb)
-        result["large_map"] = bench_large(torch, seb)
-        result["surrogate"] = bench_surrogate(torch, seb)
-        result["sdf_query"] = bench_sdf(torch, seb)
+        legs = {"rolling": bench_rolling, "large_map": bench_large,
+                "surrogate": bench_surrogate, "sdf_query": bench_sdf}
+        for name in args.extras.split(","):
+            if name not in legs:
+                sys.exit(f"unknown extra leg {name!r}; choose from {', '.join(legs)}")
+            result[name] = legs[name](torch, seb)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(p, hmap)
     # The paper's only timing for this path, for context (not comparable: it

@@ -304,8 +304,8 @@ int seb_sdf_se2(seb_ctx* ctx, const uint8_t* status, int32_t ring_x, int32_t rin
  * cell [floor, floor + 1] that holds the pose.  NaN coordinates read as the
  * clamped lower edge and yaw bin 0.  sdf and risk: device [K][H][W] in the
  * ring storage of seb_sdf_se2; either may be NULL (its four outputs are then
- * 0), not both.  n == 0 is a no-op.  Errors: SEB_ERR_INVALID.  Allocates
- * nothing. */
+ * 0), not both.  out must be 16-byte aligned.  n == 0 is a no-op.  Errors:
+ * SEB_ERR_INVALID.  Allocates nothing. */
 int seb_query_se2(seb_ctx* ctx, const float* sdf, const float* risk, int32_t ring_x, int32_t ring_y,
                   const float* poses, int64_t n, float* out, void* stream);
 

@@ -804,6 +804,7 @@ int seb_query_se2(seb_ctx* c, const float* sdf, const float* risk, int32_t ring_
         return fail(SEB_ERR_INVALID, "ring offset outside the map");
     if (n == 0) return SEB_OK;
     if (!poses || !out) return fail(SEB_ERR_INVALID, "poses and out must be non-NULL");
+    if (((uintptr_t)out & 15) != 0) return fail(SEB_ERR_INVALID, "out must be 16-byte aligned");
     if (n > (int64_t(1) << 40)) return fail(SEB_ERR_INVALID, "n too large");
     hipError_t e = launch_query(sdf, risk, poses, out, n, g.width, g.height, g.n_yaw, ring_x,
                                 ring_y, g.resolution, (hipStream_t)stream);

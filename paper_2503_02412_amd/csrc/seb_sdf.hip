@@ -13,10 +13,10 @@
 // window alone:
 //   column pass -- each thread sweeps its column from C rows below the strip
 //     up, then from C rows above it down, and keeps, for each strip row, the
-//     squared distance to the nearest obstacle and the nearest free cell of
-//     the column (none beyond C);
+//     distance in rows to the nearest obstacle and the nearest free cell of
+//     the column (none beyond C), one byte each;
 //   row pass -- for each cell, the minimum over |dx| <= C of dx^2 plus the
-//     column value at x + dx of the opposite class.  A 64-bit ballot per word
+//     squared column value at x + dx for the opposite class.  A 64-bit ballot per word
 //     of each row marks the columns holding any target; the nearest marked
 //     column starts the scan, and a cell with none within C takes the cap at
 //     once.  The scan ends once dx^2 alone reaches the best so far.
@@ -33,7 +33,7 @@ namespace {
 
 constexpr int NT = 256;                   // threads = window columns
 constexpr int NWORD = NT / 64;            // 64-bit column masks per row
-constexpr uint16_t FAR = 0xFFFF;          // no target within C rows
+constexpr uint8_t FAR = 0xFF;             // no target within C rows
 constexpr int BIG = 1 << 20;
 constexpr int DU = 4;                     // row-scan unroll; also the LDS row padding
 
@@ -66,12 +66,27 @@ __device__ __forceinline__ int nearest_marked(const uint64_t* m, int t) {
 
 template <int R>
 __global__ __launch_bounds__(NT) void sdf_kernel(const SdfArgs a) {
-    // Column values, DU padding entries (never a target) at both ends of a row.
-    __shared__ uint16_t g_obs_p[R][NT + 2 * DU], g_free_p[R][NT + 2 * DU];
+    // Column values (vertical distance in rows, <= C, or FAR), DU padding
+    // entries (never a target) at both ends of a row.
+    __shared__ uint8_t g_obs_p[R][NT + 2 * DU], g_free_p[R][NT + 2 * DU];
     __shared__ uint64_t m_obs[R][NWORD], m_free[R][NWORD];
     const int C = a.cap, TX = NT - 2 * C;
     const int t = threadIdx.x;
-    const int bx = blockIdx.x % a.tiles_x, by = blockIdx.x / a.tiles_x, k = blockIdx.y;
+    // Workgroups are handed to the 8 XCDs in turn (linear id mod 8).  Give each
+    // XCD a contiguous run of (plane, strip, column block), so that strips
+    // sharing halo rows meet in the same L2.
+    int bx, by, k;
+    {
+        const int64_t n = (int64_t)gridDim.x * gridDim.y;
+        const int64_t lin = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        const int64_t q = n / 8, r = n % 8, xcd = lin % 8, pos = lin / 8;
+        const int64_t lg = xcd < r ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
+        const int64_t per_plane = (int64_t)gridDim.x;        // tiles_x * strips
+        k = (int)(lg / per_plane);
+        const int rest = (int)(lg - (int64_t)k * per_plane);
+        bx = rest % a.tiles_x;
+        by = rest / a.tiles_x;
+    }
     const int xs = bx * TX - C + t;                          // this thread's column
     const int y0 = by * R, ny = min(R, a.H - y0);
     auto g_obs = [&](int j) { return &g_obs_p[j][DU]; };
@@ -117,8 +132,8 @@ __global__ __launch_bounds__(NT) void sdf_kernel(const SdfArgs a) {
         for (int j = R - 1; j >= 0; --j) {
             if (j < ny) {
                 if ((ob >> j) & 1) no = y0 + j; else nf = y0 + j;
-                g_obs(j)[t] = (uint16_t)min(no - (y0 + j), C + 1);
-                g_free(j)[t] = (uint16_t)min(nf - (y0 + j), C + 1);
+                g_obs(j)[t] = (uint8_t)min(no - (y0 + j), C + 1);
+                g_free(j)[t] = (uint8_t)min(nf - (y0 + j), C + 1);
             }
         }
         int ao = -BIG, af = -BIG;
@@ -138,8 +153,8 @@ __global__ __launch_bounds__(NT) void sdf_kernel(const SdfArgs a) {
                 if ((ob >> j) & 1) ao = y0 + j; else af = y0 + j;
                 const int d_o = min((int)g_obs(j)[t], y0 + j - ao);
                 const int d_f = min((int)g_free(j)[t], y0 + j - af);
-                g_obs(j)[t] = d_o <= C ? (uint16_t)(d_o * d_o) : FAR;
-                g_free(j)[t] = d_f <= C ? (uint16_t)(d_f * d_f) : FAR;
+                g_obs(j)[t] = d_o <= C ? (uint8_t)d_o : FAR;
+                g_free(j)[t] = d_f <= C ? (uint8_t)d_f : FAR;
             }
         }
     } else {
@@ -164,14 +179,14 @@ __global__ __launch_bounds__(NT) void sdf_kernel(const SdfArgs a) {
         const int j = i / n_cols, c = i - j * n_cols;
         const int tc = C + c;                                 // window column of the cell
         const bool obst = g_obs(j)[tc] == 0;
-        const uint16_t* g = obst ? g_free(j) : g_obs(j);
+        const uint8_t* g = obst ? g_free(j) : g_obs(j);
         const int dmin = nearest_marked(obst ? m_free[j] : m_obs[j], tc);
         int best = C * C;
         if (dmin <= C) {
             int dx = dmin;
             best = BIG;
             if (dx == 0) {
-                best = g[tc];
+                best = g[tc] * g[tc];
                 dx = 1;
             }
             // DU steps at a time: the 2 DU reads stay inside the padded row
@@ -187,8 +202,8 @@ __global__ __launch_bounds__(NT) void sdf_kernel(const SdfArgs a) {
 #pragma unroll
                 for (int u = 0; u < DU; ++u) {
                     const int e = dx + u, e2 = e <= C ? e * e : BIG;
-                    if (gl[u] != FAR) best = min(best, e2 + gl[u]);
-                    if (gr[u] != FAR) best = min(best, e2 + gr[u]);
+                    if (gl[u] != FAR) best = min(best, e2 + gl[u] * gl[u]);
+                    if (gr[u] != FAR) best = min(best, e2 + gr[u] * gr[u]);
                 }
             }
             best = min(best, C * C);
@@ -256,6 +271,7 @@ __global__ __launch_bounds__(256) void query_kernel(const QueryArgs q) {
                                wrap(is[e] + q.rx, q.W);
     const float sx = in_u ? (float)(1.0 / q.res) : 0.f, sy = in_v ? (float)(1.0 / q.res) : 0.f;
     const float sw = (float)(1.0 / dth);
+    float4 res[2];
     for (int f = 0; f < 2; ++f) {
         const float* g = f == 0 ? q.fa : q.fb;
         float o[4] = {0.f, 0.f, 0.f, 0.f};
@@ -266,12 +282,12 @@ __global__ __launch_bounds__(256) void query_kernel(const QueryArgs q) {
                     for (int e = 0; e < 2; ++e) c[a][b][e] = g[idx[a][b][e]];
             trilinear(c, fu, fv, fw, o);
         }
-        float* dst = q.out + 8 * n + 4 * f;
-        dst[0] = o[0];
-        dst[1] = o[1] * sx;
-        dst[2] = o[2] * sy;
-        dst[3] = o[3] * sw;
+        res[f] = make_float4(o[0], o[1] * sx, o[2] * sy, o[3] * sw);
     }
+    // 32 bytes per pose, as two 16-byte stores (out is 16-byte aligned)
+    float4* dst = reinterpret_cast<float4*>(q.out + 8 * n);
+    dst[0] = res[0];
+    dst[1] = res[1];
 }
 
 }  // namespace
