@@ -182,6 +182,56 @@ def bench_sdf(torch, seb, n_poses: int = 1 << 20):
     return res
 
 
+def bench_elevation(torch, seb, n_points: int = 200_000):
+    """The map update that precedes the assessment (Sec. V-A), on the 400 x 400
+    @ 0.05 m window: one 200k-point synthetic scan fused into a map that knows
+    95% of its cells, nearest-neighbour inpainting (radius 8 cells), and the
+    whole per-scan step fuse -> inpaint -> assess (72 yaw bins).  Inpainting is
+    also timed on the 800 x 800 map with 15% holes."""
+    p = I.CONFIG3
+    W, H, res = p.width, p.height, p.resolution
+    terrain = I.fractal_terrain(W, H, res, seed=800, hole_frac=0.05)
+    scan = I.synthetic_scan(terrain, res, n_points, seed=1, max_range=0.45 * W * res)
+    ctx = seb.Context(p)
+    fuser = seb.Fuser(ctx, len(scan["points"]))
+    pts = torch.from_numpy(scan["points"]).cuda()
+    h = torch.from_numpy(terrain).cuda()
+    v = torch.full((H, W), 1e-3, dtype=torch.float32, device="cuda")
+    n = torch.zeros(1, dtype=torch.int32, device="cuda")
+    fuse_ms = time_launches(torch, lambda: fuser.fuse(h, v, (0, 0), pts, scan, n_fused=n), 50, 5)
+    fused = int(n.item())
+    filled = torch.empty_like(h)
+    inp_ms = time_launches(torch, lambda: ctx.inpaint(h, 8, out=filled), 50, 5)
+    out = seb.alloc_outputs(p)
+
+    def step():
+        fuser.fuse(h, v, (0, 0), pts, scan, n_fused=n)
+        ctx.inpaint(h, 8, out=filled)
+        ctx.assess(filled, out)
+
+    step_ms = time_launches(torch, step, 20, 3)
+    p5 = I.CONFIG5
+    big = torch.from_numpy(I.fractal_terrain(p5.width, p5.height, p5.resolution, seed=5,
+                                             hole_frac=0.15)).cuda()
+    ctx5 = seb.Context(p5)
+    big_out = torch.empty_like(big)
+    inp5_ms = time_launches(torch, lambda: ctx5.inpaint(big, 8, out=big_out), 50, 5)
+    n_pts = len(scan["points"])
+    return {
+        "workload": f"400x400 @0.05 m window; one synthetic scan of {n_points} rays "
+                    f"({n_pts} returns) fused into a 95%-known map; inpainting radius 8 cells",
+        "fuse_ms": fuse_ms, "fuse_points_per_s": n_pts / (fuse_ms * 1e-3),
+        "points_changing_a_cell": fused,
+        # algorithmic bytes: 12 per point in, 8 read + 8 written per updated cell (bounded by points)
+        "fuse_gbps": (12 * n_pts + 16 * fused) / (fuse_ms * 1e-3) / 1e9,
+        "inpaint_ms": inp_ms, "inpaint_gbps": 8 * W * H / (inp_ms * 1e-3) / 1e9,
+        "inpaint_800x800_15pct_holes_ms": inp5_ms,
+        "inpaint_800x800_gbps": 8 * p5.width * p5.height / (inp5_ms * 1e-3) / 1e9,
+        "scan_step_ms": step_ms,
+        "scan_step_note": "fuse + inpaint + full assessment of 400x400x72 states",
+    }
+
+
 def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4):
     """Train the surrogate on plain-kernel labels, then time inference with the
     plain fallback on 200x200x36 evaluation maps against the plain kernel, and
@@ -278,7 +328,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="rolling,large_map,surrogate,sdf_query",
+    ap.add_argument("--extras", default="rolling,large_map,surrogate,sdf_query,elevation",
                     help="comma-separated extra legs to run (default: all)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -328,7 +378,8 @@ def main():
     }
     if not args.no_extras:
         legs = {"rolling": bench_rolling, "large_map": bench_large,
-                "surrogate": bench_surrogate, "sdf_query": bench_sdf}
+                "surrogate": bench_surrogate, "sdf_query": bench_sdf,
+                "elevation": bench_elevation}
         for name in args.extras.split(","):
             if name not in legs:
                 sys.exit(f"unknown extra leg {name!r}; choose from {', '.join(legs)}")

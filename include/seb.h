@@ -268,6 +268,61 @@ int seb_surrogate_infer(seb_surrogate* s, const seb_net* net, const float* heigh
                         const seb_out* out, float band, float min_known, int32_t* n_fallback_dev,
                         void* stream);
 
+/* --------------------------------------------- elevation-map update */
+
+/* One LiDAR scan and the frames and noise model of Sec. V-A, Eq. 5-9.
+ * Matrices are row-major 3 x 3 rotations; positions in metres. */
+typedef struct seb_scan {
+    const float* points;     /* device [n_points][3] float32, sensor frame              */
+    int64_t n_points;
+    double R_B[9], p_B[3];   /* robot pose: body frame -> map frame                     */
+    double R_BS[9], p_BS[3]; /* sensor extrinsics: sensor frame -> body frame           */
+    double Sigma_R[9];       /* covariance of the body-frame rotation perturbation
+                                R_B Exp(d) (rad^2), as in Eq. 7                          */
+    double Sigma_B[9];       /* covariance of p_B (m^2); Eq. 9 uses its (2, 2) entry    */
+    double sigma_range;      /* sensor model (> 0): range noise along the beam (m)      */
+    double sigma_angle;      /* sensor model (>= 0): angular noise across it (rad)      */
+    double z_min, z_max;     /* body-frame height band of the points kept               */
+    double mahalanobis;      /* gate tau (> 0) of the several-heights rule              */
+} seb_scan;
+
+/* Workspace for fusing scans of up to max_points points into maps of ctx's
+ * size (W * H < 2^31).  Errors: SEB_ERR_INVALID, SEB_ERR_UNSUPPORTED, SEB_ERR_ALLOC. */
+typedef struct seb_fuser seb_fuser;
+int seb_fuser_create(seb_ctx* ctx, int64_t max_points, seb_fuser** out);
+void seb_fuser_destroy(seb_fuser* f);
+
+/* Fuse one scan into the elevation map (Sec. V-A).  height and variance:
+ * device [H][W] float32, row stride ld, in the ring storage of a window whose
+ * logical cell (0, 0) is world cell (origin_x, origin_y) (world cell (gx, gy)
+ * at position (gx mod W, gy mod H); origin (0, 0) is a plain map).  Each point
+ * goes to the map frame (Sec. V-A: map rotation I, world cell = floor(x /
+ * res)); it is dropped outside the window or outside the body-frame height
+ * band; its height variance follows Eq. 5-9 with the sensor covariance
+ * sigma_range^2 u u^T + (sigma_angle r)^2 (I - u u^T) (u the beam direction,
+ * r the range).  The points of a cell then update it in increasing point
+ * index with a one-dimensional Kalman filter, in FP64: an unknown cell
+ * (non-finite height) takes the point; a point whose Mahalanobis distance
+ * |z - h| / sqrt(v) exceeds tau replaces the cell if it is higher and is
+ * dropped if it is lower (several heights in one cell); otherwise
+ * h <- (v z + s h) / (v + s), v <- v s / (v + s).  Cells without points are
+ * not touched.  *n_fused_dev (device int32, may be NULL) receives the number
+ * of points that changed a cell.  Errors (host-side, nothing launched):
+ * SEB_ERR_INVALID.  Allocates nothing; one fuser serves one stream at a time. */
+int seb_fuse_scan(seb_fuser* f, float* height, float* variance, int64_t ld, int64_t origin_x,
+                  int64_t origin_y, const seb_scan* scan, int32_t* n_fused_dev, void* stream);
+
+/* Nearest-neighbour inpainting (the method the experiments use; Sec. V-A
+ * leaves the inpainter open): every unknown (non-finite) cell of `height`
+ * takes the height of the known cell with the smallest (dx^2 + dy^2, dy, dx)
+ * within `radius` cells (0 <= radius <= 16), in logical coordinates; with none
+ * it is written as NaN.  Known cells are copied.  height: device [H][W], row
+ * stride ld; out: device [H][W], row stride out_ld, not overlapping height;
+ * both in ring storage with offsets (ring_x, ring_y) as for seb_sdf_se2.
+ * Errors: SEB_ERR_INVALID.  Allocates nothing. */
+int seb_inpaint_nearest(seb_ctx* ctx, const float* height, int64_t ld, int32_t ring_x,
+                        int32_t ring_y, int32_t radius, float* out, int64_t out_ld, void* stream);
+
 /* ------------------------------------------- planner-side fields */
 
 /* Signed distance field over the SE(2) states (Sec. V, and the safety

@@ -40,7 +40,8 @@ Readings (the paper leaves these open; the library uses the same ones):
     the end;
   - inpainting: an unknown cell takes the height of the known cell with the
     smallest (dx^2 + dy^2, dy, dx) within the radius (dx, dy signed, ring
-    order irrelevant: logical coordinates); none within it: stays unknown.
+    order irrelevant: logical coordinates); none within it: stays unknown,
+    written as NaN (also where it was +-Inf).
 
 Arithmetic is written out scalar by scalar (no matrix products) so that every
 IEEE operation, and so every floor and comparison, is the one the kernels
@@ -153,16 +154,20 @@ def inpaint_nearest(height: np.ndarray, radius: int) -> np.ndarray:
     Hm = np.asarray(height, dtype=np.float32)
     out = Hm.copy()
     known = np.isfinite(Hm)
-    ky, kx = np.nonzero(known)
-    vals = Hm[known]
+    Hn, Wn = Hm.shape
     r2max = radius * radius
     for y, x in zip(*np.nonzero(~known)):
-        dy = ky - y
-        dx = kx - x
+        out[y, x] = np.nan               # a cell left unknown reads NaN
+        # every known cell within the radius lies in this box
+        y0, y1 = max(0, y - radius), min(Hn, y + radius + 1)
+        x0, x1 = max(0, x - radius), min(Wn, x + radius + 1)
+        ky, kx = np.nonzero(known[y0:y1, x0:x1])
+        dy = ky + y0 - y
+        dx = kx + x0 - x
         d2 = dx * dx + dy * dy
         sel = d2 <= r2max
         if not sel.any():
             continue
         order = np.lexsort((dx[sel], dy[sel], d2[sel]))
-        out[y, x] = vals[sel][order[0]]
+        out[y, x] = Hm[y0 + ky[sel][order[0]], x0 + kx[sel][order[0]]]
     return out

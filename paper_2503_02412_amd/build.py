@@ -21,7 +21,8 @@ LIB = os.path.join(PKG, "libseb.so")
 ARCH = os.environ.get("SEB_OFFLOAD_ARCH", "gfx950")
 
 HOST_SOURCES = ["seb_host.cpp"]
-DEVICE_SOURCES = ["seb_assess.hip", "seb_net.hip", "seb_surrogate.hip", "seb_sdf.hip"]
+DEVICE_SOURCES = ["seb_assess.hip", "seb_net.hip", "seb_surrogate.hip", "seb_sdf.hip",
+                  "seb_elevation.hip"]
 
 COMMON = ["-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", f"-I{ROOT}/include"]
 # Code-object v5 loads under every ROCm 6.x/7.x runtime, including the HIP

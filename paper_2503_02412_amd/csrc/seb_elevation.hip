@@ -1,0 +1,299 @@
+// Elevation-map update before the assessment, for gfx950 (Sec. V-A).
+//
+// A scan's points are taken to the map frame, filtered (map range, body-frame
+// height band) and given the variance of their height (Eq. 5-9).  The points
+// of each map cell then update the cell's height and variance with a
+// one-dimensional Kalman filter; several heights in one cell are handled by
+// the classical elevation map's Mahalanobis test (a higher outlier replaces
+// the cell, a lower one is dropped).  The fold over a cell's points is
+// sequential by nature, so points are grouped by cell and each cell folds its
+// own points in point order: a count per cell (atomics), an exclusive prefix
+// sum, a scatter into per-cell buckets, and one thread per cell that sorts its
+// bucket by point index and folds it.  Every decision (the cell's floor, the
+// height band, the gate) is taken in FP64 from the same operations, in the
+// same order and without contraction, as the FP64 reference writes them.
+//
+// Unknown cells can then be filled from the nearest known cell within a
+// radius (nearest-neighbour inpainting, the method of the experiments), from
+// an LDS tile with a halo of that radius and a list of offsets sorted by
+// distance.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+#include "seb_elevation_internal.hpp"
+
+namespace seb {
+namespace elev {
+namespace {
+
+constexpr int SCAN_CHUNK = 4096;          // cells per prefix-sum block (256 x 16)
+
+__global__ __launch_bounds__(256) void clear_kernel(int32_t* count, int32_t* fill, int64_t n,
+                                                    int32_t* n_fused) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        count[i] = 0;
+        fill[i] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n_fused = 0;
+}
+
+__global__ __launch_bounds__(256) void points_kernel(const ScanArgs s, FuseWork w) {
+#pragma clang fp contract(off)
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < s.n; i += stride) {
+        const double px = s.pts[3 * i], py = s.pts[3 * i + 1], pz = s.pts[3 * i + 2];
+        // body frame q = R_BS p + p_BS, map frame l = R_B q + p_B
+        const double q0 = s.A[0] * px + s.A[1] * py + s.A[2] * pz + s.a[0];
+        const double q1 = s.A[3] * px + s.A[4] * py + s.A[5] * pz + s.a[1];
+        const double q2 = s.A[6] * px + s.A[7] * py + s.A[8] * pz + s.a[2];
+        const double lx = s.R[0] * q0 + s.R[1] * q1 + s.R[2] * q2 + s.b[0];
+        const double ly = s.R[3] * q0 + s.R[4] * q1 + s.R[5] * q2 + s.b[1];
+        const double lz = s.R[6] * q0 + s.R[7] * q1 + s.R[8] * q2 + s.b[2];
+        // Eq. 9 with the sensor model written without square roots
+        const double jp = s.js[0] * px + s.js[1] * py + s.js[2] * pz;
+        const double r2 = px * px + py * py + pz * pz;
+        const double sensor = r2 > 0.0 ? s.sr2 * (jp * jp) / r2 + s.sa2 * (r2 - jp * jp) : s.sr2;
+        const double k0 = q1 * s.g[2] - q2 * s.g[1];
+        const double k1 = q2 * s.g[0] - q0 * s.g[2];
+        const double k2 = q0 * s.g[1] - q1 * s.g[0];
+        const double rot = k0 * (s.SR[0] * k0 + s.SR[1] * k1 + s.SR[2] * k2) +
+                           k1 * (s.SR[3] * k0 + s.SR[4] * k1 + s.SR[5] * k2) +
+                           k2 * (s.SR[6] * k0 + s.SR[7] * k1 + s.SR[8] * k2);
+        const double var = sensor + rot + s.sb22;
+        const double cx = floor(lx / s.res) - (double)s.ox;
+        const double cy = floor(ly / s.res) - (double)s.oy;
+        const bool keep = q2 >= s.zmin && q2 <= s.zmax && cx >= 0.0 && cx < (double)s.W &&
+                          cy >= 0.0 && cy < (double)s.H && isfinite(lz);
+        int32_t c = -1;
+        if (keep) {
+            c = (int32_t)cy * s.W + (int32_t)cx;
+            atomicAdd(&w.count[c], 1);
+        }
+        w.cell[i] = c;
+        w.z[i] = lz;
+        w.var[i] = var;
+    }
+}
+
+// Exclusive prefix sum of count[0, n) into offs, in three passes: block sums,
+// a scan of the block sums, and a local scan of each block with its offset.
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t* lds, int32_t* total) {
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        const int32_t add = t >= d ? lds[t - d] : 0;
+        __syncthreads();
+        lds[t] += add;
+        __syncthreads();
+    }
+    const int32_t incl = lds[t];
+    *total = lds[255];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(256) void block_sums_kernel(const int32_t* count, int64_t n,
+                                                         int32_t* partial) {
+    __shared__ int32_t lds[256];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * 16;
+    int32_t s = 0;
+    for (int u = 0; u < 16; ++u)
+        if (base + u < n) s += count[base + u];
+    int32_t total;
+    block_exclusive_scan(s, lds, &total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void scan_partials_kernel(int32_t* partial, int64_t nb) {
+    __shared__ int32_t lds[256];
+    int32_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+        const int64_t i = b0 + threadIdx.x;
+        const int32_t v = i < nb ? partial[i] : 0;
+        int32_t total;
+        const int32_t ex = block_exclusive_scan(v, lds, &total);
+        if (i < nb) partial[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(256) void local_scan_kernel(const int32_t* count, int64_t n,
+                                                         const int32_t* partial, int32_t* offs) {
+    __shared__ int32_t lds[256];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * 16;
+    int32_t v[16], s = 0;
+    for (int u = 0; u < 16; ++u) {
+        v[u] = base + u < n ? count[base + u] : 0;
+        s += v[u];
+    }
+    int32_t total;
+    int32_t run = partial[blockIdx.x] + block_exclusive_scan(s, lds, &total);
+    for (int u = 0; u < 16; ++u) {
+        if (base + u < n) offs[base + u] = run;
+        run += v[u];
+    }
+}
+
+__global__ __launch_bounds__(256) void scatter_kernel(int64_t n, FuseWork w) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        const int32_t c = w.cell[i];
+        if (c >= 0) w.bucket[w.offs[c] + atomicAdd(&w.fill[c], 1)] = (int32_t)i;
+    }
+}
+
+// In-place ascending sort of a cell's point indices: insertion sort for short
+// buckets, heapsort (no extra memory, n log n) for long ones.
+__device__ void sort_bucket(int32_t* b, int n) {
+    if (n <= 32) {
+        for (int i = 1; i < n; ++i) {
+            const int32_t v = b[i];
+            int j = i - 1;
+            while (j >= 0 && b[j] > v) {
+                b[j + 1] = b[j];
+                --j;
+            }
+            b[j + 1] = v;
+        }
+        return;
+    }
+    auto sift = [&](int root, int end) {
+        while (2 * root + 1 < end) {
+            int child = 2 * root + 1;
+            if (child + 1 < end && b[child] < b[child + 1]) ++child;
+            if (b[root] >= b[child]) return;
+            const int32_t t = b[root];
+            b[root] = b[child];
+            b[child] = t;
+            root = child;
+        }
+    };
+    for (int i = n / 2 - 1; i >= 0; --i) sift(i, n);
+    for (int end = n - 1; end > 0; --end) {
+        const int32_t t = b[0];
+        b[0] = b[end];
+        b[end] = t;
+        sift(0, end);
+    }
+}
+
+__global__ __launch_bounds__(256) void fuse_kernel(const FuseArgs f, FuseWork w) {
+#pragma clang fp contract(off)
+    __shared__ int32_t used_lds[256];
+    const int64_t n_cells = (int64_t)f.W * f.H;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int32_t used = 0;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n_cells; c += stride) {
+        const int n = w.count[c];
+        if (n == 0) continue;
+        int32_t* b = w.bucket + w.offs[c];
+        sort_bucket(b, n);
+        const int lx = (int)(c % f.W), ly = (int)(c / f.W);
+        const int64_t at = (int64_t)((ly + f.ry) % f.H) * f.ld + (lx + f.rx) % f.W;
+        double h = (double)f.height[at], v = (double)f.variance[at];
+        for (int k = 0; k < n; ++k) {
+            const int32_t i = b[k];
+            const double zi = w.z[i], si = w.var[i];
+            if (!isfinite(h)) {
+                h = zi;
+                v = si;
+                ++used;
+            } else {
+                const double dz = zi - h;
+                if (dz * dz > f.tau2 * v) {
+                    if (zi > h) {
+                        h = zi;
+                        v = si;
+                        ++used;
+                    }
+                } else {
+                    h = (v * zi + si * h) / (v + si);
+                    v = (v * si) / (v + si);
+                    ++used;
+                }
+            }
+        }
+        f.height[at] = (float)h;
+        f.variance[at] = (float)v;
+    }
+    int32_t total;
+    block_exclusive_scan(used, used_lds, &total);
+    if (threadIdx.x == 0 && total) atomicAdd(f.n_fused, total);
+}
+
+constexpr int IT = 32;                                  // inpaint tile side
+constexpr int ISPAN = IT + 2 * INPAINT_MAX_RADIUS;      // 64
+
+__global__ __launch_bounds__(256) void inpaint_kernel(const InpaintArgs a) {
+    __shared__ float tile[ISPAN * ISPAN];
+    __shared__ int lin[INPAINT_MAX_OFFS];                 // offsets as tile index steps
+    const int r = a.radius, span = IT + 2 * r;
+    for (int k = threadIdx.x; k < a.n_offs; k += 256) lin[k] = a.offs[k].y * span + a.offs[k].x;
+    const int tiles_x = (a.W + IT - 1) / IT;
+    const int x0 = (blockIdx.x % tiles_x) * IT, y0 = (blockIdx.x / tiles_x) * IT;
+    // Loads from coordinates clamped into the map, the out-of-map test after.
+    for (int i = threadIdx.x; i < span * span; i += 256) {
+        const int rr = i / span, cc = i - rr * span;
+        const int y = y0 - r + rr, x = x0 - r + cc;
+        const int yc = min(max(y, 0), a.H - 1), xc = min(max(x, 0), a.W - 1);
+        const float v = a.src[(int64_t)((yc + a.ry) % a.H) * a.ld + (xc + a.rx) % a.W];
+        const bool in = x >= 0 && x < a.W && y >= 0 && y < a.H;
+        tile[i] = in && isfinite(v) ? v : __builtin_nanf("");
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < IT * IT; i += 256) {
+        const int ly = i / IT, lx = i - ly * IT;
+        const int x = x0 + lx, y = y0 + ly;
+        if (x >= a.W || y >= a.H) continue;
+        const int at = (ly + r) * span + lx + r;
+        float v = tile[at];
+        if (v != v) {
+            for (int k = 0; k < a.n_offs; ++k) {
+                const float t = tile[at + lin[k]];
+                if (t == t) {
+                    v = t;
+                    break;
+                }
+            }
+        }
+        a.dst[(int64_t)((y + a.ry) % a.H) * a.dst_ld + (x + a.rx) % a.W] = v;
+    }
+}
+
+}  // namespace
+
+int64_t partial_blocks(int64_t n_cells) { return (n_cells + SCAN_CHUNK - 1) / SCAN_CHUNK; }
+
+hipError_t launch_fuse_scan(const ScanArgs& s, const FuseArgs& f, const FuseWork& w,
+                            hipStream_t stream) {
+    const int64_t n_cells = (int64_t)f.W * f.H;
+    const int64_t nb = partial_blocks(n_cells);
+    auto grid = [](int64_t items) {
+        return dim3((unsigned)std::min<int64_t>(std::max<int64_t>((items + 255) / 256, 1), 8192));
+    };
+    hipLaunchKernelGGL(clear_kernel, grid(n_cells), dim3(256), 0, stream, w.count, w.fill, n_cells,
+                       f.n_fused);
+    if (s.n > 0) hipLaunchKernelGGL(points_kernel, grid(s.n), dim3(256), 0, stream, s, w);
+    hipLaunchKernelGGL(block_sums_kernel, dim3((unsigned)nb), dim3(256), 0, stream, w.count,
+                       n_cells, w.partial);
+    hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(256), 0, stream, w.partial, nb);
+    hipLaunchKernelGGL(local_scan_kernel, dim3((unsigned)nb), dim3(256), 0, stream, w.count,
+                       n_cells, w.partial, w.offs);
+    if (s.n > 0) hipLaunchKernelGGL(scatter_kernel, grid(s.n), dim3(256), 0, stream, s.n, w);
+    hipLaunchKernelGGL(fuse_kernel, grid(n_cells), dim3(256), 0, stream, f, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_inpaint(const InpaintArgs& a, hipStream_t stream) {
+    const int tiles = ((a.W + IT - 1) / IT) * ((a.H + IT - 1) / IT);
+    hipLaunchKernelGGL(inpaint_kernel, dim3((unsigned)tiles), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace elev
+}  // namespace seb

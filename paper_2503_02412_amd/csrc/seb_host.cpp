@@ -15,6 +15,7 @@
 #include "seb_internal.hpp"
 #include "seb_net_internal.hpp"
 #include "seb_sdf_internal.hpp"
+#include "seb_elevation_internal.hpp"
 #include "seb_surrogate_internal.hpp"
 
 using namespace seb;
@@ -257,7 +258,16 @@ struct seb_ctx {
     float* d_qs = nullptr;
     uint32_t* d_pks = nullptr;
     Segment* d_segs = nullptr;
+    int2* d_inpaint = nullptr;            // (dx, dy) by (dx^2 + dy^2, dy, dx), radius <= 16
+    std::vector<int> inpaint_count;       // offsets within radius r, r = 0 .. 16
     int device = 0;
+};
+
+struct seb_fuser {
+    seb_ctx* ctx;
+    int64_t max_points;
+    std::vector<void*> allocs;
+    elev::FuseWork w;
 };
 
 struct seb_surrogate {
@@ -525,6 +535,23 @@ int seb_create(const seb_config* cfg, seb_ctx** out) {
             rows = rows && g.segs[i].count == cfg->fp_nw && g.segs[i].first == (int)i * cfg->fp_nw;
         if (rows) c->row_len = cfg->fp_nw;
     }
+    // Inpainting offsets, nearest first (ties: smaller dy, then smaller dx).
+    std::vector<int2> ioffs;
+    const int rmax = elev::INPAINT_MAX_RADIUS;
+    for (int dy = -rmax; dy <= rmax; ++dy)
+        for (int dx = -rmax; dx <= rmax; ++dx) {
+            const int d2 = dx * dx + dy * dy;
+            if (d2 > 0 && d2 <= rmax * rmax) ioffs.push_back(make_int2(dx, dy));
+        }
+    std::sort(ioffs.begin(), ioffs.end(), [](const int2& p, const int2& q) {
+        const int dp = p.x * p.x + p.y * p.y, dq = q.x * q.x + q.y * q.y;
+        if (dp != dq) return dp < dq;
+        if (p.y != q.y) return p.y < q.y;
+        return p.x < q.x;
+    });
+    c->inpaint_count.assign(rmax + 1, 0);
+    for (int r = 0; r <= rmax; ++r)
+        for (const int2& o : ioffs) c->inpaint_count[r] += o.x * o.x + o.y * o.y <= r * r;
     hipError_t e;
     auto upload = [&](void** dst, const void* src, size_t bytes) {
         if ((e = hipMalloc(dst, bytes)) != hipSuccess) return false;
@@ -535,7 +562,8 @@ int seb_create(const seb_config* cfg, seb_ctx** out) {
         !upload((void**)&c->d_frac, frac.data(), frac.size() * sizeof(double2)) ||
         !upload((void**)&c->d_qs, qs.data(), qs.size() * sizeof(float)) ||
         !upload((void**)&c->d_pks, pks.data(), pks.size() * sizeof(uint32_t)) ||
-        !upload((void**)&c->d_segs, g.segs.data(), g.segs.size() * sizeof(Segment))) {
+        !upload((void**)&c->d_segs, g.segs.data(), g.segs.size() * sizeof(Segment)) ||
+        !upload((void**)&c->d_inpaint, ioffs.data(), ioffs.size() * sizeof(int2))) {
         const int code = (e == hipErrorOutOfMemory) ? SEB_ERR_ALLOC : SEB_ERR_HIP;
         g_last_error = std::string("table upload: ") + hipGetErrorString(e);
         seb_destroy(c);
@@ -548,7 +576,7 @@ int seb_create(const seb_config* cfg, seb_ctx** out) {
 void seb_destroy(seb_ctx* c) {
     if (!c) return;
     for (void* p : {(void*)c->d_wts, (void*)c->d_offs, (void*)c->d_frac, (void*)c->d_qs,
-                    (void*)c->d_pks, (void*)c->d_segs})
+                    (void*)c->d_pks, (void*)c->d_segs, (void*)c->d_inpaint})
         if (p) (void)hipFree(p);
     delete c;
 }
@@ -774,6 +802,137 @@ int seb_surrogate_infer(seb_surrogate* s, const seb_net* net, const float* heigh
     a.item_box = w.item_box;
     e = launch_assess_flagged(a, s->ctx->pitch, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fallback assessment launch");
+    return SEB_OK;
+}
+
+int seb_fuser_create(seb_ctx* c, int64_t max_points, seb_fuser** out) {
+    if (!out) return fail(SEB_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!c) return fail(SEB_ERR_INVALID, "ctx is NULL");
+    if (max_points < 1 || max_points >= (int64_t(1) << 31))
+        return fail(SEB_ERR_INVALID, "max_points must be in [1, 2^31)");
+    const int64_t n_cells = (int64_t)c->cfg.width * c->cfg.height;
+    if (n_cells >= (int64_t(1) << 31))
+        return fail(SEB_ERR_UNSUPPORTED, "elevation fusion needs W * H < 2^31");
+    seb_fuser* f = new (std::nothrow) seb_fuser();
+    if (!f) return fail(SEB_ERR_ALLOC, "host allocation");
+    f->ctx = c;
+    f->max_points = max_points;
+    auto alloc = [&](void** p, size_t bytes) {
+        if (hipMalloc(p, std::max<size_t>(bytes, 4)) != hipSuccess) return false;
+        f->allocs.push_back(*p);
+        return true;
+    };
+    elev::FuseWork& w = f->w;
+    const size_t np = (size_t)max_points, nc = (size_t)n_cells;
+    if (!alloc((void**)&w.cell, np * 4) || !alloc((void**)&w.z, np * 8) ||
+        !alloc((void**)&w.var, np * 8) || !alloc((void**)&w.bucket, np * 4) ||
+        !alloc((void**)&w.count, nc * 4) || !alloc((void**)&w.fill, nc * 4) ||
+        !alloc((void**)&w.offs, nc * 4) ||
+        !alloc((void**)&w.partial, (size_t)elev::partial_blocks(n_cells) * 4) ||
+        !alloc((void**)&w.n_fused, 4)) {
+        seb_fuser_destroy(f);
+        return fail(SEB_ERR_ALLOC, "fuser workspace allocation");
+    }
+    *out = f;
+    return SEB_OK;
+}
+
+void seb_fuser_destroy(seb_fuser* f) {
+    if (!f) return;
+    for (void* p : f->allocs) (void)hipFree(p);
+    delete f;
+}
+
+int seb_fuse_scan(seb_fuser* f, float* height, float* variance, int64_t ld, int64_t origin_x,
+                  int64_t origin_y, const seb_scan* sc, int32_t* n_fused_dev, void* stream) {
+    if (!f || !height || !variance || !sc)
+        return fail(SEB_ERR_INVALID, "fuser, height, variance and scan must be non-NULL");
+    const seb_config& g = f->ctx->cfg;
+    if (ld < g.width) return fail(SEB_ERR_INVALID, "ld must be >= width");
+    if (sc->n_points < 0 || sc->n_points > f->max_points)
+        return fail(SEB_ERR_INVALID, "n_points outside [0, max_points]");
+    if (sc->n_points > 0 && !sc->points) return fail(SEB_ERR_INVALID, "points is NULL");
+    const double* all[] = {sc->R_B, sc->p_B, sc->R_BS, sc->p_BS, sc->Sigma_R, sc->Sigma_B};
+    const int len[] = {9, 3, 9, 3, 9, 9};
+    for (int k = 0; k < 6; ++k)
+        for (int i = 0; i < len[k]; ++i)
+            if (!std::isfinite(all[k][i])) return fail(SEB_ERR_INVALID, "pose or covariance not finite");
+    if (!(sc->sigma_range > 0.0) || !(sc->sigma_angle >= 0.0) || !(sc->Sigma_B[8] >= 0.0) ||
+        !std::isfinite(sc->sigma_range) || !std::isfinite(sc->sigma_angle))
+        return fail(SEB_ERR_INVALID, "need sigma_range > 0, sigma_angle >= 0, Sigma_B[2][2] >= 0");
+    if (!(sc->z_min <= sc->z_max) || !(sc->mahalanobis > 0.0) || !std::isfinite(sc->mahalanobis))
+        return fail(SEB_ERR_INVALID, "need z_min <= z_max and mahalanobis > 0");
+    if (std::fabs((double)origin_x) > 1e15 || std::fabs((double)origin_y) > 1e15)
+        return fail(SEB_ERR_INVALID, "origin out of range");
+    elev::ScanArgs s;
+    s.pts = sc->points;
+    s.n = sc->n_points;
+    for (int i = 0; i < 9; ++i) {
+        s.A[i] = sc->R_BS[i];
+        s.R[i] = sc->R_B[i];
+        s.SR[i] = sc->Sigma_R[i];
+    }
+    for (int i = 0; i < 3; ++i) {
+        s.a[i] = sc->p_BS[i];
+        s.b[i] = sc->p_B[i];
+        // J_S = (R_B R_BS)^T b3: row 2 of R_B R_BS; g = R_B^T b3: row 2 of R_B
+        s.js[i] = s.R[6] * s.A[i] + s.R[7] * s.A[3 + i] + s.R[8] * s.A[6 + i];
+        s.g[i] = s.R[6 + i];
+    }
+    s.sb22 = sc->Sigma_B[8];
+    s.sr2 = sc->sigma_range * sc->sigma_range;
+    s.sa2 = sc->sigma_angle * sc->sigma_angle;
+    s.zmin = sc->z_min;
+    s.zmax = sc->z_max;
+    s.res = g.resolution;
+    s.W = g.width;
+    s.H = g.height;
+    s.ox = origin_x;
+    s.oy = origin_y;
+    elev::FuseArgs a;
+    a.height = height;
+    a.variance = variance;
+    a.ld = ld;
+    a.W = g.width;
+    a.H = g.height;
+    a.rx = (int32_t)pos_mod(origin_x, g.width);
+    a.ry = (int32_t)pos_mod(origin_y, g.height);
+    a.tau2 = sc->mahalanobis * sc->mahalanobis;
+    a.n_fused = n_fused_dev ? n_fused_dev : f->w.n_fused;
+    hipError_t e = elev::launch_fuse_scan(s, a, f->w, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fusion launch");
+    return SEB_OK;
+}
+
+int seb_inpaint_nearest(seb_ctx* c, const float* height, int64_t ld, int32_t ring_x,
+                        int32_t ring_y, int32_t radius, float* out, int64_t out_ld, void* stream) {
+    if (!c || !height || !out) return fail(SEB_ERR_INVALID, "ctx, height and out must be non-NULL");
+    const seb_config& g = c->cfg;
+    if (ld < g.width || out_ld < g.width) return fail(SEB_ERR_INVALID, "row strides must be >= width");
+    if (ring_x < 0 || ring_x >= g.width || ring_y < 0 || ring_y >= g.height)
+        return fail(SEB_ERR_INVALID, "ring offset outside the map");
+    if (radius < 0 || radius > elev::INPAINT_MAX_RADIUS)
+        return fail(SEB_ERR_INVALID, "radius must be in [0, 16]");
+    const char* h0 = (const char*)height;
+    const char* h1 = (const char*)(height + (int64_t)(g.height - 1) * ld + g.width);
+    const char* o0 = (const char*)out;
+    const char* o1 = (const char*)(out + (int64_t)(g.height - 1) * out_ld + g.width);
+    if (h0 < o1 && o0 < h1) return fail(SEB_ERR_INVALID, "out overlaps height");
+    elev::InpaintArgs a;
+    a.src = height;
+    a.ld = ld;
+    a.dst = out;
+    a.dst_ld = out_ld;
+    a.W = g.width;
+    a.H = g.height;
+    a.rx = ring_x;
+    a.ry = ring_y;
+    a.radius = radius;
+    a.offs = c->d_inpaint;
+    a.n_offs = c->inpaint_count[radius];
+    hipError_t e = elev::launch_inpaint(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "inpaint launch");
     return SEB_OK;
 }
 

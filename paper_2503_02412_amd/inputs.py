@@ -399,3 +399,76 @@ def trajectory_query_poses(n_traj: int, n_per: int, width: int, height: int, res
     x = np.where(small_k, x0 + s * np.cos(h0), x0 + (np.sin(th) - np.sin(h0)) / safe_k)
     y = np.where(small_k, y0 + s * np.sin(h0), y0 - (np.cos(th) - np.cos(h0)) / safe_k)
     return np.stack([x.ravel(), y.ravel(), th.ravel()], 1).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# Elevation-map update: synthetic LiDAR scans.  Points are drawn on a terrain
+# around the robot and expressed in the sensor frame; no occlusion is modelled.
+# --------------------------------------------------------------------------
+
+
+def rotation_zyx(yaw: float, pitch: float, roll: float) -> np.ndarray:
+    """Rz(yaw) Ry(pitch) Rx(roll), float64 [3][3]."""
+    cy, sy = math.cos(yaw), math.sin(yaw)
+    cp, sp = math.cos(pitch), math.sin(pitch)
+    cr, sr = math.cos(roll), math.sin(roll)
+    Rz = np.array([[cy, -sy, 0.0], [sy, cy, 0.0], [0.0, 0.0, 1.0]])
+    Ry = np.array([[cp, 0.0, sp], [0.0, 1.0, 0.0], [-sp, 0.0, cp]])
+    Rx = np.array([[1.0, 0.0, 0.0], [0.0, cr, -sr], [0.0, sr, cr]])
+    return Rz @ Ry @ Rx
+
+
+def synthetic_scan(terrain: np.ndarray, res: float, n_points: int, seed: int, *,
+                   robot_xy=None, max_range: float = 8.0, canopy_frac: float = 0.03,
+                   stray_frac: float = 0.02, origin=(0, 0)) -> dict:
+    """A scan of `terrain` (float32 [H][W], NaN = no return; cell (i, j) of the
+    array is world cell (origin_x + i, origin_y + j)) seen from a robot at
+    robot_xy (world metres; default: the terrain's centre).  Ranges
+    0.3 + (max_range - 0.3) u^2 (denser near the sensor), azimuth uniform,
+    height = the terrain cell's height + N(0, 0.01^2); a fraction of points
+    lies 1-2.5 m above the ground (overhangs), another 4-10 m above (outside
+    any height band).  Returns the points (float32 [n][3], sensor frame; rays
+    onto unknown cells or off the terrain give no point) and the frames and
+    noise model of the scan."""
+    rng = _rng(seed)
+    Ht, Wt = terrain.shape
+    ox, oy = origin
+    if robot_xy is None:
+        robot_xy = ((ox + Wt / 2.0) * res, (oy + Ht / 2.0) * res)
+    rx, ry = robot_xy
+    yaw = rng.uniform(-math.pi, math.pi)
+    pitch, roll = rng.normal(0.0, 0.05, 2)
+    R_B = rotation_zyx(yaw, pitch, roll)
+    ci = min(max(int(math.floor(rx / res)) - ox, 0), Wt - 1)
+    cj = min(max(int(math.floor(ry / res)) - oy, 0), Ht - 1)
+    ground = float(terrain[cj, ci]) if np.isfinite(terrain[cj, ci]) else 0.0
+    p_B = np.array([rx, ry, ground + 0.4])
+    R_BS = rotation_zyx(0.02, -0.03, 0.01)
+    p_BS = np.array([0.15, 0.0, 0.35])
+    r = 0.3 + (max_range - 0.3) * rng.random(n_points) ** 2
+    a = rng.uniform(0.0, 2.0 * math.pi, n_points)
+    wx = rx + r * np.cos(a)
+    wy = ry + r * np.sin(a)
+    i = np.floor(wx / res).astype(np.int64) - ox
+    j = np.floor(wy / res).astype(np.int64) - oy
+    inside = (i >= 0) & (i < Wt) & (j >= 0) & (j < Ht)
+    z = np.full(n_points, np.nan)
+    z[inside] = terrain[j[inside], i[inside]]
+    z = z + rng.normal(0.0, 0.01, n_points)
+    u = rng.random(n_points)
+    z = np.where(u < canopy_frac, z + rng.uniform(1.0, 2.5, n_points), z)
+    z = np.where((u >= canopy_frac) & (u < canopy_frac + stray_frac),
+                 z + rng.uniform(4.0, 10.0, n_points), z)
+    ok = np.isfinite(z)
+    P = np.stack([wx[ok], wy[ok], z[ok]], 1)
+    # sensor frame: R_BS^T (R_B^T (P - p_B) - p_BS)
+    body = (P - p_B) @ R_B
+    sensor = (body - p_BS) @ R_BS
+    return {
+        "points": sensor.astype(np.float32),
+        "R_B": R_B, "p_B": p_B, "R_BS": R_BS, "p_BS": p_BS,
+        "Sigma_R": np.diag([0.002 ** 2, 0.002 ** 2, 0.004 ** 2]),
+        "Sigma_B": np.diag([0.01 ** 2, 0.01 ** 2, 0.02 ** 2]),
+        "sigma_range": 0.02, "sigma_angle": 0.002,
+        "z_min": -3.0, "z_max": 2.0, "mahalanobis": 3.0,
+    }

@@ -9,6 +9,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
+
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libseb.so")
 
@@ -50,6 +52,15 @@ class WindowPlan(C.Structure):
     ]
 
 
+class Scan(C.Structure):
+    _fields_ = [("points", C.c_void_p), ("n_points", C.c_int64),
+                ("R_B", C.c_double * 9), ("p_B", C.c_double * 3),
+                ("R_BS", C.c_double * 9), ("p_BS", C.c_double * 3),
+                ("Sigma_R", C.c_double * 9), ("Sigma_B", C.c_double * 9),
+                ("sigma_range", C.c_double), ("sigma_angle", C.c_double),
+                ("z_min", C.c_double), ("z_max", C.c_double), ("mahalanobis", C.c_double)]
+
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -76,6 +87,12 @@ _SIGS = {
                               C.c_void_p, C.c_void_p]),
     "seb_query_se2": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                 C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "seb_fuser_create": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_void_p)]),
+    "seb_fuser_destroy": (None, [C.c_void_p]),
+    "seb_fuse_scan": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "seb_inpaint_nearest": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
+                                      C.c_int32, C.c_void_p, C.c_int64, C.c_void_p]),
     "seb_strerror": (C.c_char_p, [C.c_int]),
     "seb_last_error": (C.c_char_p, []),
     "seb_version": (C.c_char_p, []),
@@ -243,6 +260,68 @@ class Context:
                                    C.c_void_p(poses.data_ptr()), n, C.c_void_p(out.data_ptr()),
                                    _stream_handle(stream)), "seb_query_se2")
         return out
+
+    def inpaint(self, height, radius: int, ring=(0, 0), out=None, stream=None):
+        """seb_inpaint_nearest: nearest-neighbour fill of unknown cells (a new map)."""
+        import torch
+        _check_map(height, self.params)
+        if out is None:
+            out = torch.empty_like(height)
+        _check_map(out, self.params)
+        _check(lib().seb_inpaint_nearest(self._h, C.c_void_p(height.data_ptr()), height.stride(0),
+                                         int(ring[0]), int(ring[1]), int(radius),
+                                         C.c_void_p(out.data_ptr()), out.stride(0),
+                                         _stream_handle(stream)), "seb_inpaint_nearest")
+        return out
+
+
+class Fuser:
+    """Scan fusion into an elevation map (seb_fuser_* / seb_fuse_scan)."""
+
+    def __init__(self, ctx: Context, max_points: int):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(lib().seb_fuser_create(ctx._h, int(max_points), C.byref(h)), "seb_fuser_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().seb_fuser_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def scan_struct(points, frames: dict) -> Scan:
+        import torch
+        if not (points.is_cuda and points.dtype == torch.float32 and points.is_contiguous()
+                and points.dim() == 2 and points.shape[1] == 3):
+            raise ValueError("points must be a contiguous float32 CUDA tensor [n, 3]")
+        d = lambda k, n: (C.c_double * n)(*[float(v) for v in np.asarray(frames[k]).ravel()])
+        return Scan(points.data_ptr(), points.shape[0], d("R_B", 9), d("p_B", 3), d("R_BS", 9),
+                    d("p_BS", 3), d("Sigma_R", 9), d("Sigma_B", 9), float(frames["sigma_range"]),
+                    float(frames["sigma_angle"]), float(frames["z_min"]), float(frames["z_max"]),
+                    float(frames["mahalanobis"]))
+
+    def fuse(self, height, variance, origin, points, frames: dict, n_fused=None, stream=None):
+        """Fuse a scan (points: float32 CUDA [n, 3], sensor frame) into the ring
+        maps height / variance of the window whose logical (0, 0) is world
+        cell `origin`."""
+        p = self.ctx.params
+        _check_map(height, p)
+        _check_map(variance, p)
+        if height.stride(0) != variance.stride(0):
+            raise ValueError("height and variance must share a row stride")
+        sc = self.scan_struct(points, frames)
+        ptr = None if n_fused is None else n_fused.data_ptr()
+        _check(lib().seb_fuse_scan(self._h, C.c_void_p(height.data_ptr()),
+                                   C.c_void_p(variance.data_ptr()), height.stride(0),
+                                   int(origin[0]), int(origin[1]), C.byref(sc), C.c_void_p(ptr),
+                                   _stream_handle(stream)), "seb_fuse_scan")
 
 
 class Window:
