@@ -8,8 +8,10 @@
 // the cell, a lower one is dropped).  The fold over a cell's points is
 // sequential by nature, so points are grouped by cell and each cell folds its
 // own points in point order: a count per cell (atomics), an exclusive prefix
-// sum, a scatter into per-cell buckets, and one thread per cell that sorts its
-// bucket by point index and folds it.  Every decision (the cell's floor, the
+// sum, a scatter into per-cell buckets, then the fold: a cell with at most 8
+// points is sorted and folded by one thread in registers; a larger one by a
+// workgroup that places its points in LDS by rank (point index) and lets one
+// thread fold them.  Every decision (the cell's floor, the
 // height band, the gate) is taken in FP64 from the same operations, in the
 // same order and without contraction, as the FP64 reference writes them.
 //
@@ -30,15 +32,43 @@ namespace elev {
 namespace {
 
 constexpr int SCAN_CHUNK = 4096;          // cells per prefix-sum block (256 x 16)
+constexpr int SMALL = 8;                  // points a thread folds alone, in registers
+constexpr int CAP = 2048;                 // points a workgroup ranks in LDS
 
 __global__ __launch_bounds__(256) void clear_kernel(int32_t* count, int32_t* fill, int64_t n,
-                                                    int32_t* n_fused) {
+                                                    int32_t* n_fused, int32_t* n_large) {
     const int64_t stride = (int64_t)gridDim.x * 256;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
         count[i] = 0;
         fill[i] = 0;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *n_fused = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *n_fused = 0;
+        *n_large = 0;
+    }
+}
+
+// One point of the fold: the one-dimensional Kalman update with the
+// several-heights rule.  Returns whether the point changed the cell.
+__device__ __forceinline__ bool fold_point(double& h, double& v, double zi, double si, double tau2) {
+#pragma clang fp contract(off)
+    if (!isfinite(h)) {
+        h = zi;
+        v = si;
+        return true;
+    }
+    const double dz = zi - h;
+    if (dz * dz > tau2 * v) {
+        if (zi > h) {
+            h = zi;
+            v = si;
+            return true;
+        }
+        return false;
+    }
+    h = (v * zi + si * h) / (v + si);
+    v = (v * si) / (v + si);
+    return true;
 }
 
 __global__ __launch_bounds__(256) void points_kernel(const ScanArgs s, FuseWork w) {
@@ -182,8 +212,7 @@ __device__ void sort_bucket(int32_t* b, int n) {
     }
 }
 
-__global__ __launch_bounds__(256) void fuse_kernel(const FuseArgs f, FuseWork w) {
-#pragma clang fp contract(off)
+__global__ __launch_bounds__(256) void fuse_small_kernel(const FuseArgs f, FuseWork w) {
     __shared__ int32_t used_lds[256];
     const int64_t n_cells = (int64_t)f.W * f.H;
     const int64_t stride = (int64_t)gridDim.x * 256;
@@ -191,39 +220,88 @@ __global__ __launch_bounds__(256) void fuse_kernel(const FuseArgs f, FuseWork w)
     for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n_cells; c += stride) {
         const int n = w.count[c];
         if (n == 0) continue;
-        int32_t* b = w.bucket + w.offs[c];
-        sort_bucket(b, n);
+        if (n > SMALL) {
+            w.large[atomicAdd(w.n_large, 1)] = (int32_t)c;
+            continue;
+        }
+        // indices (clamped loads, then padding), sorted by an odd-even
+        // transposition network, then every (z, var) load at once
+        const int32_t* b = w.bucket + w.offs[c];
+        int32_t idx[SMALL];
+#pragma unroll
+        for (int k = 0; k < SMALL; ++k) {
+            const int32_t v = b[min(k, n - 1)];
+            idx[k] = k < n ? v : INT32_MAX;
+        }
+#pragma unroll
+        for (int r = 0; r < SMALL; ++r) {
+#pragma unroll
+            for (int k = r & 1; k + 1 < SMALL; k += 2) {
+                const int32_t lo = min(idx[k], idx[k + 1]), hi = max(idx[k], idx[k + 1]);
+                idx[k] = lo;
+                idx[k + 1] = hi;
+            }
+        }
+        double zs[SMALL], ss[SMALL];
+#pragma unroll
+        for (int k = 0; k < SMALL; ++k) {
+            const int32_t i = idx[k < n ? k : 0];
+            zs[k] = w.z[i];
+            ss[k] = w.var[i];
+        }
         const int lx = (int)(c % f.W), ly = (int)(c / f.W);
         const int64_t at = (int64_t)((ly + f.ry) % f.H) * f.ld + (lx + f.rx) % f.W;
         double h = (double)f.height[at], v = (double)f.variance[at];
-        for (int k = 0; k < n; ++k) {
-            const int32_t i = b[k];
-            const double zi = w.z[i], si = w.var[i];
-            if (!isfinite(h)) {
-                h = zi;
-                v = si;
-                ++used;
-            } else {
-                const double dz = zi - h;
-                if (dz * dz > f.tau2 * v) {
-                    if (zi > h) {
-                        h = zi;
-                        v = si;
-                        ++used;
-                    }
-                } else {
-                    h = (v * zi + si * h) / (v + si);
-                    v = (v * si) / (v + si);
-                    ++used;
-                }
-            }
-        }
+#pragma unroll
+        for (int k = 0; k < SMALL; ++k)
+            if (k < n) used += fold_point(h, v, zs[k], ss[k], f.tau2);
         f.height[at] = (float)h;
         f.variance[at] = (float)v;
     }
     int32_t total;
     block_exclusive_scan(used, used_lds, &total);
     if (threadIdx.x == 0 && total) atomicAdd(f.n_fused, total);
+}
+
+// A workgroup per listed cell.  Point indices are distinct, so a point's rank
+// among its cell's indices is its place in the fold.
+__global__ __launch_bounds__(256) void fuse_large_kernel(const FuseArgs f, FuseWork w) {
+    __shared__ int32_t keys[CAP];
+    __shared__ double zs[CAP], ss[CAP];
+    const int n_large = *w.n_large;
+    for (int li = blockIdx.x; li < n_large; li += gridDim.x) {
+        const int32_t c = w.large[li];
+        const int n = w.count[c];
+        int32_t* b = w.bucket + w.offs[c];
+        if (n <= CAP) {
+            for (int e = threadIdx.x; e < n; e += 256) keys[e] = b[e];
+            __syncthreads();
+            for (int e = threadIdx.x; e < n; e += 256) {
+                const int32_t k = keys[e];
+                int rank = 0;
+                for (int j = 0; j < n; ++j) rank += keys[j] < k;
+                zs[rank] = w.z[k];
+                ss[rank] = w.var[k];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (n > CAP) sort_bucket(b, n);            // rare: in place in HBM
+            const int lx = c % f.W, ly = c / f.W;
+            const int64_t at = (int64_t)((ly + f.ry) % f.H) * f.ld + (lx + f.rx) % f.W;
+            double h = (double)f.height[at], v = (double)f.variance[at];
+            int32_t used = 0;
+            for (int k = 0; k < n; ++k) {
+                const double zi = n <= CAP ? zs[k] : w.z[b[k]];
+                const double si = n <= CAP ? ss[k] : w.var[b[k]];
+                used += fold_point(h, v, zi, si, f.tau2);
+            }
+            f.height[at] = (float)h;
+            f.variance[at] = (float)v;
+            if (used) atomicAdd(f.n_fused, used);
+        }
+        __syncthreads();
+    }
 }
 
 constexpr int IT = 32;                                  // inpaint tile side
@@ -277,7 +355,7 @@ hipError_t launch_fuse_scan(const ScanArgs& s, const FuseArgs& f, const FuseWork
         return dim3((unsigned)std::min<int64_t>(std::max<int64_t>((items + 255) / 256, 1), 8192));
     };
     hipLaunchKernelGGL(clear_kernel, grid(n_cells), dim3(256), 0, stream, w.count, w.fill, n_cells,
-                       f.n_fused);
+                       f.n_fused, w.n_large);
     if (s.n > 0) hipLaunchKernelGGL(points_kernel, grid(s.n), dim3(256), 0, stream, s, w);
     hipLaunchKernelGGL(block_sums_kernel, dim3((unsigned)nb), dim3(256), 0, stream, w.count,
                        n_cells, w.partial);
@@ -285,7 +363,8 @@ hipError_t launch_fuse_scan(const ScanArgs& s, const FuseArgs& f, const FuseWork
     hipLaunchKernelGGL(local_scan_kernel, dim3((unsigned)nb), dim3(256), 0, stream, w.count,
                        n_cells, w.partial, w.offs);
     if (s.n > 0) hipLaunchKernelGGL(scatter_kernel, grid(s.n), dim3(256), 0, stream, s.n, w);
-    hipLaunchKernelGGL(fuse_kernel, grid(n_cells), dim3(256), 0, stream, f, w);
+    hipLaunchKernelGGL(fuse_small_kernel, grid(n_cells), dim3(256), 0, stream, f, w);
+    hipLaunchKernelGGL(fuse_large_kernel, dim3(1024), dim3(256), 0, stream, f, w);
     return hipGetLastError();
 }
 

@@ -40,6 +40,8 @@ struct FuseWork {
     int32_t* fill;           // [W*H]
     int32_t* offs;           // [W*H] exclusive prefix sum of count
     int32_t* partial;        // [partial_blocks(W*H)]
+    int32_t* large;          // [W*H] cells with more points than a thread folds alone
+    int32_t* n_large;        // [1]
     int32_t* n_fused;        // [1] internal counter when the caller passes none
 };
 

@@ -830,6 +830,7 @@ int seb_fuser_create(seb_ctx* c, int64_t max_points, seb_fuser** out) {
         !alloc((void**)&w.count, nc * 4) || !alloc((void**)&w.fill, nc * 4) ||
         !alloc((void**)&w.offs, nc * 4) ||
         !alloc((void**)&w.partial, (size_t)elev::partial_blocks(n_cells) * 4) ||
+        !alloc((void**)&w.large, nc * 4) || !alloc((void**)&w.n_large, 4) ||
         !alloc((void**)&w.n_fused, 4)) {
         seb_fuser_destroy(f);
         return fail(SEB_ERR_ALLOC, "fuser workspace allocation");

@@ -93,8 +93,9 @@ def test_fuse_matches_oracle(W, H, res, n_points, origin):
 
 
 def test_fuse_crowded_cell_and_edges():
-    """Thousands of points in one cell (the long-bucket sort), an empty scan,
-    and a scan whose points all miss the window."""
+    """Crowded cells (folded by a workgroup from LDS), 3000 points in one cell
+    (beyond what a workgroup ranks in LDS: sorted in place), an empty scan, and
+    a scan whose points all miss the window."""
     import torch
     W, H, res = 64, 48, 0.1
     p = small(W, H, res)
@@ -113,11 +114,18 @@ def test_fuse_crowded_cell_and_edges():
         assert same(hr.cpu().numpy(), h)
         assert gpu_fuse(fuser, hr, vr, scan, (10_000, 0)) == 0   # window far away
         assert same(hr.cpu().numpy(), h) and same(vr.cpu().numpy(), v)
+        # 3000 returns within one cell: more than a workgroup ranks in LDS
+        rng = np.random.default_rng(6)
+        one = scan["points"][:1] + rng.normal(0.0, 1e-3, (3000, 3)).astype(np.float32)
+        one_scan = dict(scan, points=one.astype(np.float32))
+        h, v, used = oracle_fuse(h, v, one_scan, p, (0, 0))
+        assert gpu_fuse(fuser, hr, vr, one_scan, (0, 0)) == used
+        assert same(hr.cpu().numpy(), h) and same(vr.cpu().numpy(), v)
         fuser.close()
     counts = np.bincount(E.process_points(scan["points"], scan["R_B"], scan["p_B"], scan["R_BS"],
                                           scan["p_BS"], scan["Sigma_R"], scan["Sigma_B"], 0.02,
                                           0.002, -3, 2, res, W, H, 0, 0)[0] + 1)
-    assert counts[1:].max() > 32                   # some bucket took the heapsort
+    assert counts[1:].max() > 8                    # some cells took the workgroup path
 
 
 def test_fuse_rejects_bad_arguments():
