@@ -14,6 +14,8 @@ What it computes (Sec. V-A of the paper):
   - the points falling into one map cell update that cell's height and
     variance with a one-dimensional Kalman filter, with the classical
     elevation map's Mahalanobis test for several heights in one cell;
+  - cells standing higher than a ray that passes through them are reset to
+    unknown (ray casting);
   - unknown cells are filled from the nearest known cell (nearest-neighbour
     inpainting, the method of the experiments).
 
@@ -38,6 +40,12 @@ Readings (the paper leaves these open; the library uses the same ones):
     an unknown cell (non-finite height) takes the point as it is.  The fold
     runs in FP64 and the cell's float32 height and variance are written at
     the end;
+  - ray casting: before the points are fused, each finite point's segment
+    from the sensor (R_B p_BS + p_B) resets the known cells it crosses --
+    cells its xy projection passes through with a parameter interval
+    t0 < t1 by slab clipping, other than the point's own cell -- whose height
+    exceeds max(z(t0), z(t1)) + margin; decisions use the heights before the
+    scan, so the result is a union and does not depend on ray order;
   - inpainting: an unknown cell takes the height of the known cell with the
     smallest (dx^2 + dy^2, dy, dx) within the radius (dx, dy signed, ring
     order irrelevant: logical coordinates); none within it: stays unknown,
@@ -171,3 +179,78 @@ def inpaint_nearest(height: np.ndarray, radius: int) -> np.ndarray:
         order = np.lexsort((dx[sel], dy[sel], d2[sel]))
         out[y, x] = Hm[y0 + ky[sel][order[0]], x0 + kx[sel][order[0]]]
     return out
+
+
+def sensor_origin(R_B, p_B, p_BS):
+    """Map-frame position of the sensor: R_B p_BS + p_B."""
+    R, b, a = _mat(R_B), _vec(p_B), _vec(p_BS)
+    return (R[0, 0] * a[0] + R[0, 1] * a[1] + R[0, 2] * a[2] + b[0],
+            R[1, 0] * a[0] + R[1, 1] * a[1] + R[1, 2] * a[2] + b[1],
+            R[2, 0] * a[0] + R[2, 1] * a[1] + R[2, 2] * a[2] + b[2])
+
+
+def map_points(points, R_B, p_B, R_BS, p_BS):
+    """Map-frame coordinates of sensor-frame points (the same operations as
+    process_points)."""
+    P = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    px, py, pz = P[:, 0], P[:, 1], P[:, 2]
+    A, a = _mat(R_BS), _vec(p_BS)
+    R, b = _mat(R_B), _vec(p_B)
+    q0 = A[0, 0] * px + A[0, 1] * py + A[0, 2] * pz + a[0]
+    q1 = A[1, 0] * px + A[1, 1] * py + A[1, 2] * pz + a[1]
+    q2 = A[2, 0] * px + A[2, 1] * py + A[2, 2] * pz + a[2]
+    lx = R[0, 0] * q0 + R[0, 1] * q1 + R[0, 2] * q2 + b[0]
+    ly = R[1, 0] * q0 + R[1, 1] * q1 + R[1, 2] * q2 + b[1]
+    lz = R[2, 0] * q0 + R[2, 1] * q1 + R[2, 2] * q2 + b[2]
+    return lx, ly, lz
+
+
+def _slab(c, res, s, d):
+    """Parameter interval [lo, hi] of s + t d inside [c res, (c + 1) res) along
+    one axis (d == 0: everything or nothing)."""
+    c = np.asarray(c, dtype=np.float64)
+    lo_edge, hi_edge = c * res, (c + 1.0) * res
+    if d != 0.0:
+        t1 = (lo_edge - s) / d
+        t2 = (hi_edge - s) / d
+        return np.minimum(t1, t2), np.maximum(t1, t2)
+    inside = (lo_edge <= s) & (s < hi_edge)
+    return np.where(inside, -np.inf, np.inf), np.where(inside, np.inf, -np.inf)
+
+
+def raycast_reset(height, points, R_B, p_B, R_BS, p_BS, res, origin_x, origin_y, margin):
+    """Ray-casting reset (Sec. V-A): a known cell crossed by the segment from
+    the sensor to a point (its projection passing through the cell's
+    interior), other than the point's own cell, becomes unknown if its height
+    exceeds the segment's highest z over the crossing by more than `margin`.
+    Decided against the heights before the scan; returns (new map, number of
+    cells reset).  Brute force over each ray's bounding box of cells."""
+    Hm = np.asarray(height, dtype=np.float32)
+    Hn, Wn = Hm.shape
+    sx, sy, sz = sensor_origin(R_B, p_B, p_BS)
+    lx, ly, lz = map_points(points, R_B, p_B, R_BS, p_BS)
+    reset = np.zeros(Hm.shape, dtype=bool)
+    si, sj = math.floor(sx / res), math.floor(sy / res)
+    for ex, ey, ez in zip(lx, ly, lz):
+        if not (math.isfinite(ex) and math.isfinite(ey) and math.isfinite(ez)):
+            continue
+        ei, ej = math.floor(ex / res), math.floor(ey / res)
+        i0, i1 = max(min(si, ei), origin_x), min(max(si, ei), origin_x + Wn - 1)
+        j0, j1 = max(min(sj, ej), origin_y), min(max(sj, ej), origin_y + Hn - 1)
+        if i0 > i1 or j0 > j1:
+            continue
+        jj, ii = np.mgrid[j0:j1 + 1, i0:i1 + 1]
+        dx, dy, dz = ex - sx, ey - sy, ez - sz
+        xlo, xhi = _slab(ii, res, sx, dx)
+        ylo, yhi = _slab(jj, res, sy, dy)
+        t0 = np.maximum(np.maximum(xlo, ylo), 0.0)
+        t1 = np.minimum(np.minimum(xhi, yhi), 1.0)
+        crossed = (t1 > t0) & ~((ii == ei) & (jj == ej))
+        zmax = np.maximum(sz + t0 * dz, sz + t1 * dz)
+        h = Hm[jj - origin_y, ii - origin_x].astype(np.float64)
+        with np.errstate(invalid="ignore"):
+            hit = crossed & (h > zmax + margin)
+        reset[jj[hit] - origin_y, ii[hit] - origin_x] = True
+    out = Hm.copy()
+    out[reset] = np.nan
+    return out, int(reset.sum())

@@ -166,3 +166,94 @@ def test_inpaint_tie_break():
     h[1, 2] = np.nan
     out = E.inpaint_nearest(h, 2)
     assert out[2, 2] == np.float32(3.0)  # dy = 0, dx = -1 before dx = +1 and dy = +1
+
+
+def ray(H, sensor, pts_map, margin=0.0, res=0.1, ox=0, oy=0):
+    """Identity frames: the robot (and sensor) at `sensor`, points given in
+    map coordinates."""
+    pts = np.asarray(pts_map, dtype=np.float64) - np.asarray(sensor)
+    return E.raycast_reset(H, pts, I3, sensor, I3, (0, 0, 0), res, ox, oy, margin)
+
+
+def test_raycast_level_ray():
+    H = np.full((3, 12), 0.5, np.float32)
+    H[0, 3] = H[0, 7] = H[0, 10] = 2.0
+    out, n = ray(H, (0.05, 0.05, 1.0), [[1.05, 0.05, 1.0]])
+    assert n == 2 and np.isnan(out[0, 3]) and np.isnan(out[0, 7])
+    assert out[0, 10] == 2.0                           # the point's own cell is kept
+    assert np.array_equal(out[1:], H[1:])
+
+
+def test_raycast_sloped_ray_threshold_and_margin():
+    # from z = 2 at x = 0.05 down to z = 0 at x = 1.05: the ray is highest where
+    # it enters cell i, at 2.1 - 0.2 i (cell 0: 2.0, where it starts)
+    H = np.full((1, 12), -5.0, np.float32)
+    top = [2.0] + [2.1 - 0.2 * i for i in range(1, 10)]
+    for i in range(10):
+        H[0, i] = top[i] + (0.01 if i % 2 else -0.01)
+    out, n = ray(H, (0.05, 0.05, 2.0), [[1.05, 0.05, 0.0]])
+    assert n == 5 and all(np.isnan(out[0, i]) == bool(i % 2) for i in range(10))
+    out, n = ray(H, (0.05, 0.05, 2.0), [[1.05, 0.05, 0.0]], margin=0.02)
+    assert n == 0
+
+
+def test_raycast_corner_touch_and_vertical_ray():
+    H = np.full((6, 6), 5.0, np.float32)
+    out, n = ray(H, (0.05, 0.05, 1.0), [[0.35, 0.35, 1.0]])
+    # the diagonal passes the corners exactly: only (0,0), (1,1), (2,2) are crossed;
+    # (3,3) is the point's own cell
+    reset = np.isnan(out)
+    assert n == 3 and reset[0, 0] and reset[1, 1] and reset[2, 2] and reset.sum() == 3
+    out, n = ray(H, (0.05, 0.05, 1.0), [[0.05, 0.55, 1.0]])
+    assert n == 5 and np.isnan(out[:5, 0]).all() and out[5, 0] == 5.0
+
+
+def test_raycast_matches_dense_sampling():
+    """One random ray at a time against the segment sampled densely: a crossed
+    cell standing clearly above the sampled ray is reset, one below is not."""
+    rng = np.random.default_rng(21)
+    res, Hn, Wn = 0.1, 30, 40
+    for _ in range(60):
+        H = rng.uniform(-1.0, 1.0, (Hn, Wn)).astype(np.float32)
+        s = (rng.uniform(0.5, 3.5), rng.uniform(0.5, 2.5), rng.uniform(-0.5, 1.0))
+        e = (rng.uniform(0.0, 4.0), rng.uniform(0.0, 3.0), rng.uniform(-1.0, 0.5))
+        out, _ = ray(H, s, [e])
+        t = np.linspace(0.0, 1.0, 40001)
+        x = s[0] + t * (e[0] - s[0])
+        y = s[1] + t * (e[1] - s[1])
+        z = s[2] + t * (e[2] - s[2])
+        ci, cj = np.floor(x / res).astype(int), np.floor(y / res).astype(int)
+        own = (math.floor(e[0] / res), math.floor(e[1] / res))
+        zs = {}
+        for i, j, zz in zip(ci, cj, z):
+            if (i, j) != own and 0 <= i < Wn and 0 <= j < Hn:
+                zs[(i, j)] = max(zs.get((i, j), -np.inf), zz)
+        slack = abs(e[2] - s[2]) / 40000 + 1e-9
+        for (i, j), zz in zs.items():
+            if H[j, i] > zz + slack:
+                assert np.isnan(out[j, i])
+            elif H[j, i] < zz:
+                assert out[j, i] == H[j, i]
+        untouched = np.ones((Hn, Wn), bool)
+        for (i, j) in zs:
+            untouched[j, i] = False
+        # a cell the samples never entered is crossed for less than 1/40000 of the ray
+        assert np.isnan(out[untouched]).sum() <= 2
+
+
+def test_raycast_sensor_cell_and_mounting():
+    # the ray starts at the sensor: in the sensor's own cell it is highest at t = 0
+    H = np.full((1, 12), -5.0, np.float32)
+    H[0, 0] = 2.05
+    out, n = ray(H, (0.05, 0.05, 2.0), [[1.05, 0.05, 0.0]])
+    assert n == 1 and np.isnan(out[0, 0])
+    # the sensor sits at R_B p_BS + p_B: a robot turned by 90 degrees with the
+    # sensor mounted 0.5 m to its left puts it at (0.05, 0.05, 1.0)
+    R_B = Rotation.from_euler("z", 90, degrees=True).as_matrix()
+    p_B, p_BS = np.array([0.55, 0.05, 0.0]), np.array([0.0, 0.5, 1.0])
+    P = np.array([[1.05, 0.05, 1.0]])
+    pts = (P - p_B) @ R_B - p_BS                      # sensor frame, with R_BS = I
+    H = np.full((3, 12), 0.5, np.float32)
+    H[0, 3] = H[0, 7] = H[0, 10] = 2.0
+    out, n = E.raycast_reset(H, pts, R_B, p_B, I3, p_BS, 0.1, 0, 0, 0.0)
+    assert n == 2 and np.isnan(out[0, 3]) and np.isnan(out[0, 7]) and out[0, 10] == 2.0
