@@ -184,10 +184,11 @@ def bench_sdf(torch, seb, n_poses: int = 1 << 20):
 
 def bench_elevation(torch, seb, n_points: int = 200_000):
     """The map update that precedes the assessment (Sec. V-A), on the 400 x 400
-    @ 0.05 m window: one 200k-point synthetic scan fused into a map that knows
-    95% of its cells, nearest-neighbour inpainting (radius 8 cells), and the
-    whole per-scan step fuse -> inpaint -> assess (72 yaw bins).  Inpainting is
-    also timed on the 800 x 800 map with 15% holes."""
+    @ 0.05 m window: the ray-casting reset of a 200k-point synthetic scan, its
+    fusion into a map that knows 95% of its cells, nearest-neighbour
+    inpainting (radius 8 cells), and the whole per-scan step ray casting ->
+    fuse -> inpaint -> assess (72 yaw bins).  Inpainting is also timed on the
+    800 x 800 map with 15% holes."""
     p = I.CONFIG3
     W, H, res = p.width, p.height, p.resolution
     terrain = I.fractal_terrain(W, H, res, seed=800, hole_frac=0.05)
@@ -200,11 +201,16 @@ def bench_elevation(torch, seb, n_points: int = 200_000):
     n = torch.zeros(1, dtype=torch.int32, device="cuda")
     fuse_ms = time_launches(torch, lambda: fuser.fuse(h, v, (0, 0), pts, scan, n_fused=n), 50, 5)
     fused = int(n.item())
+    stale = torch.from_numpy(terrain).cuda()
+    nr = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ray_ms = time_launches(torch, lambda: ctx.raycast_reset(stale, (0, 0), pts, scan, 0.0,
+                                                            n_reset=nr), 50, 5)
     filled = torch.empty_like(h)
     inp_ms = time_launches(torch, lambda: ctx.inpaint(h, 8, out=filled), 50, 5)
     out = seb.alloc_outputs(p)
 
     def step():
+        ctx.raycast_reset(h, (0, 0), pts, scan, 0.0, n_reset=nr)
         fuser.fuse(h, v, (0, 0), pts, scan, n_fused=n)
         ctx.inpaint(h, 8, out=filled)
         ctx.assess(filled, out)
@@ -224,11 +230,13 @@ def bench_elevation(torch, seb, n_points: int = 200_000):
         "points_changing_a_cell": fused,
         # algorithmic bytes: 12 per point in, 8 read + 8 written per updated cell (bounded by points)
         "fuse_gbps": (12 * n_pts + 16 * fused) / (fuse_ms * 1e-3) / 1e9,
+        "raycast_ms": ray_ms, "raycast_rays_per_s": n_pts / (ray_ms * 1e-3),
         "inpaint_ms": inp_ms, "inpaint_gbps": 8 * W * H / (inp_ms * 1e-3) / 1e9,
         "inpaint_800x800_15pct_holes_ms": inp5_ms,
         "inpaint_800x800_gbps": 8 * p5.width * p5.height / (inp5_ms * 1e-3) / 1e9,
         "scan_step_ms": step_ms,
-        "scan_step_note": "fuse + inpaint + full assessment of 400x400x72 states",
+        "scan_step_note": "ray-casting reset + fuse + inpaint + full assessment of 400x400x72 "
+                          "states",
     }
 
 

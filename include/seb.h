@@ -312,6 +312,22 @@ void seb_fuser_destroy(seb_fuser* f);
 int seb_fuse_scan(seb_fuser* f, float* height, float* variance, int64_t ld, int64_t origin_x,
                   int64_t origin_y, const seb_scan* scan, int32_t* n_fused_dev, void* stream);
 
+/* Ray-casting reset (Sec. V-A), run before the scan is fused: every finite
+ * point's segment from the sensor (R_B p_BS + p_B) to the point, in the map
+ * frame, resets to unknown (NaN) each known cell it crosses -- a cell whose
+ * interior its xy projection enters, i.e. whose slab-clipped parameter
+ * interval satisfies t0 < t1 -- other than the point's own cell, when the
+ * cell's height exceeds the segment's highest z over the crossing,
+ * max(z(t0), z(t1)), by more than margin (metres, >= 0; 0 is the literal
+ * test).  Decisions use the heights before the call, so the result does not
+ * depend on ray order.  height: device [H][W] float32, row stride ld, ring
+ * storage of the window whose logical (0, 0) is world cell (origin_x,
+ * origin_y), as for seb_fuse_scan; only scan->points, n_points, R_B, p_B,
+ * R_BS and p_BS are read.  *n_reset_dev (device int32, may be NULL) receives
+ * the number of cells reset.  Errors: SEB_ERR_INVALID.  Allocates nothing. */
+int seb_raycast_reset(seb_ctx* ctx, float* height, int64_t ld, int64_t origin_x, int64_t origin_y,
+                      const seb_scan* scan, double margin, int32_t* n_reset_dev, void* stream);
+
 /* Nearest-neighbour inpainting (the method the experiments use; Sec. V-A
  * leaves the inpainter open): every unknown (non-finite) cell of `height`
  * takes the height of the known cell with the smallest (dx^2 + dy^2, dy, dx)

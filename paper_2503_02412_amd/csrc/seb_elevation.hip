@@ -15,6 +15,15 @@
 // height band, the gate) is taken in FP64 from the same operations, in the
 // same order and without contraction, as the FP64 reference writes them.
 //
+// Before fusion, each point's ray from the sensor resets to unknown the known
+// cells it crosses (its xy projection entering their interior), other than the
+// point's own cell, that stand higher than the ray over the crossing.  A ray
+// walks its cells with a DDA clipped to the window, also trying both
+// neighbours where it passes within 1e-9 (in ray parameter) of a corner, and
+// decides every candidate with the same slab clipping as the reference.  A
+// reset is a compare-and-swap to NaN, so each cell counts once and the result
+// is a union that no ray order changes.
+//
 // Unknown cells can then be filled from the nearest known cell within a
 // radius (nearest-neighbour inpainting, the method of the experiments), from
 // an LDS tile with a halo of that radius and a list of offsets sorted by
@@ -304,6 +313,129 @@ __global__ __launch_bounds__(256) void fuse_large_kernel(const FuseArgs f, FuseW
     }
 }
 
+// Parameter interval of s + t d inside cell c along one axis.
+__device__ __forceinline__ void slab(int64_t c, double res, double s, double d, double& lo,
+                                     double& hi) {
+#pragma clang fp contract(off)
+    const double e0 = (double)c * res, e1 = ((double)c + 1.0) * res;
+    if (d != 0.0) {
+        const double t1 = (e0 - s) / d, t2 = (e1 - s) / d;
+        lo = fmin(t1, t2);
+        hi = fmax(t1, t2);
+    } else {
+        const bool in = e0 <= s && s < e1;
+        lo = in ? -INFINITY : INFINITY;
+        hi = in ? INFINITY : -INFINITY;
+    }
+}
+
+struct Ray {
+    double dx, dy, dz;
+    int64_t ei, ej;          // the point's own cell
+    int64_t i0, i1, j0, j1;  // cells between the sensor's and the point's
+};
+
+__device__ __forceinline__ int ray_cell(const RayArgs& r, const Ray& q, int64_t i, int64_t j) {
+#pragma clang fp contract(off)
+    if (i < r.ox || i >= r.ox + r.W || j < r.oy || j >= r.oy + r.H) return 0;
+    if (i < q.i0 || i > q.i1 || j < q.j0 || j > q.j1) return 0;
+    if (i == q.ei && j == q.ej) return 0;
+    double xlo, xhi, ylo, yhi;
+    slab(i, r.res, r.sx, q.dx, xlo, xhi);
+    slab(j, r.res, r.sy, q.dy, ylo, yhi);
+    const double t0 = fmax(fmax(xlo, ylo), 0.0);
+    const double t1 = fmin(fmin(xhi, yhi), 1.0);
+    if (!(t1 > t0)) return 0;
+    const double zmax = fmax(r.sz + t0 * q.dz, r.sz + t1 * q.dz);
+    const int lx = (int)(i - r.ox), ly = (int)(j - r.oy);
+    float* p = r.height + (int64_t)((ly + r.ry) % r.H) * r.ld + (lx + r.rx) % r.W;
+    const float h = *p;
+    if (!((double)h > zmax + r.margin)) return 0;
+    const unsigned int old = __float_as_uint(h);
+    return atomicCAS(reinterpret_cast<unsigned int*>(p), old, 0x7FC00000u) == old;
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(int32_t* v) { *v = 0; }
+
+__global__ __launch_bounds__(256) void raycast_kernel(const RayArgs r) {
+#pragma clang fp contract(off)
+    __shared__ int32_t cnt_lds[256];
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    const double X0 = (double)r.ox * r.res, X1 = (double)(r.ox + r.W) * r.res;
+    const double Y0 = (double)r.oy * r.res, Y1 = (double)(r.oy + r.H) * r.res;
+    int32_t count = 0;
+    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < r.n; n += stride) {
+        const double px = r.pts[3 * n], py = r.pts[3 * n + 1], pz = r.pts[3 * n + 2];
+        const double q0 = r.A[0] * px + r.A[1] * py + r.A[2] * pz + r.a[0];
+        const double q1 = r.A[3] * px + r.A[4] * py + r.A[5] * pz + r.a[1];
+        const double q2 = r.A[6] * px + r.A[7] * py + r.A[8] * pz + r.a[2];
+        const double lx = r.R[0] * q0 + r.R[1] * q1 + r.R[2] * q2 + r.b[0];
+        const double ly = r.R[3] * q0 + r.R[4] * q1 + r.R[5] * q2 + r.b[1];
+        const double lz = r.R[6] * q0 + r.R[7] * q1 + r.R[8] * q2 + r.b[2];
+        if (!isfinite(lx) || !isfinite(ly) || !isfinite(lz)) continue;
+        Ray q;
+        q.dx = lx - r.sx;
+        q.dy = ly - r.sy;
+        q.dz = lz - r.sz;
+        const double big = 1e15;
+        q.ei = (int64_t)fmin(fmax(floor(lx / r.res), -big), big);
+        q.ej = (int64_t)fmin(fmax(floor(ly / r.res), -big), big);
+        const int64_t si = (int64_t)floor(r.sx / r.res), sj = (int64_t)floor(r.sy / r.res);
+        q.i0 = min(si, q.ei);
+        q.i1 = max(si, q.ei);
+        q.j0 = min(sj, q.ej);
+        q.j1 = max(sj, q.ej);
+        // the part of the segment inside the window, [ta, tb]
+        double ta = 0.0, tb = 1.0;
+        if (q.dx != 0.0) {
+            const double t1 = (X0 - r.sx) / q.dx, t2 = (X1 - r.sx) / q.dx;
+            ta = fmax(ta, fmin(t1, t2));
+            tb = fmin(tb, fmax(t1, t2));
+        } else if (!(X0 <= r.sx && r.sx < X1)) {
+            continue;
+        }
+        if (q.dy != 0.0) {
+            const double t1 = (Y0 - r.sy) / q.dy, t2 = (Y1 - r.sy) / q.dy;
+            ta = fmax(ta, fmin(t1, t2));
+            tb = fmin(tb, fmax(t1, t2));
+        } else if (!(Y0 <= r.sy && r.sy < Y1)) {
+            continue;
+        }
+        if (!(tb >= ta)) continue;
+        const double xa = r.sx + ta * q.dx, ya = r.sy + ta * q.dy;
+        int64_t i = (int64_t)floor(xa / r.res), j = (int64_t)floor(ya / r.res);
+        i = i < r.ox ? r.ox : (i >= r.ox + r.W ? r.ox + r.W - 1 : i);
+        j = j < r.oy ? r.oy : (j >= r.oy + r.H ? r.oy + r.H - 1 : j);
+        const int step_x = q.dx > 0.0 ? 1 : (q.dx < 0.0 ? -1 : 0);
+        const int step_y = q.dy > 0.0 ? 1 : (q.dy < 0.0 ? -1 : 0);
+        double tmx = q.dx != 0.0 ? ((double)(i + (step_x > 0)) * r.res - r.sx) / q.dx : INFINITY;
+        double tmy = q.dy != 0.0 ? ((double)(j + (step_y > 0)) * r.res - r.sy) / q.dy : INFINITY;
+        const double tdx = q.dx != 0.0 ? r.res / fabs(q.dx) : INFINITY;
+        const double tdy = q.dy != 0.0 ? r.res / fabs(q.dy) : INFINITY;
+        for (int s = 0; s < r.W + r.H + 4; ++s) {
+            count += ray_cell(r, q, i, j);
+            if (fabs(tmx - tmy) <= 1e-9) {       // near a corner: both neighbours
+                count += ray_cell(r, q, i + step_x, j);
+                count += ray_cell(r, q, i, j + step_y);
+            }
+            if (fmin(tmx, tmy) > tb + 1e-9) break;
+            if (tmx < tmy) {
+                i += step_x;
+                tmx += tdx;
+            } else {
+                j += step_y;
+                tmy += tdy;
+            }
+            if (i < r.ox || i >= r.ox + r.W || j < r.oy || j >= r.oy + r.H) break;
+        }
+    }
+    if (r.n_reset) {
+        int32_t total;
+        block_exclusive_scan(count, cnt_lds, &total);
+        if (threadIdx.x == 0 && total) atomicAdd(r.n_reset, total);
+    }
+}
+
 constexpr int IT = 32;                                  // inpaint tile side
 constexpr int ISPAN = IT + 2 * INPAINT_MAX_RADIUS;      // 64
 
@@ -365,6 +497,15 @@ hipError_t launch_fuse_scan(const ScanArgs& s, const FuseArgs& f, const FuseWork
     if (s.n > 0) hipLaunchKernelGGL(scatter_kernel, grid(s.n), dim3(256), 0, stream, s.n, w);
     hipLaunchKernelGGL(fuse_small_kernel, grid(n_cells), dim3(256), 0, stream, f, w);
     hipLaunchKernelGGL(fuse_large_kernel, dim3(1024), dim3(256), 0, stream, f, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_raycast(const RayArgs& r, hipStream_t stream) {
+    if (r.n_reset) hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(1), 0, stream, r.n_reset);
+    if (r.n > 0) {
+        const unsigned blocks = (unsigned)std::min<int64_t>((r.n + 255) / 256, 4096);
+        hipLaunchKernelGGL(raycast_kernel, dim3(blocks), dim3(256), 0, stream, r);
+    }
     return hipGetLastError();
 }
 

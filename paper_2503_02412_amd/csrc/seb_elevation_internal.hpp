@@ -59,6 +59,23 @@ struct FuseArgs {
 hipError_t launch_fuse_scan(const ScanArgs& s, const FuseArgs& f, const FuseWork& w,
                             hipStream_t stream);
 
+// Ray-casting reset: the scan's rays against the heights in ring storage.
+struct RayArgs {
+    const float* pts;        // [n][3] sensor frame
+    int64_t n;
+    double A[9], a[3];       // R_BS, p_BS
+    double R[9], b[3];       // R_B, p_B
+    double sx, sy, sz;       // sensor origin R_B p_BS + p_B (map frame)
+    double res, margin;
+    int32_t W, H, rx, ry;
+    int64_t ox, oy;          // world cell of logical (0, 0)
+    float* height;           // [H][ld] ring storage
+    int64_t ld;
+    int32_t* n_reset;        // device counter or null
+};
+
+hipError_t launch_raycast(const RayArgs& r, hipStream_t stream);
+
 struct InpaintArgs {
     const float* src;        // [H][ld] ring storage
     int64_t ld;

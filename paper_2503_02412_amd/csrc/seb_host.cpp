@@ -906,6 +906,53 @@ int seb_fuse_scan(seb_fuser* f, float* height, float* variance, int64_t ld, int6
     return SEB_OK;
 }
 
+int seb_raycast_reset(seb_ctx* c, float* height, int64_t ld, int64_t origin_x, int64_t origin_y,
+                      const seb_scan* sc, double margin, int32_t* n_reset_dev, void* stream) {
+    if (!c || !height || !sc) return fail(SEB_ERR_INVALID, "ctx, height and scan must be non-NULL");
+    const seb_config& g = c->cfg;
+    if (ld < g.width) return fail(SEB_ERR_INVALID, "ld must be >= width");
+    if (sc->n_points < 0 || sc->n_points >= (int64_t(1) << 40))
+        return fail(SEB_ERR_INVALID, "n_points out of range");
+    if (sc->n_points > 0 && !sc->points) return fail(SEB_ERR_INVALID, "points is NULL");
+    const double* all[] = {sc->R_B, sc->p_B, sc->R_BS, sc->p_BS};
+    const int len[] = {9, 3, 9, 3};
+    for (int k = 0; k < 4; ++k)
+        for (int i = 0; i < len[k]; ++i)
+            if (!std::isfinite(all[k][i])) return fail(SEB_ERR_INVALID, "pose not finite");
+    if (!(margin >= 0.0) || !std::isfinite(margin)) return fail(SEB_ERR_INVALID, "margin must be >= 0");
+    if (std::fabs((double)origin_x) > 1e12 || std::fabs((double)origin_y) > 1e12)
+        return fail(SEB_ERR_INVALID, "origin out of range");
+    elev::RayArgs r;
+    r.pts = sc->points;
+    r.n = sc->n_points;
+    for (int i = 0; i < 9; ++i) {
+        r.A[i] = sc->R_BS[i];
+        r.R[i] = sc->R_B[i];
+    }
+    for (int i = 0; i < 3; ++i) {
+        r.a[i] = sc->p_BS[i];
+        r.b[i] = sc->p_B[i];
+    }
+    // sensor origin R_B p_BS + p_B, in the reference's order of operations
+    r.sx = r.R[0] * r.a[0] + r.R[1] * r.a[1] + r.R[2] * r.a[2] + r.b[0];
+    r.sy = r.R[3] * r.a[0] + r.R[4] * r.a[1] + r.R[5] * r.a[2] + r.b[1];
+    r.sz = r.R[6] * r.a[0] + r.R[7] * r.a[1] + r.R[8] * r.a[2] + r.b[2];
+    r.res = g.resolution;
+    r.margin = margin;
+    r.W = g.width;
+    r.H = g.height;
+    r.rx = (int32_t)pos_mod(origin_x, g.width);
+    r.ry = (int32_t)pos_mod(origin_y, g.height);
+    r.ox = origin_x;
+    r.oy = origin_y;
+    r.height = height;
+    r.ld = ld;
+    r.n_reset = n_reset_dev;
+    hipError_t e = elev::launch_raycast(r, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "ray-casting launch");
+    return SEB_OK;
+}
+
 int seb_inpaint_nearest(seb_ctx* c, const float* height, int64_t ld, int32_t ring_x,
                         int32_t ring_y, int32_t radius, float* out, int64_t out_ld, void* stream) {
     if (!c || !height || !out) return fail(SEB_ERR_INVALID, "ctx, height and out must be non-NULL");

@@ -91,6 +91,8 @@ _SIGS = {
     "seb_fuser_destroy": (None, [C.c_void_p]),
     "seb_fuse_scan": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
                                 C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "seb_raycast_reset": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
+                                    C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
     "seb_inpaint_nearest": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
                                       C.c_int32, C.c_void_p, C.c_int64, C.c_void_p]),
     "seb_strerror": (C.c_char_p, [C.c_int]),
@@ -260,6 +262,21 @@ class Context:
                                    C.c_void_p(poses.data_ptr()), n, C.c_void_p(out.data_ptr()),
                                    _stream_handle(stream)), "seb_query_se2")
         return out
+
+    def raycast_reset(self, height, origin, points, frames: dict, margin: float = 0.0,
+                      n_reset=None, stream=None):
+        """seb_raycast_reset: cells standing above a sensor-to-point ray become
+        unknown (in place, ring storage of the window at world cell `origin`)."""
+        _check_map(height, self.params)
+        sc = Fuser.scan_struct(points, dict({"Sigma_R": np.zeros(9), "Sigma_B": np.zeros(9),
+                                             "sigma_range": 1.0, "sigma_angle": 0.0,
+                                             "z_min": 0.0, "z_max": 0.0, "mahalanobis": 1.0},
+                                            **frames))
+        ptr = None if n_reset is None else n_reset.data_ptr()
+        _check(lib().seb_raycast_reset(self._h, C.c_void_p(height.data_ptr()), height.stride(0),
+                                       int(origin[0]), int(origin[1]), C.byref(sc), float(margin),
+                                       C.c_void_p(ptr), _stream_handle(stream)),
+               "seb_raycast_reset")
 
     def inpaint(self, height, radius: int, ring=(0, 0), out=None, stream=None):
         """seb_inpaint_nearest: nearest-neighbour fill of unknown cells (a new map)."""

@@ -173,3 +173,48 @@ def test_inpaint_matches_oracle(W, H, radius, ring, hole_frac):
             ctx.inpaint(src, 3, out=src)
     assert same(got, want)
     assert np.isfinite(got).mean() >= np.isfinite(h).mean()
+
+
+def stale_map(terrain, seed, frac=0.05, lift=1.5):
+    """The terrain with a fraction of cells standing `lift` metres too high
+    (obstacles that have moved away), as the ray casting is meant to clear."""
+    rng = np.random.default_rng(seed)
+    h = terrain.copy()
+    h[rng.random(h.shape) < frac] += lift
+    return h
+
+
+@pytest.mark.parametrize("W,H,res,origin,n_points,margin,robot", [
+    (128, 96, 0.1, (0, 0), 20000, 0.0, None),
+    (100, 70, 0.05, (-37, 1234), 20000, 0.05, None),
+    (400, 400, 0.05, (-200, -200), 30000, 0.0, None),   # the 400 x 400 @ 0.05 m window
+    (60, 50, 0.1, (10, -20), 5000, 0.0, (-0.5, -3.2)),  # the sensor outside the window
+])
+def test_raycast_matches_oracle(W, H, res, origin, n_points, margin, robot):
+    import torch
+    p = small(W, H, res)
+    if robot is None:
+        terrain = I.fractal_terrain(W, H, res, seed=W, hole_frac=0.05)
+        scan = I.synthetic_scan(terrain, res, n_points, seed=W, origin=origin,
+                                max_range=0.6 * min(W, H) * res)
+        hm = stale_map(terrain, W)
+    else:
+        big = I.fractal_terrain(200, 200, res, seed=50, hole_frac=0.05)   # world cells [-100, 100)
+        scan = I.synthetic_scan(big, res, n_points, seed=2, origin=(-100, -100), robot_xy=robot,
+                                max_range=9.0)
+        hm = stale_map(big[origin[1] + 100:origin[1] + 100 + H, origin[0] + 100:origin[0] + 100 + W],
+                       7, frac=0.1)
+    want, n_want = E.raycast_reset(hm, scan["points"], scan["R_B"], scan["p_B"], scan["R_BS"],
+                                   scan["p_BS"], res, origin[0], origin[1], margin)
+    with seb.Context(p) as ctx:
+        hr = torch.from_numpy(to_ring(hm, origin)).cuda()
+        n = torch.zeros(1, dtype=torch.int32, device="cuda")
+        ctx.raycast_reset(hr, origin, torch.from_numpy(scan["points"]).cuda(), scan, margin,
+                          n_reset=n)
+        torch.cuda.synchronize()
+        got = from_ring(hr.cpu().numpy(), origin)
+        assert int(n.item()) == n_want
+        with pytest.raises(seb.SebError):
+            ctx.raycast_reset(hr, origin, torch.from_numpy(scan["points"]).cuda(), scan, -1.0)
+    assert same(got, want)
+    assert n_want > 20                               # the rays did clear stale cells
