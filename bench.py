@@ -210,7 +210,7 @@ def bench_elevation(torch, seb, n_points: int = 200_000):
     out = seb.alloc_outputs(p)
 
     def step():
-        ctx.raycast_reset(h, (0, 0), pts, scan, 0.0, n_reset=nr)
+        ctx.raycast_reset(h, (0, 0), pts, scan, 0.0)
         fuser.fuse(h, v, (0, 0), pts, scan, n_fused=n)
         ctx.inpaint(h, 8, out=filled)
         ctx.assess(filled, out)

@@ -21,8 +21,8 @@
 // walks its cells with a DDA clipped to the window, also trying both
 // neighbours where it passes within 1e-9 (in ray parameter) of a corner, and
 // decides every candidate with the same slab clipping as the reference.  A
-// reset is a compare-and-swap to NaN, so each cell counts once and the result
-// is a union that no ray order changes.
+// reset writes NaN -- as a compare-and-swap when resets are counted, so each
+// cell counts once -- and the result is a union that no ray order changes.
 //
 // Unknown cells can then be filled from the nearest known cell within a
 // radius (nearest-neighbour inpainting, the method of the experiments), from
@@ -351,6 +351,10 @@ __device__ __forceinline__ int ray_cell(const RayArgs& r, const Ray& q, int64_t 
     float* p = r.height + (int64_t)((ly + r.ry) % r.H) * r.ld + (lx + r.rx) % r.W;
     const float h = *p;
     if (!((double)h > zmax + r.margin)) return 0;
+    if (!r.n_reset) {                        // no count wanted: the store is idempotent
+        *p = __builtin_nanf("");
+        return 0;
+    }
     const unsigned int old = __float_as_uint(h);
     return atomicCAS(reinterpret_cast<unsigned int*>(p), old, 0x7FC00000u) == old;
 }

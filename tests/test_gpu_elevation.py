@@ -216,5 +216,10 @@ def test_raycast_matches_oracle(W, H, res, origin, n_points, margin, robot):
         assert int(n.item()) == n_want
         with pytest.raises(seb.SebError):
             ctx.raycast_reset(hr, origin, torch.from_numpy(scan["points"]).cuda(), scan, -1.0)
+        # without a count the resets are plain stores: the same map
+        hr2 = torch.from_numpy(to_ring(hm, origin)).cuda()
+        ctx.raycast_reset(hr2, origin, torch.from_numpy(scan["points"]).cuda(), scan, margin)
+        torch.cuda.synchronize()
+        assert same(from_ring(hr2.cpu().numpy(), origin), want)
     assert same(got, want)
     assert n_want > 20                               # the rays did clear stale cells
