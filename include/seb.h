@@ -306,9 +306,10 @@ void seb_fuser_destroy(seb_fuser* f);
  * |z - h| / sqrt(v) exceeds tau replaces the cell if it is higher and is
  * dropped if it is lower (several heights in one cell); otherwise
  * h <- (v z + s h) / (v + s), v <- v s / (v + s).  Cells without points are
- * not touched.  *n_fused_dev (device int32, may be NULL) receives the number
- * of points that changed a cell.  Errors (host-side, nothing launched):
- * SEB_ERR_INVALID.  Allocates nothing; one fuser serves one stream at a time. */
+ * not touched; height and variance must not overlap.  *n_fused_dev (device
+ * int32, may be NULL) receives the number of points that changed a cell.
+ * Errors (host-side, nothing launched): SEB_ERR_INVALID.  Allocates nothing;
+ * one fuser serves one stream at a time. */
 int seb_fuse_scan(seb_fuser* f, float* height, float* variance, int64_t ld, int64_t origin_x,
                   int64_t origin_y, const seb_scan* scan, int32_t* n_fused_dev, void* stream);
 

@@ -500,7 +500,7 @@ hipError_t launch_fuse_scan(const ScanArgs& s, const FuseArgs& f, const FuseWork
                        n_cells, w.partial, w.offs);
     if (s.n > 0) hipLaunchKernelGGL(scatter_kernel, grid(s.n), dim3(256), 0, stream, s.n, w);
     hipLaunchKernelGGL(fuse_small_kernel, grid(n_cells), dim3(256), 0, stream, f, w);
-    hipLaunchKernelGGL(fuse_large_kernel, dim3(1024), dim3(256), 0, stream, f, w);
+    hipLaunchKernelGGL(fuse_large_kernel, dim3(8192), dim3(256), 0, stream, f, w);
     return hipGetLastError();
 }
 

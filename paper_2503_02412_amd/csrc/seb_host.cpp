@@ -851,6 +851,13 @@ int seb_fuse_scan(seb_fuser* f, float* height, float* variance, int64_t ld, int6
         return fail(SEB_ERR_INVALID, "fuser, height, variance and scan must be non-NULL");
     const seb_config& g = f->ctx->cfg;
     if (ld < g.width) return fail(SEB_ERR_INVALID, "ld must be >= width");
+    {
+        const char* h0 = (const char*)height;
+        const char* h1 = (const char*)(height + (int64_t)(g.height - 1) * ld + g.width);
+        const char* v0 = (const char*)variance;
+        const char* v1 = (const char*)(variance + (int64_t)(g.height - 1) * ld + g.width);
+        if (h0 < v1 && v0 < h1) return fail(SEB_ERR_INVALID, "height and variance overlap");
+    }
     if (sc->n_points < 0 || sc->n_points > f->max_points)
         return fail(SEB_ERR_INVALID, "n_points outside [0, max_points]");
     if (sc->n_points > 0 && !sc->points) return fail(SEB_ERR_INVALID, "points is NULL");

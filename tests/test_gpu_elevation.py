@@ -147,6 +147,8 @@ def test_fuse_rejects_bad_arguments():
                 fuser.fuse(h, h.clone(), (0, 0), pts, dict(scan, **bad))
         fuser.close()
         with pytest.raises(seb.SebError):
+            fuser.fuse(h, h, (0, 0), pts, scan)                      # height is variance
+        with pytest.raises(seb.SebError):
             seb.Fuser(ctx, 0)
 
 
