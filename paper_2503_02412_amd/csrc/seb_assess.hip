@@ -48,8 +48,18 @@ void assess_kernel(const AssessArgs a) {
     int ri = 0;
     while (ri + 1 < a.n_rects && b >= a.tile_start[ri + 1]) ++ri;
     const int lb = b - a.tile_start[ri];
-    const int tyi = lb / a.tiles_x[ri];
-    const int txi = lb - tyi * a.tiles_x[ri];
+    const int tx = a.tiles_x[ri];
+    int txi, tyi;
+    bool paired = false;
+    if (a.edge_pair[ri] && lb >= (tx - 1) * a.tiles_y[ri]) {
+        paired = true;                             // tiles tyi and tyi + 1 of the last column
+        txi = tx - 1;
+        tyi = 2 * (lb - (tx - 1) * a.tiles_y[ri]);
+    } else {
+        const int w = a.edge_pair[ri] ? tx - 1 : tx;
+        tyi = lb / w;
+        txi = lb - tyi * w;
+    }
     const int sx0 = a.rect[ri][0] + txi * TILE;
     const int sy0 = a.rect[ri][1] + tyi * TILE;
     const int sx1 = a.rect[ri][0] + a.rect[ri][2];
@@ -57,28 +67,36 @@ void assess_kernel(const AssessArgs a) {
     const int R = a.R;
     const int tw = TILE + 2 * R;
 
-    // Stage heights of logical cells [sx0-R, sx0+16+R) x [sy0-R, sy0+16+R).
-    for (int i = tid; i < tw * tw; i += BLOCK) {
-        const int ly = i / tw;
-        const int lx = i - ly * tw;
-        const int gx = sx0 - R + lx, gy = sy0 - R + ly;
+    // Stage heights of logical cells [sx0-R, sx0+16+R) x [sy0-R, sy0+16+R); a
+    // pair stages [sx0-R, sx0+8+R) of both tiles, the lower one tw rows further
+    // down and 8 columns further right in LDS (so that lanes 8-15 fall on the
+    // banks next to lanes 0-7).
+    const int cw = paired ? TILE / 2 + 2 * R : tw;
+    const int n_stage = (paired ? 2 : 1) * tw * cw;
+    for (int i = tid; i < n_stage; i += BLOCK) {
+        const int half = i >= tw * cw;
+        const int k = i - half * tw * cw;
+        const int ly = k / cw;
+        const int lx = k - ly * cw;
+        const int gx = sx0 - R + lx, gy = sy0 - R + ly + half * TILE;
         float v = SENTINEL;
         if (gx >= 0 && gx < a.W && gy >= 0 && gy < a.H) {
             const int px = wrap(gx + a.rx, a.W), py = wrap(gy + a.ry, a.H);
             const float h = a.height[(int64_t)py * a.ld + px];
             if (fabsf(h) < HEIGHT_LIMIT) v = h;      // false for NaN and +-Inf
         }
-        tile[ly * P + lx] = v;
+        tile[(half * tw + ly) * P + lx + half * (TILE / 2)] = v;
     }
     __syncthreads();
 
     const int lane = tid & 63;
     const int lx = lane & 15;
     const int ly = (tid >> 6) * 4 + (lane >> 4);
-    const int ix = sx0 + lx, iy = sy0 + ly;
+    const int hb = paired ? lx >> 3 : 0;           // lower tile of a pair
+    const int ix = sx0 + (paired ? lx & 7 : lx), iy = sy0 + ly + hb * TILE;
     const bool active = ix < sx1 && iy < sy1;
     if (!__ballot(active)) return;                 // wave entirely past the rectangle's edge
-    const float* tp0 = tile + (ly + R) * P + (lx + R);
+    const float* tp0 = tile + (hb * tw + ly + R) * P + (lx + R);
     const float hc = tp0[0];
     const int64_t cell = (int64_t)wrap(iy + a.ry, a.H) * a.W + wrap(ix + a.rx, a.W);
 
@@ -336,7 +354,10 @@ hipError_t launch_assess(const AssessArgs& a, int pitch, hipStream_t stream) {
     if (tiles == 0) return hipSuccess;
     const int groups = (a.n_units + a.units_per_group - 1) / a.units_per_group;
     const dim3 grid(tiles, groups);
-    const size_t lds = (size_t)(TILE + 2 * a.R) * pitch * sizeof(float);
+    bool any_pair = false;
+    for (int r = 0; r < a.n_rects; ++r) any_pair = any_pair || a.edge_pair[r];
+    const size_t lds = any_pair ? edge_pair_lds(a.R, pitch)
+                                : (size_t)(TILE + 2 * a.R) * pitch * sizeof(float);
     switch (pitch) {
         case 48: return launch_p<48>(a, grid, lds, stream);
         case 80: return launch_p<80>(a, grid, lds, stream);

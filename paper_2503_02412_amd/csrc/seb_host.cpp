@@ -330,17 +330,23 @@ void base_args(const seb_ctx* c, AssessArgs* a) {
 }
 
 // Tile decomposition of the state rectangles; chooses the yaw bins per workgroup.
-void set_rects(AssessArgs* a, int n, const int32_t (*rects)[4]) {
+void set_rects(AssessArgs* a, int n, const int32_t (*rects)[4], int pitch) {
     a->n_rects = 0;
     int start = 0;
+    // Pairing edge tiles doubles the LDS block; only where 8 workgroups (32
+    // waves) still fit in a CU's 160 KB.
+    const bool pair_ok = edge_pair_lds(a->R, pitch) <= 20 * 1024;
     for (int r = 0; r < n; ++r) {
         if (rects[r][2] <= 0 || rects[r][3] <= 0) continue;
         const int i = a->n_rects++;
         for (int t = 0; t < 4; ++t) a->rect[i][t] = rects[r][t];
         a->tiles_x[i] = (rects[r][2] + TILE - 1) / TILE;
-        const int ty = (rects[r][3] + TILE - 1) / TILE;
+        a->tiles_y[i] = (rects[r][3] + TILE - 1) / TILE;
+        const int rem = rects[r][2] % TILE;
+        a->edge_pair[i] = pair_ok && rem >= 1 && rem <= TILE / 2;
         a->tile_start[i] = start;
-        start += a->tiles_x[i] * ty;
+        start += a->edge_pair[i] ? (a->tiles_x[i] - 1) * a->tiles_y[i] + (a->tiles_y[i] + 1) / 2
+                                 : a->tiles_x[i] * a->tiles_y[i];
     }
     a->tile_start[a->n_rects] = start;
     // One yaw unit per workgroup: the most workgroups and the best balance
@@ -367,7 +373,7 @@ int run_assess(seb_ctx* c, const float* height, int64_t ld, int rx, int ry, cons
     a.pitch = out->pitch;
     a.risk = out->risk;
     a.status = out->status;
-    set_rects(&a, n_rects, rects);
+    set_rects(&a, n_rects, rects, c->pitch);
     const hipError_t e = launch_assess(a, c->pitch, stream);
     if (e != hipSuccess) return hip_fail(e, "assessment kernel launch");
     return SEB_OK;

@@ -98,6 +98,11 @@ struct AssessArgs {
     int32_t n_rects;
     int32_t rect[MAX_RECTS][4];
     int32_t tiles_x[MAX_RECTS];
+    int32_t tiles_y[MAX_RECTS];
+    // A rect whose last tile column holds at most 8 columns runs that column as
+    // pairs of vertically adjacent tiles, one workgroup per pair (lanes 0-7 the
+    // upper tile, lanes 8-15 the lower), after its full tiles.
+    int32_t edge_pair[MAX_RECTS];
     int32_t tile_start[MAX_RECTS + 1];
 };
 
@@ -126,5 +131,9 @@ bool has_row_kernel(int row_len);
 hipError_t launch_insert(const InsertArgs& a, hipStream_t stream);
 // LDS pitches (floats) the assessment kernel is instantiated for.
 int pick_pitch(int R);
+// LDS bytes of a workgroup that runs a pair of edge tiles.
+inline size_t edge_pair_lds(int R, int pitch) {
+    return (size_t)2 * (TILE + 2 * R) * pitch * sizeof(float);
+}
 
 }  // namespace seb
