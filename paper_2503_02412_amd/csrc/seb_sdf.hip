@@ -20,6 +20,7 @@
 //     of each row marks the columns holding any target; the nearest marked
 //     column starts the scan, and a cell with none within C takes the cap at
 //     once.  The scan ends once dx^2 alone reaches the best so far.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -244,9 +245,15 @@ __device__ __forceinline__ void trilinear(const float (&c)[2][2][2], float fu, f
     o[3] = cuv[1] - cuv[0];                                                // d/dw
 }
 
+__device__ __forceinline__ void query_pose(const QueryArgs& q, int64_t n);
+
 __global__ __launch_bounds__(256) void query_kernel(const QueryArgs q) {
-    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (n >= q.n) return;
+    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < q.n;
+         n += (int64_t)gridDim.x * 256)
+        query_pose(q, n);
+}
+
+__device__ __forceinline__ void query_pose(const QueryArgs& q, int64_t n) {
     const double x = q.poses[3 * n], y = q.poses[3 * n + 1], th = q.poses[3 * n + 2];
     const double ur = x / q.res - 0.5, vr = y / q.res - 0.5;
     const double u = fmin(fmax(ur, 0.0), q.W - 1.0), v = fmin(fmax(vr, 0.0), q.H - 1.0);
@@ -335,7 +342,8 @@ hipError_t launch_query(const float* fa, const float* fb, const float* poses, fl
     q.rx = rx;
     q.ry = ry;
     q.res = res;
-    hipLaunchKernelGGL(query_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, q);
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, int64_t(1) << 20);
+    hipLaunchKernelGGL(query_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, q);
     return hipGetLastError();
 }
 
