@@ -37,34 +37,6 @@ using namespace dev;
 // The least-squares kernels are held to 8 waves per SIMD (64 VGPRs), which
 // the chunked sample loop would otherwise exceed by one register; the FP64
 // eigen epilogue of the principal-component fit needs more and runs at 5.
-// Stage n heights into LDS: element i is logical cell (gx, gy) stored at LDS
-// index li, as map(i, gx, gy, li) says.  Each thread issues SB loads at once,
-// from coordinates clamped into the map (always valid), and applies the
-// out-of-map and unknown tests afterwards; a guarded load per element would
-// wait for each load in turn.
-template <int SB, typename Map>
-__device__ __forceinline__ void stage_heights(const AssessArgs& a, float* tile, int n, Map map) {
-    for (int i0 = threadIdx.x; i0 < n; i0 += SB * BLOCK) {
-        float v[SB];
-        int at[SB];
-#pragma unroll
-        for (int u = 0; u < SB; ++u) {
-            const int i = i0 + u * BLOCK;
-            int gx, gy, li;
-            map(min(i, n - 1), gx, gy, li);
-            const bool in = gx >= 0 && gx < a.W && gy >= 0 && gy < a.H;
-            const int px = wrap(min(max(gx, 0), a.W - 1) + a.rx, a.W);
-            const int py = wrap(min(max(gy, 0), a.H - 1) + a.ry, a.H);
-            const float h = a.height[(int64_t)py * a.ld + px];
-            v[u] = in && fabsf(h) < HEIGHT_LIMIT ? h : SENTINEL;   // false for NaN and +-Inf
-            at[u] = i < n ? li : -1;
-        }
-#pragma unroll
-        for (int u = 0; u < SB; ++u)
-            if (at[u] >= 0) tile[at[u]] = v[u];
-    }
-}
-
 template <int P, int NW, int FIT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FIT == 0 ? 8 : 1)))
 void assess_kernel(const AssessArgs a) {
@@ -100,15 +72,21 @@ void assess_kernel(const AssessArgs a) {
     // down and 8 columns further right in LDS (so that lanes 8-15 fall on the
     // banks next to lanes 0-7).
     const int cw = paired ? TILE / 2 + 2 * R : tw;
-    stage_heights<4>(a, tile, (paired ? 2 : 1) * tw * cw, [&](int i, int& gx, int& gy, int& li) {
+    const int n_stage = (paired ? 2 : 1) * tw * cw;
+    for (int i = tid; i < n_stage; i += BLOCK) {
         const int half = i >= tw * cw;
         const int k = i - half * tw * cw;
         const int ly = k / cw;
         const int lx = k - ly * cw;
-        gx = sx0 - R + lx;
-        gy = sy0 - R + ly + half * TILE;
-        li = (half * tw + ly) * P + lx + half * (TILE / 2);
-    });
+        const int gx = sx0 - R + lx, gy = sy0 - R + ly + half * TILE;
+        float v = SENTINEL;
+        if (gx >= 0 && gx < a.W && gy >= 0 && gy < a.H) {
+            const int px = wrap(gx + a.rx, a.W), py = wrap(gy + a.ry, a.H);
+            const float h = a.height[(int64_t)py * a.ld + px];
+            if (fabsf(h) < HEIGHT_LIMIT) v = h;      // false for NaN and +-Inf
+        }
+        tile[(half * tw + ly) * P + lx + half * (TILE / 2)] = v;
+    }
     __syncthreads();
 
     const int lane = tid & 63;
@@ -269,12 +247,20 @@ __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, cons
         const int bh = ((it.z >> 15) & 31) - by0 + 1 + 2 * R;
         // Block origin moved to the bounding box of the item's cells.
         const int sx0 = (it.x % tiles_x) * TF + bx0, sy0 = (it.x / tiles_x) * TF + by0;
-        stage_heights<8>(a, tile, bh * bw, [&](int i, int& gx, int& gy, int& li) {
-            const int ly = i / bw, lx = i - ly * bw;
-            gx = sx0 - R + lx;
-            gy = sy0 - R + ly;
-            li = ly * P + lx;
-        });
+        for (int ly = wave; ly < bh; ly += BLOCK / 64) {
+            const int gy = sy0 - R + ly;
+            const bool row_in = gy >= 0 && gy < a.H;
+            const float* hrow = a.height + (int64_t)(row_in ? wrap(gy + a.ry, a.H) : 0) * a.ld;
+            for (int lx = lane; lx < bw; lx += 64) {
+                const int gx = sx0 - R + lx;
+                float v = SENTINEL;
+                if (row_in && gx >= 0 && gx < a.W) {
+                    const float h = hrow[wrap(gx + a.rx, a.W)];
+                    if (fabsf(h) < HEIGHT_LIMIT) v = h;      // false for NaN and +-Inf
+                }
+                tile[ly * P + lx] = v;
+            }
+        }
         __syncthreads();
         const bool act = lane < (it.w & 255);
         // Lanes past the item's count take the box corner (staged, not stored).
