@@ -240,14 +240,16 @@ def bench_elevation(torch, seb, n_points: int = 200_000):
     }
 
 
-def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4):
+def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4, p=None):
     """Train the surrogate on plain-kernel labels, then time inference with the
     plain fallback on 200x200x36 evaluation maps against the plain kernel, and
     measure its error on the states it answered against the plain kernel (which
-    matches the FP64 oracle to within 1e-5 on these maps)."""
+    matches the FP64 oracle to within 1e-5 on these maps).  `p`: the map and
+    footprint (default: the headline workload)."""
     from paper_2503_02412_amd.surrogate import TrainingData, train
+    p = I.CONFIG2 if p is None else p
     t0 = time.perf_counter()
-    data = TrainingData(count=2_000_000)
+    data = TrainingData(params=p.with_(width=64, height=64), count=2_000_000)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     net = seb.Net(seed=1, max_batch=4096)
@@ -255,7 +257,6 @@ def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4):
     hist = train(net, data, steps=train_steps, batch=4096)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    p = I.CONFIG2
     ctx = seb.Context(p)
     sur = seb.Surrogate(ctx)
     out = seb.alloc_outputs(p)
@@ -280,7 +281,8 @@ def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4):
     return {
         "workload": "2-conv + 3-layer MLP (bf16, MFMA) on 24x24 slope/known patches + yaw; "
                     "trained on 2M plain-kernel labels of 70 seeded 64x64 sinusoid terrains; "
-                    f"evaluated on {eval_maps} seeded 200x200x36 fractal maps",
+                    f"evaluated on {eval_maps} seeded 200x200x36 fractal maps; footprint "
+                    f"{p.fp_length}x{p.fp_width} m on {p.fp_nl}x{p.fp_nw} samples",
         "train_steps": train_steps, "train_batch": 4096,
         "train_samples_per_s": train_steps * 4096 / t_train, "label_seconds": t_data,
         "loss_first_last": [float(hist[:20].mean()), float(hist[-20:].mean())],
@@ -336,7 +338,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="rolling,large_map,surrogate,sdf_query,elevation",
+    ap.add_argument("--extras", default="rolling,large_map,surrogate,surrogate_large_footprint,"
+                                         "sdf_query,elevation",
                     help="comma-separated extra legs to run (default: all)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -386,7 +389,10 @@ def main():
     }
     if not args.no_extras:
         legs = {"rolling": bench_rolling, "large_map": bench_large,
-                "surrogate": bench_surrogate, "sdf_query": bench_sdf,
+                "surrogate": bench_surrogate,
+                "surrogate_large_footprint":
+                    lambda t, s: bench_surrogate(t, s, p=I.CONFIG2_LARGE_FOOTPRINT),
+                "sdf_query": bench_sdf,
                 "elevation": bench_elevation}
         for name in args.extras.split(","):
             if name not in legs:

@@ -277,6 +277,9 @@ def rolling_world(params: Params = CONFIG3, seed: int = 3, n_steps: int = 100,
 # --------------------------------------------------------------------------
 
 SURROGATE_LABEL_PARAMS = CONFIG2.with_(width=64, height=64)
+# The same map with a 2.0 x 1.2 m footprint on 40 x 24 samples: four times the
+# plain method's work per state, still inside the network's 24 x 24 window.
+CONFIG2_LARGE_FOOTPRINT = CONFIG2.with_(fp_length=2.0, fp_width=1.2, fp_nl=40, fp_nw=24)
 SURROGATE_TRAIN_SEEDS = tuple(range(1000, 1070))
 SURROGATE_VAL_SEEDS = (1070, 1071)
 SURROGATE_EVAL_SEEDS = (2000, 2001, 2002, 2003)
