@@ -251,9 +251,11 @@ struct seb_ctx {
     seb_config cfg;
     Geometry geo;
     int pitch = 0;
+    int fpitch = 0;                       // pitch of the surrogate's fallback kernel
     int row_len = 0;
     float4* d_wts = nullptr;
     int32_t* d_offs = nullptr;
+    int32_t* d_offs_f = nullptr;          // offsets at fpitch (d_offs when equal)
     double2* d_frac = nullptr;
     float* d_qs = nullptr;
     uint32_t* d_pks = nullptr;
@@ -502,6 +504,14 @@ int seb_create(const seb_config* cfg, seb_ctx** out) {
     std::string why;
     build_geometry(*cfg, &c->geo, &why);
     c->pitch = pick_pitch(c->geo.R);
+    // The fallback kernel takes 32 x 32 blocks when their halo fits a pitch:
+    // four times as many flagged cells per block fill its 64-lane items.
+    c->fpitch = c->pitch;
+    for (int p : {48, 80, 112, 144})
+        if (p >= 32 + 2 * c->geo.R) {
+            c->fpitch = std::max(p, c->pitch);
+            break;
+        }
     (void)hipGetDevice(&c->device);
 
     // FP64 table: per yaw bin, per sample, the snapped grid offset split into
@@ -509,7 +519,7 @@ int seb_create(const seb_config* cfg, seb_ctx** out) {
     const Geometry& g = c->geo;
     const int ns = (int)g.samples.size();
     std::vector<float4> wts((size_t)g.n_units * ns);
-    std::vector<int32_t> offs((size_t)g.n_units * ns);
+    std::vector<int32_t> offs((size_t)g.n_units * ns), offs_f((size_t)g.n_units * ns);
     std::vector<double2> frac((size_t)g.n_units * ns);
     std::vector<float> qs(ns);
     std::vector<uint32_t> pks(ns);
@@ -528,6 +538,7 @@ int seb_create(const seb_config* cfg, seb_ctx** out) {
             const double fx = ox - flx, fy = oy - fly;
             const size_t e = (size_t)u * ns + s;
             offs[e] = (int)fly * c->pitch + (int)flx;
+            offs_f[e] = (int)fly * c->fpitch + (int)flx;
             wts[e] = make_float4((float)((1.0 - fx) * (1.0 - fy)), (float)(fx * (1.0 - fy)),
                                  (float)((1.0 - fx) * fy), (float)(fx * fy));
             frac[e] = make_double2(fx, fy);
@@ -565,6 +576,8 @@ int seb_create(const seb_config* cfg, seb_ctx** out) {
     };
     if (!upload((void**)&c->d_wts, wts.data(), wts.size() * sizeof(float4)) ||
         !upload((void**)&c->d_offs, offs.data(), offs.size() * sizeof(int32_t)) ||
+        (c->fpitch != c->pitch &&
+         !upload((void**)&c->d_offs_f, offs_f.data(), offs_f.size() * sizeof(int32_t))) ||
         !upload((void**)&c->d_frac, frac.data(), frac.size() * sizeof(double2)) ||
         !upload((void**)&c->d_qs, qs.data(), qs.size() * sizeof(float)) ||
         !upload((void**)&c->d_pks, pks.data(), pks.size() * sizeof(uint32_t)) ||
@@ -575,12 +588,14 @@ int seb_create(const seb_config* cfg, seb_ctx** out) {
         seb_destroy(c);
         return code;
     }
+    if (c->fpitch == c->pitch) c->d_offs_f = c->d_offs;
     *out = c;
     return SEB_OK;
 }
 
 void seb_destroy(seb_ctx* c) {
     if (!c) return;
+    if (c->d_offs_f && c->d_offs_f != c->d_offs) (void)hipFree(c->d_offs_f);
     for (void* p : {(void*)c->d_wts, (void*)c->d_offs, (void*)c->d_frac, (void*)c->d_qs,
                     (void*)c->d_pks, (void*)c->d_segs, (void*)c->d_inpaint})
         if (p) (void)hipFree(p);
@@ -736,8 +751,8 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
     };
     seb::sur::SurArgs& w = s->ws;
     std::memset(&w, 0, sizeof(w));
-    const int64_t max_items = flagged_work_items((int)W, (int)H, U, c->geo.R, c->pitch);
-    const int64_t n_blocks = flagged_blocks((int)W, (int)H, U, c->geo.R, c->pitch);
+    const int64_t max_items = flagged_work_items((int)W, (int)H, U, c->geo.R, c->fpitch);
+    const int64_t n_blocks = flagged_blocks((int)W, (int)H, U, c->geo.R, c->fpitch);
     const bool ok =
         al((void**)&w.o1map, (size_t)(H + 20) * (W + 20) * seb::net::C1 * 2) &&
         al((void**)&w.o2map, (size_t)(H + 16) * (W + 16) * seb::net::C2 * 2) &&
@@ -758,7 +773,7 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
     w.K = c->cfg.n_yaw;
     w.U = U;
     w.mirror = c->geo.mirror;
-    w.pitch = c->pitch;
+    w.pitch = c->fpitch;
     w.risk_max = (float)c->cfg.risk_max;
     *out = s;
     return SEB_OK;
@@ -806,7 +821,8 @@ int seb_surrogate_infer(seb_surrogate* s, const seb_net* net, const float* heigh
     a.work_cells = w.work_cells;
     a.block_count = w.block_count;
     a.item_box = w.item_box;
-    e = launch_assess_flagged(a, s->ctx->pitch, (hipStream_t)stream);
+    a.offs = s->ctx->d_offs_f;
+    e = launch_assess_flagged(a, s->ctx->fpitch, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fallback assessment launch");
     return SEB_OK;
 }

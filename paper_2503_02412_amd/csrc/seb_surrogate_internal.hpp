@@ -17,7 +17,7 @@ struct SurArgs {
     int W, H;
     float inv_res;
     int K, U, mirror;            // yaw bins, units evaluated (K/2 if mirrored), mirror offset
-    int pitch;                   // LDS pitch of the context's table offsets
+    int pitch;                   // LDS pitch of the fallback kernel's table offsets
     // network
     const float* theta;          // float32 parameters (biases and Wy are read from here)
     net::PackedWeights pw;       // bf16 GEMM weights
