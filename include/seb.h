@@ -235,7 +235,9 @@ int seb_net_forward(seb_net* net, const seb_train_batch* batch, float* y_dev, vo
 
 /* One training step on the batch: loss = mean over samples of the squared
  * error of the four scaled outputs against the labels (targets
- * ((z - h_cell)/0.05, roll/0.5, pitch/0.5, risk)); backward pass; Adam
+ * ((z - h_ref)/0.05, roll/0.5, pitch/0.5, risk), where h_ref is the
+ * sample cell's height when known, else the mean of its known in-map
+ * 8-neighbours; every sample must have one); backward pass; Adam
  * (lr, beta 0.9 / 0.999, eps 1e-8) on float32 master weights.  loss_dev
  * (device float, may be NULL) receives the batch loss.  If grad_dev (device
  * [param_count]) is non-NULL the gradient is written there and the weights
@@ -258,9 +260,11 @@ void seb_surrogate_destroy(seb_surrogate* s);
 /* Fill `out` ([K][H][W]) for every state of the map `height` ([H][W], row
  * stride ld).  Network outputs are written with status SEB_ST_VALID |
  * SEB_ST_SURROGATE (| SEB_ST_TRAV when risk <= risk_max).  A state falls back
- * to the plain method (Alg. 1 exactly as seb_assess_se2 computes it) when its
- * own cell is unknown, when fewer than min_known of the 24 x 24 window's cells
- * are known (outside the training distribution), or when the predicted risk
+ * to the plain method (Alg. 1 exactly as seb_assess_se2 computes it) when
+ * neither its own cell nor any of its 8 neighbours is known (no reference
+ * height for z: the own cell's, else the mean of the known neighbours), when
+ * fewer than min_known of the 24 x 24 window's cells are known (outside the
+ * training distribution), or when the predicted risk
  * lies within `band` of risk_max.  *n_fallback_dev (device int32, may be NULL)
  * receives the number of states that fell back.  Asynchronous on `stream`;
  * allocates nothing.  One surrogate handle serves one stream at a time. */

@@ -27,7 +27,11 @@ Layers (ReLU after every layer but the last):
     fc2   128 -> 64
     fc3    64 -> 4
 Outputs y = (dz / S_Z, roll / S_A, pitch / S_A, risk) with S_Z = 0.05 m and
-S_A = 0.5 rad, where dz = z - H(cy, cx).
+S_A = 0.5 rad, where dz = z - h_ref and h_ref is H(cy, cx) when known, else
+the mean of the known in-map cells among its eight neighbours (a reading: the
+paper does not say what the height output is relative to; expressing it
+against nearby known ground lets the network answer states whose own cell is
+a hole).  A state with no such cell has no reference and no network output.
 
 Parameter vector layout (float32, in this order, C order within each array):
     W1 [16,3,4,4]  b1 [16]  W2 [32,16,3,3]  b2 [32]  W3 [128,800]  Wy [128,2]
@@ -186,9 +190,25 @@ def loss(y: np.ndarray, t: np.ndarray, w: np.ndarray = LOSS_WEIGHTS):
     return L, 2.0 * w[None, :] * r / B
 
 
+def _known(h) -> bool:
+    return bool(np.isfinite(h)) and abs(float(h)) < 2.0 ** 60
+
+
+def reference_height(H: np.ndarray, cy: int, cx: int):
+    """Height the z output is expressed against: the cell's own height when
+    known, else the mean of its known in-map 8-neighbours, else None (the state
+    has no reference and is left to the plain method)."""
+    if _known(H[cy, cx]):
+        return float(H[cy, cx])
+    vals = [float(H[y, x]) for y in range(cy - 1, cy + 2) for x in range(cx - 1, cx + 2)
+            if (y, x) != (cy, cx) and 0 <= y < H.shape[0] and 0 <= x < H.shape[1]
+            and _known(H[y, x])]
+    return sum(vals) / len(vals) if vals else None
+
+
 def targets(H: np.ndarray, z: float, roll: float, pitch: float, risk: float, cy: int, cx: int):
-    """Scaled training targets of one state."""
-    return np.array([(z - float(H[cy, cx])) / S_Z, roll / S_A, pitch / S_A, risk])
+    """Scaled training targets of one state (which must have a reference height)."""
+    return np.array([(z - reference_height(H, cy, cx)) / S_Z, roll / S_A, pitch / S_A, risk])
 
 
 def adam_step(theta, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -106,6 +106,26 @@ __device__ __forceinline__ float map_at(const BatchArgs& a, int mi, int y, int x
     return ok ? h : 0.f;
 }
 
+// Height the z output is relative to: the cell's own height when known, else
+// the mean of its known 8-neighbours (false when none is known).
+__device__ __forceinline__ bool ref_height(const BatchArgs& a, int mi, int cy, int cx, float* h) {
+    float v;
+    const float h0 = map_at(a, mi, cy, cx, &v);
+    if (v > 0.f) {
+        *h = h0;
+        return true;
+    }
+    float sum = 0.f, n = 0.f;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (dy == 0 && dx == 0) continue;
+            sum += map_at(a, mi, cy + dy, cx + dx, &v);      // 0 when unknown
+            n += v;
+        }
+    *h = n > 0.f ? sum / n : 0.f;
+    return n > 0.f;
+}
+
 // Channel c (0: x-slope, 1: y-slope, 2: known) of map cell (y, x).
 __device__ __forceinline__ float encode(const BatchArgs& a, int mi, int y, int x, int c) {
     float v0, v1;
@@ -143,7 +163,8 @@ __global__ __launch_bounds__(256) void im2col1_kernel(const BatchArgs a, bf16* A
         sc[2 * b + 1] = (float)cos(th);
         if (a.lz) {
             const int64_t o = (((int64_t)mi * a.K + k) * a.mh + cy) * a.mw + cx;
-            const float hc = a.maps[((int64_t)mi * a.mh + cy) * a.mw + cx];
+            float hc;
+            ref_height(a, mi, cy, cx, &hc);     // samples are drawn where one exists
             tgt[4 * b] = (a.lz[o] - hc) / S_Z;
             tgt[4 * b + 1] = a.lroll[o] / S_A;
             tgt[4 * b + 2] = a.lpitch[o] / S_A;

@@ -9,9 +9,10 @@
 // Yaw bins k and k + K/2 are mirror images (roll and pitch change sign), as in
 // the plain kernel, so the network is evaluated for the first K/2 bins only.
 //
-// Flagged states -- unknown own cell, too few known cells in the window (out
-// of the training distribution), or predicted risk within `band` of risk_max
-// -- are marked in a per-state mask; the plain method then re-assesses exactly
+// z is predicted relative to a reference height: the own cell's, else the
+// mean of its known 8-neighbours.  Flagged states -- no reference, too few
+// known cells in the window (out of the training distribution), or predicted
+// risk within `band` of risk_max -- are marked in a per-state mask; the plain method then re-assesses exactly
 // those, compacted tile by tile (assess_flagged_kernel).
 #include <cmath>
 
@@ -46,6 +47,26 @@ __device__ __forceinline__ float height_at(const SurArgs& s, int y, int x, float
     const bool ok = fabsf(h) < HEIGHT_LIMIT;
     *known = ok ? 1.f : 0.f;
     return ok ? h : 0.f;
+}
+
+// Height the z output is relative to: the cell's own height when known, else
+// the mean of its known 8-neighbours (false when none is known).
+__device__ __forceinline__ bool ref_height(const SurArgs& s, int cy, int cx, float* h) {
+    float v;
+    const float h0 = height_at(s, cy, cx, &v);
+    if (v > 0.f) {
+        *h = h0;
+        return true;
+    }
+    float sum = 0.f, n = 0.f;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            if (dy == 0 && dx == 0) continue;
+            sum += height_at(s, cy + dy, cx + dx, &v);        // 0 when unknown
+            n += v;
+        }
+    *h = n > 0.f ? sum / n : 0.f;
+    return n > 0.f;
 }
 
 // conv1 at every position (y1, x1) in [-12, H+8) x [-12, W+8): ReLU(b1 + W1 . input
@@ -91,6 +112,8 @@ __global__ __launch_bounds__(256) void conv2_map_kernel(const SurArgs s) {
     const int r = lane & 15, kq = lane >> 4;
     const int64_t pr = min(row0 + r, M - 1);
     const int y2 = (int)(pr / W2) - 12, x2 = (int)(pr % W2) - 12;
+    // Biases first: a load issued after the stores below would wait for them.
+    const float bias[2] = {s.theta[net::OFF_B2 + r], s.theta[net::OFF_B2 + 16 + r]};
     f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
     const bf16x8 zero8 = {};
     for (int ks = 0; ks < net::K2P / 32; ++ks) {
@@ -111,7 +134,7 @@ __global__ __launch_bounds__(256) void conv2_map_kernel(const SurArgs s) {
             const int64_t row = row0 + 4 * kq + e;
             const int n = 16 * t + r;
             if (row >= M) continue;
-            const float v = fmaxf(acc[t][e] + s.theta[net::OFF_B2 + n], 0.f);
+            const float v = fmaxf(acc[t][e] + bias[t], 0.f);
             s.o2map[row * net::C2 + n] = to_bf16(v);
         }
 }
@@ -131,29 +154,43 @@ __global__ __launch_bounds__(256) void fc1_map_kernel(const SurArgs s) {
         cy[i] = (int)(c / s.W);
         cx[i] = (int)(c % s.W);
     }
+    // Biases first: a load issued after the stores below would wait for them.
+    const float bias[2] = {s.theta[net::OFF_B3 + 32 * wave + r],
+                           s.theta[net::OFF_B3 + 32 * wave + 16 + r]};
     f32x4 acc[4][2];
     for (int i = 0; i < 4; ++i)
         for (int t = 0; t < 2; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int ks = 0; ks < net::F / 32; ++ks) {
-        const int a5 = ks / 5, b5 = ks % 5;
-        bf16x8 bfr[2];
-        for (int t = 0; t < 2; ++t)
-            bfr[t] = *(const bf16x8*)(s.pw.w3 + (int64_t)(32 * wave + 16 * t + r) * net::F + 32 * ks +
-                                      8 * kq);
-        for (int i = 0; i < 4; ++i) {
-            const int y2 = cy[i] - 12 + 4 * a5, x2 = cx[i] - 12 + 4 * b5;
-            const bf16x8 a =
-                *(const bf16x8*)(s.o2map + ((int64_t)(y2 + 12) * W2 + (x2 + 12)) * net::C2 + 8 * kq);
+    // One conv2 row (a5) of the 5 x 5 gather per pass: its five k-steps' loads
+    // are all issued before the first product, so a wave waits five times per
+    // cell block instead of 25.
+    for (int a5 = 0; a5 < net::P2; ++a5) {
+        bf16x8 bfr[net::P2][2], afr[net::P2][4];
+#pragma unroll
+        for (int b5 = 0; b5 < net::P2; ++b5) {
+            const int ks = a5 * net::P2 + b5;
             for (int t = 0; t < 2; ++t)
-                acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[t], acc[i][t], 0, 0, 0);
+                bfr[b5][t] = *(const bf16x8*)(s.pw.w3 + (int64_t)(32 * wave + 16 * t + r) * net::F +
+                                              32 * ks + 8 * kq);
+            for (int i = 0; i < 4; ++i) {
+                const int y2 = cy[i] - 12 + 4 * a5, x2 = cx[i] - 12 + 4 * b5;
+                afr[b5][i] = *(const bf16x8*)(s.o2map + ((int64_t)(y2 + 12) * W2 + (x2 + 12)) * net::C2 +
+                                              8 * kq);
+            }
         }
+        __builtin_amdgcn_sched_barrier(0);   // keep every load ahead of the products
+#pragma unroll
+        for (int b5 = 0; b5 < net::P2; ++b5)
+            for (int i = 0; i < 4; ++i)
+                for (int t = 0; t < 2; ++t)
+                    acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[b5][i], bfr[b5][t], acc[i][t],
+                                                                         0, 0, 0);
     }
     for (int i = 0; i < 4; ++i)
         for (int t = 0; t < 2; ++t)
             for (int e = 0; e < 4; ++e) {
                 const int64_t c = c0 + 16 * i + 4 * kq + e;
                 const int n = 32 * wave + 16 * t + r;
-                if (c < cells) s.T[c * net::H1 + n] = acc[i][t][e] + s.theta[net::OFF_B3 + n];
+                if (c < cells) s.T[c * net::H1 + n] = acc[i][t][e] + bias[t];
             }
 }
 
@@ -251,11 +288,17 @@ __global__ __launch_bounds__(256) void head_kernel(const SurArgs s, const Assess
             w5[ks][e] = s.pw.w5[r * net::H2 + n];   // rows 4..15 of the packed W5 are zero
         }
 
+    float b5[4];
+    for (int j = 0; j < 4; ++j) b5[j] = s.theta[net::OFF_B5 + j];
+
     // Per-cell part of the fallback rule and the plane height offset.
     const int cy = (int)(cell / s.W), cx = (int)(cell % s.W);
-    float kn;
-    const float hc = height_at(s, cy, cx, &kn);
-    const bool out_of_dist = !(kn > 0.f) || s.known[cell] < s.min_known;
+    float hc;
+    const bool has_ref = ref_height(s, cy, cx, &hc);
+    const bool out_of_dist = !has_ref || s.known[cell] < s.min_known;
+    // Every load above is complete before the loop: a wait inside it would
+    // also wait for the previous unit's stores.
+    __builtin_amdgcn_s_waitcnt(0);
 
     for (int u = 0; u < s.U; ++u) {
         f32x4 acc[4];
@@ -286,10 +329,10 @@ __global__ __launch_bounds__(256) void head_kernel(const SurArgs s, const Assess
         }
         // Lanes of group 0 hold the four outputs of state (cell, u).
         if (g == 0 && real) {
-            const float o0 = y3[0] + s.theta[net::OFF_B5 + 0];
-            const float o1 = y3[1] + s.theta[net::OFF_B5 + 1];
-            const float o2 = y3[2] + s.theta[net::OFF_B5 + 2];
-            const float o3 = y3[3] + s.theta[net::OFF_B5 + 3];
+            const float o0 = y3[0] + b5[0];
+            const float o1 = y3[1] + b5[1];
+            const float o2 = y3[2] + b5[2];
+            const float o3 = y3[3] + b5[3];
             const float risk = fminf(fmaxf(o3, 0.f), 1.f);
             const bool fb = out_of_dist || fabsf(risk - s.risk_max) < s.band;
             s.need[(int64_t)u * cells + cell] = fb ? 1 : 0;

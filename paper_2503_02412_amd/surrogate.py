@@ -12,6 +12,19 @@ from . import inputs as I
 from . import seb
 
 
+def has_reference(maps: np.ndarray) -> np.ndarray:
+    """Cells of [n][H][W] height maps whose state has a height reference for
+    the network's z output: the cell or one of its in-map 8-neighbours known."""
+    known = np.isfinite(maps) & (np.abs(maps) < 2.0 ** 60)
+    pad = np.pad(known, ((0, 0), (1, 1), (1, 1)))
+    H, W = maps.shape[1:]
+    out = np.zeros_like(known)
+    for dy in range(3):
+        for dx in range(3):
+            out |= pad[:, dy:dy + H, dx:dx + W]
+    return out
+
+
 class TrainingData:
     """Training maps, their plain-method labels and the sample list, on the GPU."""
 
@@ -33,12 +46,12 @@ class TrainingData:
                 ctx.assess(self.maps[i], out)
         torch.cuda.synchronize()
         # Samples: yaw bins of the first half (the second half mirrors them),
-        # every cell (windows may reach past the map edge), own cell known,
-        # plain fit valid.
+        # every cell (windows may reach past the map edge) with a reference
+        # height (own cell or an 8-neighbour known), plain fit valid.
         cand = I.surrogate_samples(n, params.width, K // 2 if K % 2 == 0 else K, sample_seed)
         st = status.cpu().numpy()
         ok = (st[cand[:, 0], cand[:, 3], cand[:, 1], cand[:, 2]] & seb.ST_VALID) > 0
-        ok &= np.isfinite(maps[cand[:, 0], cand[:, 1], cand[:, 2]])
+        ok &= has_reference(maps)[cand[:, 0], cand[:, 1], cand[:, 2]]
         cand = cand[ok]
         if count is not None:
             cand = cand[:count]

@@ -29,7 +29,12 @@ def random_setup(n_maps=3, size=40, B=64, seed=0):
     maps = np.stack([I.surrogate_training_map(7000 + i, size) for i in range(n_maps)])
     K = 12
     known = np.argwhere(np.isfinite(maps))            # (map, y, x) of known cells
-    pick = known[rng.integers(0, len(known), B)]
+    # holes whose z target is relative to the mean of their known neighbours
+    holes = np.array([c for c in np.argwhere(~np.isfinite(maps))
+                      if S.reference_height(maps[c[0]], c[1], c[2]) is not None])
+    assert len(holes) >= 8
+    pick = np.concatenate([known[rng.integers(0, len(known), B - 8)],
+                           holes[rng.integers(0, len(holes), 8)]])
     samp = np.c_[pick, rng.integers(0, K, B)].astype(np.int32)
     labels = {k: rng.normal(0, 0.3, (n_maps, K, size, size)).astype(np.float32)
               for k in ("z", "roll", "pitch", "risk")}

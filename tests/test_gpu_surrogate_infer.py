@@ -4,6 +4,7 @@ against the oracle."""
 import numpy as np
 import pytest
 
+from oracle import surrogate as S
 from paper_2503_02412_amd import inputs as I
 from paper_2503_02412_amd import seb
 from parity import compare, to_numpy
@@ -28,14 +29,18 @@ def test_map_form_equals_patch_form():
     with seb.Context(p) as ctx:
         sur = seb.Surrogate(ctx)
         dh = torch.from_numpy(h).cuda()
-        # no fallback except unknown own cells
+        # no fallback except states without a reference height
         out = sur.infer(net, dh, band=0.0, min_known=0.0)
         torch.cuda.synchronize()
         g = to_numpy(out)
     K, U = p.n_yaw, p.n_yaw // 2
     cy, cx, k = np.meshgrid(np.arange(p.height), np.arange(p.width), np.arange(U), indexing="ij")
     samp = np.stack([np.zeros(cy.size), cy.ravel(), cx.ravel(), k.ravel()], 1).astype(np.int32)
-    known = np.isfinite(h[samp[:, 1], samp[:, 2]])
+    href = np.array([np.nan if r is None else r for r in
+                     (S.reference_height(h, y, x) for y in range(p.height) for x in range(p.width))]
+                    ).reshape(p.height, p.width)
+    assert np.isnan(href).mean() < np.isnan(h).mean()          # holes answered by the network
+    known = np.isfinite(href[samp[:, 1], samp[:, 2]])
     samp = samp[known]
     samp = samp[: len(samp) - len(samp) % 32]
     y = []
@@ -47,7 +52,8 @@ def test_map_form_equals_patch_form():
     sy, sx, sk = samp[:, 1], samp[:, 2], samp[:, 3]
     st = g["status"][sk, sy, sx]
     assert np.all(st & seb.ST_SURROGATE)
-    zf = (g["z"][sk, sy, sx] - h[sy, sx]) / 0.05
+    assert not np.any(g["status"][:, np.isnan(href)] & seb.ST_SURROGATE)   # no reference
+    zf = (g["z"][sk, sy, sx] - href[sy, sx]) / 0.05
     for got, ref, name in [(zf, y[:, 0], "z"), (g["roll"][sk, sy, sx] / 0.5, y[:, 1], "roll"),
                            (g["pitch"][sk, sy, sx] / 0.5, y[:, 2], "pitch")]:
         err = np.abs(got - ref).max() / (np.abs(ref).max() + 1e-9)

@@ -50,6 +50,30 @@ def test_encode_plane_and_holes():
     assert X3[2, 0, 0] == 0 and X3[2, 12, 12] == 1 and X3[2, 12, 15] == 0
 
 
+def test_reference_height():
+    """The z target is relative to the own cell, else the mean of the known
+    8-neighbours (in-map only), else undefined."""
+    H = np.arange(1.0, 10.0).reshape(3, 3).astype(np.float32)
+    assert S.reference_height(H, 1, 1) == 5.0
+    H[1, 1] = np.nan
+    assert S.reference_height(H, 1, 1) == 5.0          # (1+2+3+4+6+7+8+9) / 8
+    H[0, 0] = np.inf                                    # +-Inf is unknown too
+    assert S.reference_height(H, 1, 1) == 39.0 / 7
+    H[0, 2] = 2.0 ** 61                                 # beyond the height limit
+    assert S.reference_height(H, 1, 1) == 6.0
+    G = np.full((4, 5), np.nan, np.float32)
+    G[1, 1], G[0, 1], G[3, 4] = 0.5, 1.5, 9.0
+    assert S.reference_height(G, 0, 0) == 1.0           # corner: 3 in-map neighbours
+    assert S.reference_height(G, 1, 3) is None and S.reference_height(G, 3, 3) == 9.0
+    # a plane: the neighbour mean of a hole is the plane's height there
+    iy, ix = np.mgrid[0:9, 0:9]
+    P = (0.3 * ix - 0.7 * iy + 2.0).astype(np.float64)
+    P[4, 4] = np.nan
+    assert abs(S.reference_height(P, 4, 4) - (0.3 * 4 - 0.7 * 4 + 2.0)) < 1e-12
+    t = S.targets(P, 1.6, 0.1, -0.2, 0.3, 4, 4)
+    assert np.allclose(t, [(1.6 - 0.4) / S.S_Z, 0.1 / S.S_A, -0.2 / S.S_A, 0.3])
+
+
 def test_gradients_match_finite_differences():
     rng = np.random.default_rng(2)
     P = small_params(rng, 0.2)
