@@ -135,55 +135,60 @@ template <int TF>
 __global__ __launch_bounds__(64) void compact_kernel(const AssessArgs a) {
     constexpr int mbx = TF / 16;
     constexpr int steps = TF * TF / 64;      // 16 (TF = 32) or 4 (TF = 16)
-    __shared__ int bb[steps][4];
+    __shared__ uint16_t list[TF * TF];
     const int lane = threadIdx.x;
     const int blk = blockIdx.x, u = blockIdx.y;
     const int tiles_x = (a.W + TF - 1) / TF;
     const int64_t slot = (int64_t)u * gridDim.x + blk;
     const int sx0 = (blk % tiles_x) * TF, sy0 = (blk / tiles_x) * TF;
     const int64_t plane = (int64_t)a.W * a.H;
-    // Step k covers micro-block k: ordinal 64 k + lane.  Unrolled, so the
-    // mask bytes of all steps are requested at once.
-    uint32_t flags = 0u;
+    // Step k covers micro-block k: ordinal 64 k + lane.  Unrolled, with
+    // clamped unconditional loads, so the mask bytes of all steps are
+    // requested at once (a guarded load would wait for its own result).
+    uint8_t nb[steps];
+    uint32_t inside = 0u;
 #pragma unroll
     for (int k = 0; k < steps; ++k) {
         const int ly = (k / mbx) * 4 + (lane >> 4), lx = (k % mbx) * 16 + (lane & 15);
         const int ix = sx0 + lx, iy = sy0 + ly;
-        bool f = false;
-        if (ix < a.W && iy < a.H) {
-            const int64_t c = (int64_t)wrap(iy + a.ry, a.H) * a.W + wrap(ix + a.rx, a.W);
-            f = a.need[(int64_t)u * plane + c] != 0;
-        }
-        if (f) flags |= 1u << k;
+        inside |= (uint32_t)(ix < a.W && iy < a.H) << k;
+        const int cx = min(ix, a.W - 1), cy = min(iy, a.H - 1);
+        nb[k] = a.need[(int64_t)u * plane + (int64_t)wrap(cy + a.ry, a.H) * a.W + wrap(cx + a.rx, a.W)];
     }
-    if (lane < steps) {
-        bb[lane][0] = TF;
-        bb[lane][1] = TF;
-        bb[lane][2] = 0;
-        bb[lane][3] = 0;
-    }
-    __syncthreads();
+    uint32_t flags = 0u;
+#pragma unroll
+    for (int k = 0; k < steps; ++k) flags |= (uint32_t)(nb[k] != 0) << k;
+    flags &= inside;
     int pos = 0;
 #pragma unroll
     for (int k = 0; k < steps; ++k) {
         const bool f = (flags >> k) & 1u;
         const uint64_t m = __ballot(f);
         if (f) {
-            const int i = pos + __popcll(m & ((1ull << lane) - 1ull));
             const int ly = (k / mbx) * 4 + (lane >> 4), lx = (k % mbx) * 16 + (lane & 15);
-            a.work_cells[slot * (TF * TF) + i] = (uint16_t)(ly * TF + lx);
-            atomicMin(&bb[i >> 6][0], lx);
-            atomicMin(&bb[i >> 6][1], ly);
-            atomicMax(&bb[i >> 6][2], lx);
-            atomicMax(&bb[i >> 6][3], ly);
+            list[pos + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)(ly * TF + lx);
         }
         pos += __popcll(m);
     }
     __syncthreads();
     if (lane == 0) a.block_count[slot] = pos;
-    if (lane < (pos + 63) / 64)
-        a.item_box[slot * steps + lane] =
-            bb[lane][0] | (bb[lane][1] << 5) | (bb[lane][2] << 10) | (bb[lane][3] << 15);
+    for (int t = 0; 64 * t < pos; ++t) {
+        const int n = min(64, pos - 64 * t);
+        const bool v = lane < n;
+        const int c = list[64 * t + min(lane, n - 1)];
+        const int ly = c / TF, lx = c % TF;
+        if (v) a.work_cells[slot * (TF * TF) + 64 * t + lane] = (uint16_t)c;
+        // Bounding box of the item's cells (wave reductions).
+        int x0 = v ? lx : TF, y0 = v ? ly : TF, x1 = v ? lx : 0, y1 = v ? ly : 0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            x0 = min(x0, __shfl_xor(x0, o));
+            y0 = min(y0, __shfl_xor(y0, o));
+            x1 = max(x1, __shfl_xor(x1, o));
+            y1 = max(y1, __shfl_xor(y1, o));
+        }
+        if (lane == 0) a.item_box[slot * steps + t] = x0 | (y0 << 5) | (x1 << 10) | (y1 << 15);
+    }
 }
 
 // Dense list of work items from the per-(unit, block) counts: one workgroup,
@@ -247,26 +252,44 @@ __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, cons
         const int bh = ((it.z >> 15) & 31) - by0 + 1 + 2 * R;
         // Block origin moved to the bounding box of the item's cells.
         const int sx0 = (it.x % tiles_x) * TF + bx0, sy0 = (it.x / tiles_x) * TF + by0;
-        for (int ly = wave; ly < bh; ly += BLOCK / 64) {
-            const int gy = sy0 - R + ly;
-            const bool row_in = gy >= 0 && gy < a.H;
-            const float* hrow = a.height + (int64_t)(row_in ? wrap(gy + a.ry, a.H) : 0) * a.ld;
-            for (int lx = lane; lx < bw; lx += 64) {
-                const int gx = sx0 - R + lx;
-                float v = SENTINEL;
-                if (row_in && gx >= 0 && gx < a.W) {
-                    const float h = hrow[wrap(gx + a.rx, a.W)];
-                    if (fabsf(h) < HEIGHT_LIMIT) v = h;      // false for NaN and +-Inf
-                }
-                tile[ly * P + lx] = v;
-            }
-        }
-        __syncthreads();
         const bool act = lane < (it.w & 255);
         // Lanes past the item's count take the box corner (staged, not stored).
         const int64_t slot = (int64_t)u * ((a.W + TF - 1) / TF) * ((a.H + TF - 1) / TF) + it.x;
         const int li = act ? a.work_cells[slot * (TF * TF) + 64 * (it.w >> 8) + lane]
                            : by0 * TF + bx0;
+        // Staging: SB elements of the box per thread and batch, loaded from
+        // clamped positions without a guard so the batch's loads are all in
+        // flight together; out-of-map and unknown cells become SENTINEL.
+        // A workgroup holds a few dozen states, so the latency of these loads,
+        // not their bandwidth, is what the staging costs.
+        constexpr int SB = 8;
+        const int n = bw * bh;
+        const float inv_bw = 1.f / (float)bw;
+        for (int i0 = tid; i0 < n; i0 += BLOCK * SB) {
+            float v[SB];
+            int pos[SB];
+            uint32_t ok = 0u;
+#pragma unroll
+            for (int j = 0; j < SB; ++j) {
+                const int i = min(i0 + BLOCK * j, n - 1);
+                // i / bw from the float quotient (i < 2^24), corrected by one either way
+                int ly = (int)((float)i * inv_bw);
+                ly += (i - ly * bw >= bw) ? 1 : 0;
+                ly -= (i - ly * bw < 0) ? 1 : 0;
+                const int lx = i - ly * bw;
+                const int gy = sy0 - R + ly, gx = sx0 - R + lx;
+                ok |= (uint32_t)(gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) << j;
+                const int cy = min(max(gy, 0), a.H - 1), cx = min(max(gx, 0), a.W - 1);
+                v[j] = a.height[(int64_t)wrap(cy + a.ry, a.H) * a.ld + wrap(cx + a.rx, a.W)];
+                pos[j] = ly * P + lx;
+            }
+#pragma unroll
+            for (int j = 0; j < SB; ++j) {
+                const bool keep = ((ok >> j) & 1u) && fabsf(v[j]) < HEIGHT_LIMIT;  // false for NaN, Inf
+                if (i0 + BLOCK * j < n) tile[pos[j]] = keep ? v[j] : SENTINEL;
+            }
+        }
+        __syncthreads();
         const int ly = li / TF - by0, lx = li % TF - bx0;   // relative to the bounding box
         const float* tp0 = tile + (ly + R) * P + (lx + R);
         const float hc = tp0[0];

@@ -50,21 +50,32 @@ __device__ __forceinline__ float height_at(const SurArgs& s, int y, int x, float
 }
 
 // Height the z output is relative to: the cell's own height when known, else
-// the mean of its known 8-neighbours (false when none is known).
+// the mean of its known 8-neighbours, summed in row-major order (false when
+// none is known).  The nine loads are issued together from clamped positions
+// and masked afterwards.
 __device__ __forceinline__ bool ref_height(const SurArgs& s, int cy, int cx, float* h) {
-    float v;
-    const float h0 = height_at(s, cy, cx, &v);
-    if (v > 0.f) {
-        *h = h0;
+    float v[9];
+    uint32_t known = 0u;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int y = cy + k / 3 - 1, x = cx + k % 3 - 1;
+        known |= (uint32_t)(y >= 0 && x >= 0 && y < s.H && x < s.W) << k;
+        v[k] = s.height[(int64_t)min(max(y, 0), s.H - 1) * s.ld + min(max(x, 0), s.W - 1)];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        if (!(fabsf(v[k]) < HEIGHT_LIMIT)) known &= ~(1u << k);
+    if (known & (1u << 4)) {
+        *h = v[4];
         return true;
     }
     float sum = 0.f, n = 0.f;
-    for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-            if (dy == 0 && dx == 0) continue;
-            sum += height_at(s, cy + dy, cx + dx, &v);        // 0 when unknown
-            n += v;
-        }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        if (k == 4 || !((known >> k) & 1u)) continue;
+        sum += v[k];
+        n += 1.f;
+    }
     *h = n > 0.f ? sum / n : 0.f;
     return n > 0.f;
 }
@@ -257,7 +268,18 @@ __global__ __launch_bounds__(256) void prep_kernel(const SurArgs s) {
 // go to 16 consecutive cells of one yaw plane.
 __global__ __launch_bounds__(256) void head_kernel(const SurArgs s, const AssessArgs a) {
     extern __shared__ float ys[];            // [U][128] yaw term, shared by the workgroup
-    for (int i = threadIdx.x; i < s.U * net::H1; i += 256) ys[i] = s.Y[i];
+    {
+        // Eight loads per thread in flight before the LDS writes.
+        const int n = s.U * net::H1;
+        for (int i0 = threadIdx.x; i0 < n; i0 += 256 * 8) {
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = s.Y[min(i0 + 256 * j, n - 1)];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (i0 + 256 * j < n) ys[i0 + 256 * j] = v[j];
+        }
+    }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
