@@ -237,7 +237,9 @@ template <int P, int NW, int FIT>
 __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, const int TF) {
     extern __shared__ float tile[];
     __shared__ Parts parts;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // The wave index, and with it the wave's footprint rows and every table
+    // address, marked wave-uniform so the table arrives by scalar loads.
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int R = a.R;
     const int tiles_x = (a.W + TF - 1) / TF;
     const int nr = a.n_segs;
@@ -296,7 +298,9 @@ __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, cons
         float ref = (fabsf(hc) < HEIGHT_LIMIT) ? hc : 0.f;
         bool need = act && !(fabsf(hc) < HEIGHT_LIMIT);
         Moments<float> m;
-        partial_moments<NW>(a, LdsSource<P>{tp0}, u, g0, g1, ref, need, m);
+        // Scattered lanes make every tile read a bank-conflicted one here, so
+        // samples that repeat their predecessor's corner cell skip the reads.
+        partial_moments<NW, LdsSource<P>, true>(a, LdsSource<P>{tp0}, u, g0, g1, ref, need, m);
         if (wave > 0) put_part(parts, wave, lane, m, ref, need);
         __syncthreads();
         if (wave == 0) {

@@ -254,12 +254,18 @@ constexpr int bits_for(int v) {
 // have no reference height yet (need); such a lane takes the raw value of
 // its first valid sample in table order as its reference (that sample then
 // counts as z = 0), which is exactly the value a separate search in table
-// order would find, since no earlier sample contributes.
-template <int NW, bool SEARCH, class Src>
+// order would find, since no earlier sample contributes.  REUSE: a sample
+// whose corner cell equals the previous sample's (a wave-uniform test on the
+// table) takes that sample's four heights instead of reading the tile again;
+// samples are half a cell apart, so about two in five repeat their quad.
+// (Reusing the two shared corners of a quad one cell over as well measured
+// slower: the extra branches cost more than the reads they save.)
+// (prev_o, hp) carry the previous sample's offset and heights.
+template <int NW, bool SEARCH, bool REUSE, class Src>
 __device__ __forceinline__ void accumulate_row(const Src& src, cptr<float4> W, cptr<int32_t> O,
                                                int i, int row1, float4 (&wn)[4], int (&on)[4],
                                                float& ref, bool& need, float& rz, uint32_t& pk,
-                                               Moments<float>& m) {
+                                               Moments<float>& m, int& prev_o, float (&hp)[4]) {
     constexpr int kQoff = NW - 1;
     constexpr int kSh2 = 6 + bits_for(NW * 2 * kQoff);
     constexpr int CH = 4;
@@ -270,8 +276,29 @@ __device__ __forceinline__ void accumulate_row(const Src& src, cptr<float4> W, c
 #pragma unroll
         for (int s = 0; s < CH; ++s) { w[s] = wn[s]; o[s] = on[s]; }
         float h[CH][4];
+        if constexpr (REUSE) {
+            // A wave-uniform branch per sample.  Each repeat waits for the
+            // previous sample's reads; measured, this still beats reading
+            // every quad and selecting afterwards.
 #pragma unroll
-        for (int s = 0; s < CH; ++s) src.quad(o[s], h[s][0], h[s][1], h[s][2], h[s][3]);
+            for (int s = 0; s < CH; ++s) {
+                const int po = s == 0 ? prev_o : o[s - 1];
+                if (o[s] == po) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) h[s][t] = s == 0 ? hp[t] : h[s - 1][t];
+                    continue;
+                }
+                src.quad(o[s], h[s][0], h[s][1], h[s][2], h[s][3]);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < CH; ++s) src.quad(o[s], h[s][0], h[s][1], h[s][2], h[s][3]);
+        }
+        if constexpr (REUSE) {
+            prev_o = o[CH - 1];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) hp[t] = h[CH - 1][t];
+        }
         // prefetch the next chunk's table entries (the last chunk of the
         // range re-loads itself, so no read leaves the unit's table)
         const int nx = min(i * NW + c + CH, row1 * NW - CH);
@@ -307,7 +334,7 @@ __device__ __forceinline__ void accumulate_row(const Src& src, cptr<float4> W, c
 // integer constants of each sample are compile-time values.  A row runs the
 // reference-adopting body only while some lane of the wave still lacks a
 // reference height (normally the first row or two).
-template <int NW, class Src>
+template <int NW, bool REUSE, class Src>
 __device__ __forceinline__ void accumulate_rows(const AssessArgs& a, const Src& src,
                                                 cptr<float4> W, cptr<int32_t> O, float& ref,
                                                 bool& need, Moments<float>& m, int row0,
@@ -330,17 +357,20 @@ __device__ __forceinline__ void accumulate_rows(const AssessArgs& a, const Src& 
     int on[CH];
 #pragma unroll
     for (int s = 0; s < CH; ++s) { wn[s] = W[row0 * NW + s]; on[s] = O[row0 * NW + s]; }
+    int prev_o = INT32_MIN;                  // no previous sample: never equal to an offset
+    float hp[4] = {0.f, 0.f, 0.f, 0.f};
     int i = row0;
     for (; i < row1 && __ballot(need); ++i, p += 2) {
         float rz = 0.f;
         uint32_t pk = 0u;
-        accumulate_row<NW, true>(src, W, O, i, row1, wn, on, ref, need, rz, pk, m);
+        accumulate_row<NW, true, REUSE>(src, W, O, i, row1, wn, on, ref, need, rz, pk, m, prev_o, hp);
         add_segment(m, p, pk, kQoff, kMask1, kSh2, rz);
     }
     for (; i < row1; ++i, p += 2) {
         float rz = 0.f;
         uint32_t pk = 0u;
-        accumulate_row<NW, false>(src, W, O, i, row1, wn, on, ref, need, rz, pk, m);
+        accumulate_row<NW, false, REUSE>(src, W, O, i, row1, wn, on, ref, need, rz, pk, m, prev_o,
+                                         hp);
         add_segment(m, p, pk, kQoff, kMask1, kSh2, rz);
     }
 }
@@ -447,7 +477,9 @@ __device__ __forceinline__ Result finish_state(const AssessArgs& a, const Src& s
 // FP32 moments of rows (segments) [g0, g1) of yaw unit u.  On entry ref is
 // the own cell's height, or 0 with need set when that cell is unknown; a lane
 // with need adopts its first valid sample in table order (see accumulate_rows).
-template <int NW, class Src>
+// REUSE: skip the tile reads of samples that repeat the previous sample's
+// corner cell (see accumulate_row).
+template <int NW, class Src, bool REUSE = false>
 __device__ __forceinline__ void partial_moments(const AssessArgs& a, const Src& src, int u, int g0,
                                                 int g1, float& ref, bool& need,
                                                 Moments<float>& m) {
@@ -455,7 +487,7 @@ __device__ __forceinline__ void partial_moments(const AssessArgs& a, const Src& 
     const cptr<float4> W = as_const(a.wts) + ub;
     const cptr<int32_t> O = as_const(a.offs) + ub;
     if constexpr (NW > 0) {
-        accumulate_rows<NW>(a, src, W, O, ref, need, m, g0, g1);
+        accumulate_rows<NW, REUSE>(a, src, W, O, ref, need, m, g0, g1);
     } else {
         if (__ballot(need))
             accumulate_segments<true>(a, src, W, O, ref, need, m, g0, g1);
