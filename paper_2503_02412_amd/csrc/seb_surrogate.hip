@@ -83,33 +83,79 @@ __device__ __forceinline__ bool ref_height(const SurArgs& s, int cy, int cx, flo
 // conv1 at every position (y1, x1) in [-12, H+8) x [-12, W+8): ReLU(b1 + W1 . input
 // window [y1, y1+4) x [x1, x1+4)); inputs and outputs rounded to bf16 as in training.
 __global__ __launch_bounds__(256) void conv1_map_kernel(const SurArgs s) {
-    __shared__ float w[net::C1 * net::K1];
-    for (int i = threadIdx.x; i < net::C1 * net::K1; i += 256) {
-        const int o = i / net::K1, c = i % net::K1;
-        w[i] = from_bf16(s.pw.w1[o * net::K1P + c]);
-    }
-    __syncthreads();
+    __shared__ float4 w[net::K1][net::C1 / 4];      // [input][output], transposed
     const int W1 = s.W + 20;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= (int64_t)(s.H + 20) * W1) return;
-    const int y1 = (int)(p / W1) - 12, x1 = (int)(p % W1) - 12;
+    const bool live = p < (int64_t)(s.H + 20) * W1;
+    const int64_t pc = live ? p : 0;
+    const int y1 = (int)(pc / W1) - 12, x1 = (int)(pc % W1) - 12;
+    // Every load of the thread is issued before the first wait: the 5 x 5
+    // heights the window's slopes use (clamped positions, masked afterwards:
+    // unknown and out-of-map cells read as 0 with weight 0), its three
+    // weights for the LDS table and the biases.
+    float hv[25], kv[25];
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+        const int y = y1 + k / 5, x = x1 + k % 5;
+        hv[k] = s.height[(int64_t)min(max(y, 0), s.H - 1) * s.ld + min(max(x, 0), s.W - 1)];
+        kv[k] = (y >= 0 && x >= 0 && y < s.H && x < s.W) ? 1.f : 0.f;
+    }
+    constexpr int NW1 = net::C1 * net::K1 / 256;
+    static_assert(net::C1 * net::K1 % 256 == 0, "conv1 weight staging assumes whole passes");
+    bf16 wv[NW1];
+#pragma unroll
+    for (int j = 0; j < NW1; ++j) {
+        const int i = threadIdx.x + 256 * j;
+        wv[j] = s.pw.w1[(i / net::K1) * net::K1P + i % net::K1];
+    }
+    float b1[net::C1];
+#pragma unroll
+    for (int o = 0; o < net::C1; ++o) b1[o] = s.theta[net::OFF_B1 + o];
+#pragma unroll
+    for (int j = 0; j < NW1; ++j) {
+        const int i = threadIdx.x + 256 * j;
+        reinterpret_cast<float*>(&w[i % net::K1][0])[i / net::K1] = from_bf16(wv[j]);
+    }
+    __syncthreads();
+    if (!live) return;
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+        const bool ok = kv[k] > 0.f && fabsf(hv[k]) < HEIGHT_LIMIT;
+        kv[k] = ok ? 1.f : 0.f;
+        hv[k] = ok ? hv[k] : 0.f;
+    }
     float in[net::K1];
+#pragma unroll
     for (int i = 0; i < 4; ++i)
+#pragma unroll
         for (int j = 0; j < 4; ++j) {
-            float v0, vx, vy;
-            const float h0 = height_at(s, y1 + i, x1 + j, &v0);
-            const float hx = height_at(s, y1 + i, x1 + j + 1, &vx);
-            const float hy = height_at(s, y1 + i + 1, x1 + j, &vy);
+            const int k = i * 5 + j;
+            const float v0 = kv[k], vx = kv[k + 1], vy = kv[k + 5];
+            const float h0 = hv[k], hx = hv[k + 1], hy = hv[k + 5];
             in[0 * 16 + i * 4 + j] = from_bf16(to_bf16(v0 * vx * (hx - h0) * s.inv_res));
             in[1 * 16 + i * 4 + j] = from_bf16(to_bf16(v0 * vy * (hy - h0) * s.inv_res));
             in[2 * 16 + i * 4 + j] = v0;
         }
-    bf16* out = s.o1map + p * net::C1;
-    for (int o = 0; o < net::C1; ++o) {
-        float acc = 0.f;
-        for (int c = 0; c < net::K1; ++c) acc = fmaf(w[o * net::K1 + c], in[c], acc);
-        out[o] = to_bf16(fmaxf(acc + s.theta[net::OFF_B1 + o], 0.f));
+    // The 16 outputs accumulate side by side (16 independent chains), each
+    // input's 16 weights arriving in four vector LDS reads; every output still
+    // sums its 48 products in input order.
+    float acc[net::C1];
+#pragma unroll
+    for (int o = 0; o < net::C1; ++o) acc[o] = 0.f;
+#pragma unroll
+    for (int c = 0; c < net::K1; ++c) {
+#pragma unroll
+        for (int q = 0; q < net::C1 / 4; ++q) {
+            const float4 wq = w[c][q];
+            acc[4 * q + 0] = fmaf(wq.x, in[c], acc[4 * q + 0]);
+            acc[4 * q + 1] = fmaf(wq.y, in[c], acc[4 * q + 1]);
+            acc[4 * q + 2] = fmaf(wq.z, in[c], acc[4 * q + 2]);
+            acc[4 * q + 3] = fmaf(wq.w, in[c], acc[4 * q + 3]);
+        }
     }
+    bf16* out = s.o1map + p * net::C1;
+#pragma unroll
+    for (int o = 0; o < net::C1; ++o) out[o] = to_bf16(fmaxf(acc[o] + b1[o], 0.f));
 }
 
 // conv2 at every position (y2, x2) in [-12, H+4) x [-12, W+4), dilation 2 on
@@ -151,52 +197,72 @@ __global__ __launch_bounds__(256) void conv2_map_kernel(const SurArgs s) {
 }
 
 // fc1 without the yaw term, per cell: T[cell][n] = b3[n] + W3[n] . (conv2 at
-// the 5 x 5 positions cell - 12 + 4 (a, b)).  Implicit GEMM: a workgroup owns 64
-// cells; wave w computes outputs [32 w, 32 w + 32).
+// the 5 x 5 positions cell - 12 + 4 (a, b)).  Implicit GEMM: a workgroup owns
+// FC1_CELLS cells.  For each row a of the 5 x 5 gather it stages the cells'
+// five conv2 vectors (FC1_CELLS x 5 x 32 bf16) in LDS once, so the four waves
+// share them instead of each fetching them from L2; wave w then multiplies
+// them with W3's rows [32 w, 32 w + 32).  Each output still accumulates its 25
+// k-steps in order.
+constexpr int FC1_CELLS = 128;
+constexpr int FC1_STRIDE = net::P2 * net::C2 + 8;     // bf16 per cell in LDS (16 B pad)
+constexpr int FC1_ITEMS = FC1_CELLS * net::P2 * 4;    // 16-byte pieces staged per gather row
+static_assert(FC1_ITEMS % 256 == 0, "fc1 staging assumes whole passes");
+
 __global__ __launch_bounds__(256) void fc1_map_kernel(const SurArgs s) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ bf16x8 As[FC1_CELLS * FC1_STRIDE / 8];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int W2 = s.W + 16;
     const int64_t cells = (int64_t)s.H * s.W;
-    const int64_t c0 = (int64_t)blockIdx.x * 64;
+    const int64_t c0 = (int64_t)blockIdx.x * FC1_CELLS;
     const int r = lane & 15, kq = lane >> 4;
-    int cy[4], cx[4];
-    for (int i = 0; i < 4; ++i) {
-        const int64_t c = min(c0 + 16 * i + r, cells - 1);
-        cy[i] = (int)(c / s.W);
-        cx[i] = (int)(c % s.W);
-    }
     // Biases first: a load issued after the stores below would wait for them.
     const float bias[2] = {s.theta[net::OFF_B3 + 32 * wave + r],
                            s.theta[net::OFF_B3 + 32 * wave + 16 + r]};
-    f32x4 acc[4][2];
-    for (int i = 0; i < 4; ++i)
-        for (int t = 0; t < 2; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // One conv2 row (a5) of the 5 x 5 gather per pass: its five k-steps' loads
-    // are all issued before the first product, so a wave waits five times per
-    // cell block instead of 25.
-    for (int a5 = 0; a5 < net::P2; ++a5) {
-        bf16x8 bfr[net::P2][2], afr[net::P2][4];
+    // Staging pieces of this thread: piece = tid + 256 j -> (cell, b, quarter).
+    constexpr int NJ = FC1_ITEMS / 256;
+    int64_t src[NJ];
+    int dst[NJ];
 #pragma unroll
-        for (int b5 = 0; b5 < net::P2; ++b5) {
-            const int ks = a5 * net::P2 + b5;
-            for (int t = 0; t < 2; ++t)
-                bfr[b5][t] = *(const bf16x8*)(s.pw.w3 + (int64_t)(32 * wave + 16 * t + r) * net::F +
-                                              32 * ks + 8 * kq);
-            for (int i = 0; i < 4; ++i) {
-                const int y2 = cy[i] - 12 + 4 * a5, x2 = cx[i] - 12 + 4 * b5;
-                afr[b5][i] = *(const bf16x8*)(s.o2map + ((int64_t)(y2 + 12) * W2 + (x2 + 12)) * net::C2 +
-                                              8 * kq);
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);   // keep every load ahead of the products
+    for (int j = 0; j < NJ; ++j) {
+        const int piece = tid + 256 * j;
+        const int cell = piece / (net::P2 * 4), rem = piece % (net::P2 * 4);
+        const int b5 = rem / 4, q = rem % 4;
+        const int64_t c = min(c0 + cell, cells - 1);
+        const int cy = (int)(c / s.W), cx = (int)(c % s.W);
+        // conv2 position (cy - 12 + 4 a, cx - 12 + 4 b) sits at row cy + 4 a, column cx + 4 b
+        src[j] = ((int64_t)cy * W2 + (cx + 4 * b5)) * net::C2 + 8 * q;
+        dst[j] = (cell * FC1_STRIDE + b5 * net::C2 + 8 * q) / 8;
+    }
+    f32x4 acc[FC1_CELLS / 16][2];
+#pragma unroll
+    for (int i = 0; i < FC1_CELLS / 16; ++i)
+        for (int t = 0; t < 2; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int a5 = 0; a5 < net::P2; ++a5) {
+        bf16x8 v[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+            v[j] = *(const bf16x8*)(s.o2map + src[j] + (int64_t)a5 * 4 * W2 * net::C2);
+        bf16x8 bfr[net::P2][2];
 #pragma unroll
         for (int b5 = 0; b5 < net::P2; ++b5)
-            for (int i = 0; i < 4; ++i)
+            for (int t = 0; t < 2; ++t)
+                bfr[b5][t] = *(const bf16x8*)(s.pw.w3 + (int64_t)(32 * wave + 16 * t + r) * net::F +
+                                              32 * (a5 * net::P2 + b5) + 8 * kq);
+        if (a5 > 0) __syncthreads();        // the previous row's products are done with As
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) As[dst[j]] = v[j];
+        __syncthreads();
+#pragma unroll
+        for (int b5 = 0; b5 < net::P2; ++b5)
+#pragma unroll
+            for (int i = 0; i < FC1_CELLS / 16; ++i) {
+                const bf16x8 a = As[((16 * i + r) * FC1_STRIDE + b5 * net::C2 + 8 * kq) / 8];
                 for (int t = 0; t < 2; ++t)
-                    acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[b5][i], bfr[b5][t], acc[i][t],
-                                                                         0, 0, 0);
+                    acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[b5][t], acc[i][t], 0, 0, 0);
+            }
     }
-    for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int i = 0; i < FC1_CELLS / 16; ++i)
         for (int t = 0; t < 2; ++t)
             for (int e = 0; e < 4; ++e) {
                 const int64_t c = c0 + 16 * i + 4 * kq + e;
@@ -229,11 +295,26 @@ __global__ __launch_bounds__(256) void prep_kernel(const SurArgs s) {
             s.Y[i] = sn * s.theta[net::OFF_WY + 2 * n] + cs * s.theta[net::OFF_WY + 2 * n + 1];
         }
     }
-    for (int i = tid; i < SPAN * SPAN; i += 256) {
-        const int r = i / SPAN, c = i % SPAN;
-        float v;
-        height_at(s, y0 - net::HALF + r, x0 - net::HALF + c, &v);
-        kf[r][c] = v;
+    {
+        // Known flags of the (16 + 23)^2 span: six loads per thread in flight,
+        // from clamped positions, masked afterwards.
+        constexpr int NB = (SPAN * SPAN + 255) / 256;
+        float hv[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i = min(tid + 256 * j, SPAN * SPAN - 1);
+            const int y = y0 - net::HALF + i / SPAN, x = x0 - net::HALF + i % SPAN;
+            hv[j] = s.height[(int64_t)min(max(y, 0), s.H - 1) * s.ld + min(max(x, 0), s.W - 1)];
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i = tid + 256 * j;
+            if (i >= SPAN * SPAN) continue;
+            const int r = i / SPAN, c = i % SPAN;
+            const int y = y0 - net::HALF + r, x = x0 - net::HALF + c;
+            const bool in = y >= 0 && x >= 0 && y < s.H && x < s.W;
+            kf[r][c] = (in && fabsf(hv[j]) < HEIGHT_LIMIT) ? 1.f : 0.f;
+        }
     }
     __syncthreads();
     for (int i = tid; i < SPAN * T; i += 256) {
@@ -382,7 +463,7 @@ hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, hipStream_t s
                        dim3(256), 0, stream, s);
     hipLaunchKernelGGL(conv2_map_kernel, dim3(blocks((int64_t)(s.H + 16) * (s.W + 16), 64)),
                        dim3(256), 0, stream, s);
-    hipLaunchKernelGGL(fc1_map_kernel, dim3(blocks(cells, 64)), dim3(256), 0, stream, s);
+    hipLaunchKernelGGL(fc1_map_kernel, dim3(blocks(cells, FC1_CELLS)), dim3(256), 0, stream, s);
     hipLaunchKernelGGL(head_kernel, dim3(blocks(cells, 64)), dim3(256),
                        (size_t)s.U * net::H1 * sizeof(float), stream, s, a);
     return hipGetLastError();
