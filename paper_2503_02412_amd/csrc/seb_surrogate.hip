@@ -374,10 +374,15 @@ __global__ __launch_bounds__(256) void head_kernel(const SurArgs s, const Assess
     float b4v[4][4];                         // [t][e]:  b4[16t + 4g + e]
     float tv[4][8];                          // [ks][e]: T[cell][32ks + 8g + e]
     bf16x8 w5[2];                            // [ks][e']: W5[r][neuron(ks, g, e')]
+    static_assert(net::OFF_B4 % 4 == 0, "fc2 biases are read as float4");
     for (int t = 0; t < 4; ++t) {
         for (int ks = 0; ks < 4; ++ks)
             w4[t][ks] = *(const bf16x8*)(s.pw.w4 + (16 * t + r) * net::H1 + 32 * ks + 8 * g);
-        for (int e = 0; e < 4; ++e) b4v[t][e] = s.theta[net::OFF_B4 + 16 * t + 4 * g + e];
+        const float4 b = *(const float4*)(s.theta + net::OFF_B4 + 16 * t + 4 * g);
+        b4v[t][0] = b.x;
+        b4v[t][1] = b.y;
+        b4v[t][2] = b.z;
+        b4v[t][3] = b.w;
     }
     for (int ks = 0; ks < 4; ++ks) {
         const float4* tp = (const float4*)(s.T + cell * net::H1 + 32 * ks + 8 * g);
@@ -385,11 +390,17 @@ __global__ __launch_bounds__(256) void head_kernel(const SurArgs s, const Assess
         tv[ks][0] = t0.x; tv[ks][1] = t0.y; tv[ks][2] = t0.z; tv[ks][3] = t0.w;
         tv[ks][4] = t1.x; tv[ks][5] = t1.y; tv[ks][6] = t1.z; tv[ks][7] = t1.w;
     }
-    for (int ks = 0; ks < 2; ++ks)
-        for (int e = 0; e < 8; ++e) {
-            const int n = 32 * ks + (e < 4 ? 4 * g + e : 16 + 4 * g + (e - 4));
-            w5[ks][e] = s.pw.w5[r * net::H2 + n];   // rows 4..15 of the packed W5 are zero
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    for (int ks = 0; ks < 2; ++ks) {
+        // neurons 32 ks + 4 g .. + 3, then 32 ks + 16 + 4 g .. + 3 (rows 4..15 of
+        // the packed W5 are zero)
+        const bf16x4 lo = *(const bf16x4*)(s.pw.w5 + r * net::H2 + 32 * ks + 4 * g);
+        const bf16x4 hi = *(const bf16x4*)(s.pw.w5 + r * net::H2 + 32 * ks + 16 + 4 * g);
+        for (int e = 0; e < 4; ++e) {
+            w5[ks][e] = lo[e];
+            w5[ks][4 + e] = hi[e];
         }
+    }
 
     float b5[4];
     for (int j = 0; j < 4; ++j) b5[j] = s.theta[net::OFF_B5 + j];
