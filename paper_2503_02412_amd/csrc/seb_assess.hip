@@ -117,10 +117,13 @@ void assess_kernel(const AssessArgs a) {
 // unit) lists the block's flagged cells for that yaw unit in 16 x 4
 // micro-block order (so a full item has the tiled kernel's lane pattern) into
 // the block's own slots, with the count and the bounding box of every 64-cell
-// item.  scan_kernel turns the counts into a dense list of items (prefix sum,
-// no atomics, so the list is the same on every run).
+// item.
 //
-// flagged_kernel: one workgroup per item.  For its item, the workgroup
+// flagged_kernel: one workgroup per possible item, item-major (workgroup
+// k * slots + slot takes item k of slot (unit, block)), so the first items of
+// every block come first and workgroups past a block's count return at once.
+// Its first wave also sums the blocks' counts into the optional state counter
+// (one wave reading them all: no atomics, and off the items' critical path).  For its item, the workgroup
 // stages the block's heights, and each of its four waves accumulates a
 // quarter of the footprint rows for the same 64 states; wave 0 adds the four
 // partial moment sets and finishes the states.  Four short waves per 64
@@ -191,48 +194,6 @@ __global__ __launch_bounds__(64) void compact_kernel(const AssessArgs a) {
     }
 }
 
-// Dense list of work items from the per-(unit, block) counts: one workgroup,
-// each thread takes a contiguous run of slots, then an exclusive scan of the
-// runs' item counts in LDS.
-__global__ __launch_bounds__(1024) void scan_kernel(const AssessArgs a, const int nslots,
-                                                    const int blocks, const int steps) {
-    __shared__ int part[1024];
-    const int tid = threadIdx.x;
-    const int per = (nslots + 1023) / 1024;
-    const int s0 = min(nslots, tid * per), s1 = min(nslots, s0 + per);
-    int items = 0, states = 0;
-    for (int q = s0; q < s1; ++q) {
-        const int n = a.block_count[q];
-        items += (n + 63) / 64;
-        states += n;
-    }
-    part[tid] = items;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {     // inclusive Hillis-Steele scan
-        const int v = tid >= o ? part[tid - o] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    int base = part[tid] - items;
-    for (int q = s0; q < s1; ++q) {
-        const int n = a.block_count[q];
-        for (int k = 0; k * 64 < n; ++k)
-            a.work_items[base++] = make_int4(q % blocks, q / blocks, a.item_box[(int64_t)q * steps + k],
-                                             min(64, n - 64 * k) | (k << 8));
-    }
-    // The last thread's run ends at the item total; the state total is a sum.
-    if (tid == 1023) *a.work_count = base;
-    __syncthreads();
-    part[tid] = states;
-    __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
-        if (tid < o) part[tid] += part[tid + o];
-        __syncthreads();
-    }
-    if (tid == 0 && a.count) *a.count = part[0] * (a.mirror ? 2 : 1);
-}
-
 template <int P, int NW, int FIT>
 __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, const int TF) {
     extern __shared__ float tile[];
@@ -245,20 +206,33 @@ __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, cons
     const int nr = a.n_segs;
     const int g0 = nr * wave / 4, g1 = nr * (wave + 1) / 4;
     {
-        const int t = blockIdx.x;            // one item per workgroup
-        if (t >= *a.work_count) return;
-        const int4 it = a.work_items[t];
-        const int u = it.y;
-        const int bx0 = it.z & 31, by0 = (it.z >> 5) & 31;
-        const int bw = ((it.z >> 10) & 31) - bx0 + 1 + 2 * R;
-        const int bh = ((it.z >> 15) & 31) - by0 + 1 + 2 * R;
+        const int blocks = tiles_x * ((a.H + TF - 1) / TF);
+        const int nslot = blocks * a.n_units;
+        if (blockIdx.x == 0 && wave == 0 && a.count) {
+            int total = 0;
+            for (int q0 = lane; q0 < nslot; q0 += 64 * 8) {      // eight loads in flight
+                int v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = a.block_count[min(q0 + 64 * j, nslot - 1)];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) total += q0 + 64 * j < nslot ? v[j] : 0;
+            }
+            for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o);
+            if (lane == 0) *a.count = total * (a.mirror ? 2 : 1);
+        }
+        const int k = blockIdx.x / nslot, slot = blockIdx.x % nslot;
+        const int cnt = a.block_count[slot];
+        if (64 * k >= cnt) return;
+        const int u = slot / blocks, blk = slot % blocks;
+        const int box = a.item_box[(int64_t)slot * (TF * TF / 64) + k];
+        const int bx0 = box & 31, by0 = (box >> 5) & 31;
+        const int bw = ((box >> 10) & 31) - bx0 + 1 + 2 * R;
+        const int bh = ((box >> 15) & 31) - by0 + 1 + 2 * R;
         // Block origin moved to the bounding box of the item's cells.
-        const int sx0 = (it.x % tiles_x) * TF + bx0, sy0 = (it.x / tiles_x) * TF + by0;
-        const bool act = lane < (it.w & 255);
+        const int sx0 = (blk % tiles_x) * TF + bx0, sy0 = (blk / tiles_x) * TF + by0;
+        const bool act = lane < min(64, cnt - 64 * k);
         // Lanes past the item's count take the box corner (staged, not stored).
-        const int64_t slot = (int64_t)u * ((a.W + TF - 1) / TF) * ((a.H + TF - 1) / TF) + it.x;
-        const int li = act ? a.work_cells[slot * (TF * TF) + 64 * (it.w >> 8) + lane]
-                           : by0 * TF + bx0;
+        const int li = act ? a.work_cells[(int64_t)slot * (TF * TF) + 64 * k + lane] : by0 * TF + bx0;
         // Staging: SB elements of the box per thread and batch, loaded from
         // clamped positions without a guard so the batch's loads are all in
         // flight together; out-of-map and unknown cells become SENTINEL.
@@ -426,8 +400,8 @@ int64_t flagged_work_items(int W, int H, int n_units, int R, int pitch) {
 }
 
 hipError_t launch_assess_flagged(const AssessArgs& a, int pitch, hipStream_t stream) {
-    if (!a.need || !a.work_count || !a.work_items || !a.work_cells || !a.block_count ||
-        !a.item_box || a.W <= 0 || a.H <= 0 || a.n_units <= 0)
+    if (!a.need || !a.work_cells || !a.block_count || !a.item_box || a.W <= 0 || a.H <= 0 ||
+        a.n_units <= 0)
         return hipErrorInvalidValue;
     if (pitch != 48 && pitch != 80 && pitch != 112 && pitch != 144) return hipErrorInvalidValue;
     const int tf = flagged_tile(a.R, pitch);
@@ -436,9 +410,7 @@ hipError_t launch_assess_flagged(const AssessArgs& a, int pitch, hipStream_t str
         hipLaunchKernelGGL(compact_kernel<32>, dim3(blocks, a.n_units), dim3(64), 0, stream, a);
     else
         hipLaunchKernelGGL(compact_kernel<16>, dim3(blocks, a.n_units), dim3(64), 0, stream, a);
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, stream, a, blocks * a.n_units, blocks,
-                       tf * tf / 64);
-    // One workgroup per possible item; those past the list's length return.
+    // One workgroup per possible item; those past their block's count return.
     const int64_t max_items = flagged_work_items(a.W, a.H, a.n_units, a.R, pitch);
     const dim3 grid((unsigned)max_items);
     const size_t lds = (size_t)(tf + 2 * a.R) * pitch * sizeof(float);

@@ -758,8 +758,6 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
         al((void**)&w.o2map, (size_t)(H + 16) * (W + 16) * seb::net::C2 * 2) &&
         al((void**)&w.T, (size_t)cells * seb::net::H1 * 4) &&
         al((void**)&w.Y, (size_t)U * seb::net::H1 * 4) && al((void**)&w.known, (size_t)cells * 4) && al((void**)&w.need, (size_t)U * cells) &&
-        al((void**)&w.work_count, sizeof(int32_t)) &&
-        al((void**)&w.work_items, (size_t)max_items * sizeof(int4)) &&
         al((void**)&w.work_cells, (size_t)max_items * 64 * 2) &&
         al((void**)&w.block_count, (size_t)n_blocks * sizeof(int32_t)) &&
         al((void**)&w.item_box, (size_t)max_items * sizeof(int32_t));
@@ -816,8 +814,6 @@ int seb_surrogate_infer(seb_surrogate* s, const seb_net* net, const float* heigh
     // The plain method for the flagged states, compacted tile by tile.
     a.need = w.need;
     a.count = n_fallback_dev;
-    a.work_count = w.work_count;
-    a.work_items = w.work_items;
     a.work_cells = w.work_cells;
     a.block_count = w.block_count;
     a.item_box = w.item_box;

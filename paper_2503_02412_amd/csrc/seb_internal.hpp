@@ -89,8 +89,6 @@ struct AssessArgs {
                                  // flagged-state kernels assess (both mirror bins)
     // workspace of the flagged-state kernels (caller-owned, sized by
     // flagged_work_items; see launch_assess_flagged)
-    int32_t* work_count;         // number of work items
-    int4* work_items;            // (block, yaw unit, bounding box, entries | item << 8)
     uint16_t* work_cells;        // per (unit, block): its flagged cells, block-local
     int32_t* block_count;        // per (unit, block): number of flagged cells
     int32_t* item_box;           // per (unit, block, item): bounding box of the item's cells

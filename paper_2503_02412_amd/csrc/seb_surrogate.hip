@@ -284,10 +284,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const SurArgs s) {
     const int tid = threadIdx.x;
     const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
     if (blockIdx.x == 0 && blockIdx.y == 0) {
-        if (tid == 0) {
-            *s.work_count = 0;
-            if (s.n_fallback) *s.n_fallback = 0;
-        }
+        if (tid == 0 && s.n_fallback) *s.n_fallback = 0;
         for (int i = tid; i < s.U * net::H1; i += 256) {
             const int u = i / net::H1, n = i % net::H1;
             const double th = 2.0 * 3.14159265358979323846 * (double)u / (double)s.K;

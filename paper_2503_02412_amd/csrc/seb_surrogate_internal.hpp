@@ -29,9 +29,7 @@ struct SurArgs {
     float* known;                // [H*W]               known fraction of the 24 x 24 window
     uint8_t* need;               // [U][H*W]            1 = state falls back to the plain method
     int32_t* n_fallback;         // optional device counter of fallen-back states
-    int32_t* work_count;         // fallback work queue (see AssessArgs)
-    int4* work_items;
-    uint16_t* work_cells;
+    uint16_t* work_cells;        // fallback workspace (see AssessArgs)
     int32_t* block_count;
     int32_t* item_box;
     // fallback rule
