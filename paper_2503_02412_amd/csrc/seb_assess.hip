@@ -122,8 +122,8 @@ void assess_kernel(const AssessArgs a) {
 // flagged_kernel: one workgroup per possible item, item-major (workgroup
 // k * slots + slot takes item k of slot (unit, block)), so the first items of
 // every block come first and workgroups past a block's count return at once.
-// Its first wave also sums the blocks' counts into the optional state counter
-// (one wave reading them all: no atomics, and off the items' critical path).  For its item, the workgroup
+// Its first workgroups also add the blocks' counts to the optional state
+// counter, 2048 blocks per workgroup and one atomic add per wave.  For its item, the workgroup
 // stages the block's heights, and each of its four waves accumulates a
 // quarter of the footprint rows for the same 64 states; wave 0 adds the four
 // partial moment sets and finishes the states.  Four short waves per 64
@@ -208,17 +208,18 @@ __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, cons
     {
         const int blocks = tiles_x * ((a.H + TF - 1) / TF);
         const int nslot = blocks * a.n_units;
-        if (blockIdx.x == 0 && wave == 0 && a.count) {
+        if (a.count && (int64_t)blockIdx.x * (BLOCK * 8) < nslot) {
+            // Workgroup b sums slots [2048 b, 2048 b + 2048): eight loads per
+            // thread in flight, then one add per wave to the counter.
             int total = 0;
-            for (int q0 = lane; q0 < nslot; q0 += 64 * 8) {      // eight loads in flight
-                int v[8];
+            const int q0 = blockIdx.x * (BLOCK * 8) + tid;
+            int v[8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = a.block_count[min(q0 + 64 * j, nslot - 1)];
+            for (int j = 0; j < 8; ++j) v[j] = a.block_count[min(q0 + BLOCK * j, nslot - 1)];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) total += q0 + 64 * j < nslot ? v[j] : 0;
-            }
+            for (int j = 0; j < 8; ++j) total += q0 + BLOCK * j < nslot ? v[j] : 0;
             for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o);
-            if (lane == 0) *a.count = total * (a.mirror ? 2 : 1);
+            if (lane == 0 && total > 0) atomicAdd(a.count, total * (a.mirror ? 2 : 1));
         }
         const int k = blockIdx.x / nslot, slot = blockIdx.x % nslot;
         const int cnt = a.block_count[slot];

@@ -85,8 +85,9 @@ struct AssessArgs {
     int32_t fit;                 // 0 least-squares plane, 1 principal-component plane
     const uint8_t* need;         // [n_units][H][W] (ring cells) for the flagged-state
                                  // kernel: assess the states whose byte is nonzero
-    int32_t* count;              // optional: receives the number of states the
-                                 // flagged-state kernels assess (both mirror bins)
+    int32_t* count;              // optional, zero on entry: the flagged-state
+                                 // kernels add the number of states they assess
+                                 // (both mirror bins)
     // workspace of the flagged-state kernels (caller-owned, sized by
     // flagged_work_items; see launch_assess_flagged)
     uint16_t* work_cells;        // per (unit, block): its flagged cells, block-local

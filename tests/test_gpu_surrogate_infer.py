@@ -124,3 +124,27 @@ def test_forced_fallback_other_geometries(orc, case):
     for f in ("z", "roll", "pitch", "risk"):
         assert np.array_equal(np.isnan(a[f]), np.isnan(b[f])), f
         assert np.abs(a[f][v].astype(np.float64) - b[f][v]).max(initial=0.0) <= 2e-5, f
+
+
+def test_fallback_count_spans_several_summing_workgroups():
+    """The fallback count on a 400 x 400 map with 36 yaw bins (3042 block
+    slots, summed by two workgroups), every state forced to fall back, on two
+    calls in a row: the count equals the number of states each time, and the
+    states equal the plain kernel's."""
+    import torch
+    p = I.CONFIG2.with_(width=400, height=400)
+    h = I.fractal_terrain(400, 400, 0.1, seed=12, hole_frac=0.05)
+    net = seb.Net(seed=8, max_batch=256)
+    with seb.Context(p) as ctx:
+        sur = seb.Surrogate(ctx)
+        dh = torch.from_numpy(h).cuda()
+        nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+        for _ in range(2):
+            a = to_numpy(sur.infer(net, dh, band=10.0, min_known=0.0, n_fallback=nf))
+            torch.cuda.synchronize()
+            assert int(nf.item()) == p.n_states
+        b = to_numpy(ctx.assess(dh))
+    assert np.array_equal(a["status"] & 9, b["status"] & 9)
+    v = (b["status"] & 1) > 0
+    for f in ("z", "roll", "pitch", "risk"):
+        assert np.abs(a[f][v].astype(np.float64) - b[f][v]).max(initial=0.0) <= 2e-5, f
