@@ -12,8 +12,9 @@
 // z is predicted relative to a reference height: the own cell's, else the
 // mean of its known 8-neighbours.  Flagged states -- no reference, too few
 // known cells in the window (out of the training distribution), or predicted
-// risk within `band` of risk_max -- are marked in a per-state mask; the plain method then re-assesses exactly
-// those, compacted tile by tile (assess_flagged_kernel).
+// risk within `band` of risk_max -- are marked in a per-state mask; the plain
+// method then re-assesses exactly those, compacted block by block
+// (launch_assess_flagged: compact_kernel, then flagged_kernel).
 #include <cmath>
 
 #include "seb.h"
