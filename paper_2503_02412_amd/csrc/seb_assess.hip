@@ -21,9 +21,8 @@
 // positions (N, sum p, sum q, sum p^2, sum pq, sum q^2) give an exact gate
 // (enough samples, not collinear) and exact centred second moments; the
 // least-squares plane is then a closed-form 2 x 2 solve.
-#include <cmath>
-
 #include <algorithm>
+#include <cmath>
 
 #include "seb.h"
 #include "seb_internal.hpp"
@@ -197,7 +196,11 @@ __global__ __launch_bounds__(64) void compact_kernel(const AssessArgs a) {
 template <int P, int NW, int FIT>
 __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, const int TF) {
     extern __shared__ float tile[];
-    __shared__ Parts parts;
+    // Partial moments of waves 1..3: in FP32 mode the tile is dead once the
+    // moments are summed, so they reuse its start (after a barrier); the FP64
+    // redo reads the tile later, so with precision 1 they sit after it.
+    const size_t tile_words = (size_t)(TF + 2 * a.R) * P;
+    Parts& parts = *reinterpret_cast<Parts*>(a.precision == 1 ? tile + tile_words : tile);
     // The wave index, and with it the wave's footprint rows and every table
     // address, marked wave-uniform so the table arrives by scalar loads.
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -276,6 +279,7 @@ __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, cons
         // Scattered lanes make every tile read a bank-conflicted one here, so
         // samples that repeat their predecessor's corner cell skip the reads.
         partial_moments<NW, LdsSource<P>, true>(a, LdsSource<P>{tp0}, u, g0, g1, ref, need, m);
+        if (a.precision != 1) __syncthreads();    // every wave is done with the tile
         if (wave > 0) put_part(parts, wave, lane, m, ref, need);
         __syncthreads();
         if (wave == 0) {
@@ -414,7 +418,8 @@ hipError_t launch_assess_flagged(const AssessArgs& a, int pitch, hipStream_t str
     // One workgroup per possible item; those past their block's count return.
     const int64_t max_items = flagged_work_items(a.W, a.H, a.n_units, a.R, pitch);
     const dim3 grid((unsigned)max_items);
-    const size_t lds = (size_t)(tf + 2 * a.R) * pitch * sizeof(float);
+    const size_t tile_bytes = (size_t)(tf + 2 * a.R) * pitch * sizeof(float);
+    const size_t lds = a.precision == 1 ? tile_bytes + sizeof(Parts) : std::max(tile_bytes, sizeof(Parts));
     switch (pitch) {
         case 48: launch_flagged_p<48>(a, tf, grid, lds, stream); break;
         case 80: launch_flagged_p<80>(a, tf, grid, lds, stream); break;
