@@ -68,6 +68,8 @@ def _load():
         lib.orc_reach.restype = C.c_int
         lib.orc_reach.argtypes = [C.POINTER(_Params)] + [C.POINTER(C.c_int32)] * 4
         lib.orc_max_threads.restype = C.c_int
+        lib.orc_rho_full.restype = C.c_double
+        lib.orc_rho_full.argtypes = [C.POINTER(_Params), C.POINTER(C.c_int32)]
         _lib = lib
     return _lib
 
@@ -153,6 +155,15 @@ def reach(params) -> tuple[int, int, int, int]:
     v = [C.c_int32() for _ in range(4)]
     lib.orc_reach(C.byref(_params(params)), *[C.byref(x) for x in v])
     return tuple(int(x.value) for x in v)
+
+
+def rho_full(params) -> tuple[float, int]:
+    """(rho_full, n_total): 4 det / (D + E)^2 of the complete footprint's exact
+    integer scatter, and its sample count."""
+    lib = _load()
+    n = C.c_int32()
+    r = lib.orc_rho_full(C.byref(_params(params)), C.byref(n))
+    return float(r), int(n.value)
 
 
 def max_threads() -> int:

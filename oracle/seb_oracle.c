@@ -408,6 +408,15 @@ int orc_reach(const orc_params* P, int32_t* dx_min, int32_t* dx_max, int32_t* dy
     return 0;
 }
 
+/* rho_full of the configuration's footprint (the scale of the near-degenerate
+   threshold, Sec. V-B gate reading) and its sample count n_total. */
+double orc_rho_full(const orc_params* P, int32_t* n_total) {
+    int n;
+    double r = rho_full(P, &n);
+    if (n_total) *n_total = n;
+    return r;
+}
+
 int orc_max_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

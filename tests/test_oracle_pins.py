@@ -431,3 +431,134 @@ def test_ellipse_mask_counts(orc):
     expect = sum(1 for i in range(10) for j in range(6)
                  if ((2 * i + 1 - 10) / 10) ** 2 + ((2 * j + 1 - 6) / 6) ** 2 <= 1.0)
     assert r.n_valid[0] == expect < 60
+
+
+# --------------------------------------------------------------------------
+# The near-degenerate flag (status bit 8, the Sec. V-B gate reading): set when
+# 2N < n_total or rho = 4 det / (D + E)^2 of the valid samples' exact integer
+# scatter is below rho_full / 16, rho_full being the value of the complete
+# footprint.  The flag decides the GPU's FP64 path and must match exactly.
+# --------------------------------------------------------------------------
+
+from fractions import Fraction  # noqa: E402
+
+
+def _rho_closed_form(nl, nw):
+    """Complete nl x nw midpoint grid, p = 2i - (nl - 1), q = 2j - (nw - 1):
+    sum p = sum q = sum pq = 0 and sum p^2 = nw * nl (nl^2 - 1) / 3 (sum of
+    the squares of the odd numbers), sum q^2 = nl * nw (nw^2 - 1) / 3, so
+    D = N sum p^2, E = N sum q^2, F = 0 and rho = 4 a b / (a + b)^2 with
+    a = nl^2 - 1, b = nw^2 - 1."""
+    a, b = nl * nl - 1, nw * nw - 1
+    return Fraction(4 * a * b, (a + b) ** 2)
+
+
+@pytest.mark.parametrize("nl,nw,expect", [(6, 4, Fraction(21, 25)),
+                                          (20, 12, Fraction(57057, 73441)),
+                                          (40, 24, Fraction(919425, 1181569))])
+def test_rho_full_of_the_workload_footprints(orc, nl, nw, expect):
+    assert _rho_closed_form(nl, nw) == expect
+    r, n = orc.rho_full(I.Params(64, 64, 0.1, 8, 0.1 * nl, 0.1 * nw, nl, nw))
+    assert n == nl * nw
+    assert r == pytest.approx(float(expect), rel=1e-15, abs=0.0)
+
+
+def test_rho_full_closed_form_sweep(orc):
+    for nl in range(2, 41, 3):
+        for nw in range(2, 25, 2):
+            r, n = orc.rho_full(I.Params(64, 64, 0.1, 8, 0.1 * nl, 0.1 * nw, nl, nw))
+            assert n == nl * nw
+            assert r == pytest.approx(float(_rho_closed_form(nl, nw)), rel=1e-14, abs=0.0)
+
+
+@pytest.mark.parametrize("nl,nw", [(6, 4), (10, 6), (20, 12), (9, 7)])
+def test_rho_full_of_the_ellipse_from_eigenvalues(orc, nl, nw):
+    """Inscribed-ellipse footprint: rho = 4 det C / (tr C)^2 for the covariance
+    C of the kept (p, q), i.e. 4 l1 l2 / (l1 + l2)^2 of its eigenvalues."""
+    i, j = np.meshgrid(np.arange(nl), np.arange(nw), indexing="ij")
+    p, q = 2 * i + 1 - nl, 2 * j + 1 - nw
+    keep = (p * nw) ** 2 + (q * nl) ** 2 <= (nl * nw) ** 2
+    lam = np.linalg.eigvalsh(np.cov(np.stack([p[keep], q[keep]]).astype(float), bias=True))
+    expect = 4 * lam[0] * lam[1] / (lam[0] + lam[1]) ** 2
+    r, n = orc.rho_full(I.Params(64, 64, 0.1, 8, 0.1 * nl, 0.1 * nw, nl, nw, fp_shape=1))
+    assert n == int(keep.sum()) < nl * nw
+    assert r == pytest.approx(expect, rel=1e-12)
+
+
+def _subset_rho_ratio_min(nl, nw):
+    """Smallest rho / rho_full over every subset of the grid's samples with
+    2N >= n and a non-collinear scatter (brute force over all 2^n subsets)."""
+    n = nl * nw
+    i, j = np.meshgrid(np.arange(nl), np.arange(nw), indexing="ij")
+    P, Q = (2 * i - (nl - 1)).ravel(), (2 * j - (nw - 1)).ravel()
+    m = np.arange(1 << n, dtype=np.int64)
+    bits = ((m[:, None] >> np.arange(n)) & 1).astype(np.int64)
+    N = bits.sum(1)
+    Sp, Sq = bits @ P, bits @ Q
+    D = N * (bits @ (P * P)) - Sp * Sp
+    E = N * (bits @ (Q * Q)) - Sq * Sq
+    F = N * (bits @ (P * Q)) - Sp * Sq
+    det = D * E - F * F
+    ok = (2 * N >= n) & (det > 0)
+    rho = 4.0 * det[ok] / (D[ok] + E[ok]).astype(float) ** 2
+    return float(rho.min() / _rho_closed_form(nl, nw))
+
+
+def test_rho_branch_needs_a_thin_half_footprint():
+    """With at least half of the samples valid, no subset of these grids is
+    thin enough for rho < rho_full / 16: the rho term can only add the flag
+    to states that 2N < n_total already flags.  (The smallest ratios are
+    0.2-0.38; the design notes list the search up to 6 x 4.)"""
+    for nl, nw in ((3, 2), (4, 2), (4, 3), (4, 4), (5, 3), (6, 2)):
+        assert _subset_rho_ratio_min(nl, nw) > 0.19
+
+
+def _spaced_footprint():
+    """6 x 2 samples two cells apart: at yaw 0 sample (i, j) reads exactly the
+    one cell (2i - 5, 2j - 1) from the state (the offsets snap to integers),
+    so any set of valid samples is made by knowing exactly its cells."""
+    return I.Params(24, 24, 0.1, 4, 1.2, 0.4, 6, 2)
+
+
+def _map_with_samples(samples, cx=12, cy=12):
+    h = np.full((24, 24), np.nan, np.float32)
+    for i, j in samples:
+        h[cy + 2 * j - 1, cx + 2 * i - 5] = 0.05 * i - 0.03 * j + 0.01 * (i * j % 3)
+    return h
+
+
+def test_degen_flag_full_footprint_is_clear(orc):
+    p = _spaced_footprint()
+    r = orc.assess_list(p, _map_with_samples([(i, j) for i in range(6) for j in range(2)]),
+                        [12], [12], [0])
+    assert r.n_valid[0] == 12 and (r.status[0] & ST_VALID) and not (r.status[0] & ST_DEGEN)
+
+
+def test_degen_flag_half_footprint_boundary(orc):
+    p = _spaced_footprint()
+    # six samples, three per row: 2N = n_total, rho / rho_full = 0.99 -> clear
+    six = [(0, 0), (2, 0), (5, 0), (1, 1), (3, 1), (4, 1)]
+    r = orc.assess_list(p, _map_with_samples(six), [12], [12], [0])
+    assert r.n_valid[0] == 6 and (r.status[0] & ST_VALID) and not (r.status[0] & ST_DEGEN)
+    # one fewer: 2N < n_total -> set
+    r = orc.assess_list(p, _map_with_samples(six[:-1]), [12], [12], [0])
+    assert r.n_valid[0] == 5 and (r.status[0] & ST_VALID) and (r.status[0] & ST_DEGEN)
+
+
+def test_degen_flag_thinnest_half_footprint_is_clear(orc):
+    """The thinnest valid half of the 6 x 2 grid (brute force: half rows at
+    q = +1 for i < 3 and q = -1 for i >= 3) has rho / rho_full = 0.2286: inside
+    the /16 threshold's clear side, outside a /4 one."""
+    p = _spaced_footprint()
+    thin = [(0, 1), (1, 1), (2, 1), (3, 0), (4, 0), (5, 0)]
+    P = np.array([2 * i - 5 for i, _ in thin])
+    Q = np.array([2 * j - 1 for _, j in thin])
+    N = len(thin)
+    D = N * (P * P).sum() - P.sum() ** 2
+    E = N * (Q * Q).sum() - Q.sum() ** 2
+    F = N * (P * Q).sum() - P.sum() * Q.sum()
+    ratio = Fraction(4 * int(D * E - F * F), int(D + E) ** 2) / _rho_closed_form(6, 2)
+    assert abs(float(ratio) - _subset_rho_ratio_min(6, 2)) < 1e-12
+    assert Fraction(1, 16) < ratio < Fraction(1, 4)
+    r = orc.assess_list(p, _map_with_samples(thin), [12], [12], [0])
+    assert r.n_valid[0] == 6 and (r.status[0] & ST_VALID) and not (r.status[0] & ST_DEGEN)
