@@ -70,6 +70,9 @@ def _load():
         lib.orc_max_threads.restype = C.c_int
         lib.orc_rho_full.restype = C.c_double
         lib.orc_rho_full.argtypes = [C.POINTER(_Params), C.POINTER(C.c_int32)]
+        lib.orc_gate_points.restype = C.c_int
+        lib.orc_gate_points.argtypes = [C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int,
+                                        C.c_int, C.c_int, C.c_double]
         _lib = lib
     return _lib
 
@@ -168,3 +171,15 @@ def rho_full(params) -> tuple[float, int]:
 
 def max_threads() -> int:
     return int(_load().orc_max_threads())
+
+
+def gate_points(p, q, min_valid: int, n_total: int, rho_f: float) -> int:
+    """Gate of the fit for valid samples at integer body-grid coordinates
+    (p[m], q[m]): -1 no fit, 0 fit, 1 near-degenerate fit (Sec. V-B gate
+    reading: fewer than half the samples, or rho below rho_full / 16)."""
+    lib = _load()
+    pa = np.ascontiguousarray(p, dtype=np.int32)
+    qa = np.ascontiguousarray(q, dtype=np.int32)
+    assert pa.shape == qa.shape and pa.ndim == 1
+    return int(lib.orc_gate_points(_ptr(pa, C.c_int32), _ptr(qa, C.c_int32), int(pa.size),
+                                   int(min_valid), int(n_total), float(rho_f)))

@@ -186,6 +186,21 @@ static double rho_full(const orc_params* P, int* n_total) {
     return (de > 0) ? (4.0 * (double)det) / (de * de) : 0.0;
 }
 
+/* The exact gate of the fit on the integer sample coordinates (p, q) of the
+   valid samples (N, sums and sums of products): -1 = no fit (fewer than
+   min_valid samples, or all of them on one line: det = 0), 0 = fit,
+   1 = fit on a near-degenerate footprint, i.e. fewer than half of the n_total
+   samples, or rho = 4 det / (D + E)^2 below rho_f / 16. */
+static int gate(int64_t N, int64_t Sp, int64_t Sq, int64_t Spp, int64_t Spq, int64_t Sqq,
+                int min_valid, int n_total, double rho_f) {
+    int64_t D = N * Spp - Sp * Sp, E = N * Sqq - Sq * Sq, F = N * Spq - Sp * Sq;
+    int64_t det = D * E - F * F;
+    if (N < min_valid || det <= 0) return -1;
+    double de = (double)(D + E);
+    double rho = (4.0 * (double)det) / (de * de);
+    return (2 * N < n_total || rho < rho_f / 16.0) ? 1 : 0;
+}
+
 static void assess_state(const orc_params* P, const float* H, int64_t ld, int ix, int iy,
                          int k, double rho_f, int n_total, orc_state* out) {
     const double theta = 2.0 * ORC_PI * (double)k / (double)P->n_yaw;
@@ -209,9 +224,8 @@ static void assess_state(const orc_params* P, const float* H, int64_t ld, int ix
     memset(out, 0, sizeof(*out));
     out->n_valid = n;
     /* Exact gate: enough points and not all on one line (integer scatter). */
-    int64_t D = N * Spp - Sp * Sp, E = N * Sqq - Sq * Sq, F = N * Spq - Sp * Sq;
-    int64_t det = D * E - F * F;
-    if (N < P->min_valid || det <= 0) {
+    const int g = gate(N, Sp, Sq, Spp, Spq, Sqq, P->min_valid, n_total, rho_f);
+    if (g < 0) {
         out->z = out->roll = out->pitch = NAN;
         out->kappa = out->phi_x = out->phi_y = NAN;
         out->risk = 1.0;
@@ -220,11 +234,7 @@ static void assess_state(const orc_params* P, const float* H, int64_t ld, int ix
         return;
     }
     uint8_t status = ST_VALID;
-    {
-        double de = (double)(D + E);
-        double rho = (4.0 * (double)det) / (de * de);
-        if (2 * N < n_total || rho < rho_f / 16.0) status |= ST_DEGEN;
-    }
+    if (g > 0) status |= ST_DEGEN;
 
     /* GetMeanPosition and the covariance accumulation of Algorithm 1. */
     double mean[3] = {0, 0, 0};
@@ -415,6 +425,20 @@ double orc_rho_full(const orc_params* P, int32_t* n_total) {
     double r = rho_full(P, &n);
     if (n_total) *n_total = n;
     return r;
+}
+
+/* The gate of a set of n valid samples given by their integer body-grid
+   coordinates (p[m], q[m]) (the sample at body (u, v) = (p du/2, q dv/2)),
+   for a footprint of n_total samples whose complete set has rho_full rho_f:
+   -1 no fit, 0 fit, 1 near-degenerate fit. */
+int orc_gate_points(const int32_t* p, const int32_t* q, int n, int min_valid, int n_total,
+                    double rho_f) {
+    int64_t N = 0, Sp = 0, Sq = 0, Spp = 0, Spq = 0, Sqq = 0;
+    for (int m = 0; m < n; ++m) {
+        N += 1; Sp += p[m]; Sq += q[m];
+        Spp += (int64_t)p[m] * p[m]; Spq += (int64_t)p[m] * q[m]; Sqq += (int64_t)q[m] * q[m];
+    }
+    return gate(N, Sp, Sq, Spp, Spq, Sqq, min_valid, n_total, rho_f);
 }
 
 int orc_max_threads(void) {

@@ -562,3 +562,82 @@ def test_degen_flag_thinnest_half_footprint_is_clear(orc):
     assert Fraction(1, 16) < ratio < Fraction(1, 4)
     r = orc.assess_list(p, _map_with_samples(thin), [12], [12], [0])
     assert r.n_valid[0] == 6 and (r.status[0] & ST_VALID) and not (r.status[0] & ST_DEGEN)
+
+
+# The gate as a predicate of the valid samples' integer coordinates.  Its
+# rho is pinned here through an independent characterisation: with D, E, F
+# the scatter of (p, q) times N, rho = 4 det / (D + E)^2 = 4 l1 l2 / (l1 + l2)^2
+# for the eigenvalues l1, l2 of the (p, q) covariance.  Rotated thin sets have
+# F != 0, so a gate that used D E in place of det would miss their flag.
+
+def _rho_eig(P, Q):
+    lam = np.linalg.eigvalsh(np.cov(np.stack([P, Q]).astype(float), bias=True))
+    return 4 * lam[0] * lam[1] / (lam[0] + lam[1]) ** 2
+
+
+def _diagonal_band(n, width):
+    """n samples along the body-grid diagonal p = q, alternately offset by
+    `width` grid steps across it: a thin, rotated cloud."""
+    t = np.arange(n)
+    P = 2 * t - (n - 1)
+    Q = P + 2 * width * (t % 2)
+    return P, Q
+
+
+@pytest.mark.parametrize("width,flag", [(1, 1), (2, 1), (4, 0), (5, 0)])
+def test_gate_flags_thin_rotated_sets(orc, width, flag):
+    P, Q = _diagonal_band(20, width)
+    rho_f = 57057 / 73441
+    ratio = _rho_eig(P, Q) / rho_f
+    # the cases sit well away from the /16 threshold, and the clear ones
+    # below a /4 threshold
+    if flag:
+        assert ratio < 1 / 16 * 0.8
+    else:
+        assert 1 / 16 * 1.2 < ratio < 1 / 4
+    # n_total = 2N: the sample-count branch stays clear, only rho decides
+    assert orc.gate_points(P, Q, 3, 2 * len(P), rho_f) == flag
+    # the scatter's cross term is far from zero on these sets
+    N = len(P)
+    F = N * int((P * Q).sum()) - int(P.sum()) * int(Q.sum())
+    D = N * int((P * P).sum()) - int(P.sum()) ** 2
+    assert abs(F) > 0.5 * D
+
+
+def test_gate_random_sets_match_the_eigenvalue_rule(orc):
+    rng = np.random.default_rng(11)
+    rho_f = 21 / 25
+    seen = {-1: 0, 0: 0, 1: 0}
+    for _ in range(3000):
+        n = int(rng.integers(1, 13))
+        a = rng.uniform(0, np.pi)
+        s = rng.uniform(0.05, 1.0)
+        t = rng.uniform(-8, 8, n)
+        e = rng.uniform(-8, 8, n) * s
+        P = np.rint(t * np.cos(a) - e * np.sin(a)).astype(np.int64)
+        Q = np.rint(t * np.sin(a) + e * np.cos(a)).astype(np.int64)
+        n_total = int(rng.integers(n, 2 * n + 2))
+        N = len(P)
+        lam = np.linalg.eigvalsh(np.cov(np.stack([P, Q]).astype(float), bias=True)) if N > 1 \
+            else np.zeros(2)
+        if N < 3 or lam[0] <= 1e-9 * max(lam[1], 1.0):
+            expect = -1
+        else:
+            rho = 4 * lam[0] * lam[1] / (lam[0] + lam[1]) ** 2
+            if abs(rho / (rho_f / 16) - 1) < 1e-9:
+                continue
+            expect = 1 if (2 * N < n_total or rho < rho_f / 16) else 0
+        got = orc.gate_points(P, Q, 3, n_total, rho_f)
+        assert got == expect, (P, Q, n_total)
+        seen[got] += 1
+    assert min(seen.values()) > 100, seen
+
+
+def test_gate_counts_and_collinear_sets(orc):
+    P = np.array([-3, -1, 1, 3])
+    assert orc.gate_points(P, 2 * P, 3, 4, 0.8) == -1           # collinear, det = 0
+    assert orc.gate_points(P[:2], np.array([1, -1]), 3, 2, 0.8) == -1   # N < min_valid
+    Q = np.array([-1, 1, -1, 1])
+    assert orc.gate_points(P, Q, 3, 8, 0.8) == 0                # 2N = n_total
+    assert orc.gate_points(P, Q, 3, 9, 0.8) == 1                # 2N < n_total
+    assert orc.gate_points(P, Q, 5, 8, 0.8) == -1               # min_valid 5
