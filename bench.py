@@ -262,7 +262,7 @@ def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4, p=N
     out = seb.alloc_outputs(p)
     nf = torch.zeros(1, dtype=torch.int32, device="cuda")
     err = {f: [] for f in ("z", "roll", "pitch", "risk")}
-    mask_ok, answered, fallback, t_sur, t_plain = 0, 0, [], [], []
+    mask_ok, answered, unsafe, fallback, t_sur, t_plain = 0, 0, 0, [], [], []
     for seed in I.SURROGATE_EVAL_SEEDS[:eval_maps]:
         h = I.config2_map(seed)
         dh = torch.from_numpy(h).cuda()
@@ -277,6 +277,8 @@ def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4, p=N
         for f in err:
             err[f].append(np.abs(g[f][m].astype(np.float64) - o[f][m]))
         mask_ok += int(np.sum(((g["status"][m] & 16) > 0) == ((o["status"][m] & 16) > 0)))
+        # unsafe direction: answered traversable where the plain method sets an obstacle bit
+        unsafe += int(np.count_nonzero(m & ((g["status"] & 16) > 0) & ((o["status"] & 6) > 0)))
     ms_sur, ms_plain = float(np.mean(t_sur)), float(np.mean(t_plain))
     return {
         "workload": "2-conv + 3-layer MLP (bf16, MFMA) on 24x24 slope/known patches + yaw; "
@@ -294,6 +296,8 @@ def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4, p=N
         "mean_abs_err": {f: float(np.concatenate(v).mean()) for f, v in err.items()},
         "max_abs_err": {f: float(np.concatenate(v).max()) for f, v in err.items()},
         "mask_agreement": mask_ok / max(1, answered),
+        "unsafe_traversable": unsafe,
+        "unsafe_traversable_fraction": unsafe / max(1, answered),
         "band": 0.1, "min_known": 0.5,
     }
 

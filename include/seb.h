@@ -188,7 +188,9 @@ int seb_update_window(seb_window* w, double x, double y, const float* new_cells,
  * Layers: conv 3->16 (4x4, stride 2), conv 16->32 (3x3, stride 2), fc
  * 800 + (sin yaw, cos yaw) -> 128 -> 64 -> 4, ReLU between layers; bf16
  * weights and activations, fp32 accumulation.  Outputs (dz/0.05 m,
- * roll/0.5 rad, pitch/0.5 rad, risk) with dz = z - height of the cell.
+ * roll/0.5 rad, pitch/0.5 rad, risk) with dz = z - h_ref, h_ref being the
+ * cell's own height when it is known, else the mean of its known in-map
+ * 8-neighbours (a cell with neither has no network answer).
  * Parameters: float32 vector of seb_net_param_count() values, in the order
  * W1[16][3][4][4] b1[16] W2[32][16][3][3] b2[32] W3[128][800] Wy[128][2]
  * b3[128] W4[64][128] b4[64] W5[4][64] b5[4]; W3's 800 inputs are ordered
@@ -351,8 +353,10 @@ int seb_inpaint_nearest(seb_ctx* ctx, const float* height, int64_t ld, int32_t r
  * distance in metres from its cell centre to the edge of the nearest obstacle
  * region within its own yaw plane, negative for states inside an obstacle.
  * Obstacle states are those with SEB_ST_CURV or SEB_ST_TILT set (Algorithm 1's
- * explicit obstacles), plus, when unknown_is_obstacle != 0, UNKNOWN states
- * (SEB_ST_VALID clear).  With d the Euclidean distance between cell centres
+ * explicit obstacles), those with SEB_ST_SURROGATE set and SEB_ST_TRAV clear
+ * (the surrogate does not tell which early-out applies, so every state it
+ * answers as not traversable counts as an obstacle, the safe side), plus,
+ * when unknown_is_obstacle != 0, UNKNOWN states (SEB_ST_VALID clear).  With d the Euclidean distance between cell centres
  * (in cells) to the nearest obstacle state (for a free state) or nearest free
  * state (for an obstacle state), and C = cap_cells,
  *     sdf = +(min(d, C) - 0.5) res   (free),   -(min(d, C) - 0.5) res   (obstacle);

@@ -13,8 +13,11 @@ the yaw axis handled on SO(2).
 Readings (the paper leaves these open; the same readings are used by the
 library):
   - obstacle states: the explicit obstacles of Algorithm 1 (curvature or tilt
-    early-out, status bits 2 and 4), and, when `unknown_is_obstacle`, the
-    UNKNOWN states (status bit 1 clear);
+    early-out, status bits 2 and 4), states answered by the learned surrogate
+    (bit 32) without the traversable bit (16) -- the network does not say
+    which early-out applies, so its non-traversable answers all count, the
+    safe side -- and, when `unknown_is_obstacle`, the UNKNOWN states (status
+    bit 1 clear);
   - distance: Euclidean, within each yaw bin's (x, y) plane, between cell
     centres, in metres; for a free state the distance to the nearest obstacle
     state, for an obstacle state the distance to the nearest free state; the
@@ -37,12 +40,13 @@ import math
 
 import numpy as np
 
-VALID, CURV, TILT = 1, 2, 4
+VALID, CURV, TILT, TRAV, SURROGATE = 1, 2, 4, 16, 32
 
 
 def obstacle_mask(status: np.ndarray, unknown_is_obstacle: bool = True) -> np.ndarray:
     st = np.asarray(status).astype(np.int64)
     m = (st & (CURV | TILT)) != 0
+    m |= ((st & SURROGATE) != 0) & ((st & TRAV) == 0)
     if unknown_is_obstacle:
         m |= (st & VALID) == 0
     return m

@@ -106,8 +106,10 @@ __global__ __launch_bounds__(NT) void sdf_kernel(const SdfArgs a) {
         // obstacle test come afterwards, so each batch of loads is in flight
         // at once.
         auto load = [&](int y) -> int { return plane[wrap(y + a.ry, a.H) * a.W + cx]; };
-        auto obstacle = [&](int st) {           // 1: CURV or TILT, or UNKNOWN if counted
-            return ((st >> 1) | (st >> 2) | (unk & ~st)) & 1;
+        // 1: CURV or TILT, a surrogate answer that is not traversable, or
+        // UNKNOWN if counted
+        auto obstacle = [&](int st) {
+            return ((st >> 1) | (st >> 2) | ((st >> 5) & ~(st >> 4)) | (unk & ~st)) & 1;
         };
         // The halos only contribute the nearest obstacle / free row beyond the
         // strip: a min (below) and a max (above), HB rows at a time.

@@ -319,8 +319,10 @@ def synthetic_status(width: int, height: int, n_yaw: int, seed: int, *,
                      max_radius: int = 9) -> np.ndarray:
     """uint8 [K][H][W] status planes: elliptical obstacle blobs whose extent
     changes with the yaw bin (obstacles of a yawed footprint grow along the
-    body's long axis), elliptical unknown patches shared by every yaw bin, and
-    random near-degenerate / traversable / surrogate bits elsewhere."""
+    body's long axis), tagged curvature, tilt, both, or surrogate-answered
+    and not traversable; elliptical unknown patches shared by every yaw bin;
+    and random near-degenerate / traversable bits elsewhere, with the
+    surrogate bit only on traversable states there."""
     rng = _rng(seed)
     area = width * height
     n_obstacles = max(1, area // 700) if n_obstacles is None else n_obstacles
@@ -337,8 +339,9 @@ def synthetic_status(width: int, height: int, n_yaw: int, seed: int, *,
         if e is not None:
             unknown[e[0]] |= e[1]
     ox, oy, oa, ob, oang = blobs(n_obstacles)
-    kind = rng.integers(0, 3, n_obstacles)              # curvature, tilt or both
+    kind = rng.integers(0, 4, n_obstacles)      # curvature, tilt, both, surrogate
     extra = rng.integers(0, 64, (n_yaw, height, width)).astype(np.uint8) & (8 | 16 | 32)
+    extra |= (extra & 32) >> 1                  # a free surrogate answer is traversable
     out = np.empty((n_yaw, height, width), dtype=np.uint8)
     for k in range(n_yaw):
         th = 2.0 * math.pi * k / n_yaw
@@ -347,7 +350,7 @@ def synthetic_status(width: int, height: int, n_yaw: int, seed: int, *,
             grow = 1.0 + 0.5 * abs(math.cos(th - oang[i]))
             e = _ellipse(bits.shape, ox[i], oy[i], oa[i] * grow, ob[i], th)
             if e is not None:
-                bits[e[0]] |= np.where(e[1], (2, 4, 6)[kind[i]], 0).astype(np.uint8)
+                bits[e[0]] |= np.where(e[1], (2, 4, 6, 32)[kind[i]], 0).astype(np.uint8)
         plane = np.where(bits != 0, 1 | bits, 1 | extra[k]).astype(np.uint8)
         plane[bits != 0] |= extra[k][bits != 0] & 8
         plane[unknown] = extra[k][unknown] & 8

@@ -25,6 +25,8 @@ def errors(out, o, own_known):
         d = np.abs(out[f][m].astype(np.float64) - getattr(o, f)[m])
         res[f] = (float(d.mean()), float(d.max()))
     res["mask_agree"] = float(np.mean(((st[m] & 16) > 0) == ((o.status[m] & 16) > 0)))
+    # unsafe direction: answered traversable where Alg. 1 sets an obstacle bit
+    res["unsafe"] = int(np.count_nonzero(m & ((st & 16) > 0) & ((o.status & 6) > 0)))
     return res
 
 
@@ -68,4 +70,6 @@ def test_trained_surrogate_beats_baselines(orc):
         assert e["roll"][0] < 0.5 * mb["roll"] and e["pitch"][0] < 0.5 * mb["pitch"]
         assert e["risk"][0] < 0.8 * mb["risk"]
         assert e["mask_agree"] > 0.95
+        # measured 0.3-0.7% of answered states on these maps
+        assert e["unsafe"] <= 0.01 * e["n"]
         assert e["fallback"] < 0.4

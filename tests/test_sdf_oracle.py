@@ -50,6 +50,21 @@ def test_empty_and_full_planes_and_unknown_states():
     assert a[0, 2, 2] < 0 and b[0, 2, 2] > 0 and a[0, 0, 4] < 0 and b[0, 0, 4] < 0
 
 
+def test_surrogate_answers_count_as_obstacles_unless_traversable():
+    """Surrogate states (bit 32) carry no curvature or tilt bit; those not
+    traversable are obstacles, the traversable ones free.  Near-degenerate and
+    traversable bits alone never make an obstacle."""
+    st = np.full((1, 3, 4), 1 | 16, np.uint8)
+    st[0, 0, 0] = 1 | 32                 # surrogate, not traversable -> obstacle
+    st[0, 1, 1] = 1 | 16 | 32            # surrogate, traversable -> free
+    st[0, 2, 2] = 1 | 8                  # plain, near-degenerate, risk > r_max -> free
+    st[0, 2, 3] = 1 | 8 | 32             # surrogate (bit 8 ignored), not traversable
+    m = S.obstacle_mask(st, unknown_is_obstacle=False)
+    want = np.zeros((1, 3, 4), bool)
+    want[0, 0, 0] = want[0, 2, 3] = True
+    assert np.array_equal(m, want)
+
+
 def grid_and_res():
     rng = np.random.default_rng(9)
     return rng.normal(size=(6, 9, 11)), 0.1
