@@ -446,14 +446,17 @@ __device__ void accumulate64(const AssessArgs& a, const Src& src, cptr<int32_t> 
     }
 }
 
+// Outputs are written once and not read again by the kernel: non-temporal
+// stores keep them from evicting the footprint table (read by every wave
+// through the scalar cache) and the height map from L2.
 __device__ __forceinline__ void store(const AssessArgs& a, int k, int64_t cell, const Result& r,
                                       bool negate) {
     const int64_t o = (int64_t)k * a.H * a.W + cell;
-    a.z[o] = r.z;
-    a.roll[o] = negate ? -r.roll : r.roll;
-    a.pitch[o] = negate ? -r.pitch : r.pitch;
-    a.risk[o] = r.risk;
-    a.status[o] = r.st;
+    __builtin_nontemporal_store(r.z, a.z + o);
+    __builtin_nontemporal_store(negate ? -r.roll : r.roll, a.roll + o);
+    __builtin_nontemporal_store(negate ? -r.pitch : r.pitch, a.pitch + o);
+    __builtin_nontemporal_store(r.risk, a.risk + o);
+    __builtin_nontemporal_store(r.st, a.status + o);
 }
 
 // Result of a state from its FP32 moments; with precision 1, near-degenerate

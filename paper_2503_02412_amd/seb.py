@@ -222,6 +222,27 @@ class Context:
                "seb_assess_se2")
         return out
 
+    def launcher(self, height, out, rect=None, stream=None):
+        """A zero-argument callable that issues seb_assess_se2 with the
+        arguments marshalled once, here (for launch loops that repeat the same
+        call: the host cost per launch is then the C call alone).  Raises
+        SebError on a failed launch."""
+        _check_map(height, self.params)
+        x0, y0, nx, ny = rect if rect is not None else (0, 0, self.params.width,
+                                                         self.params.height)
+        o = _out_struct(out, self.params)
+        fn = lib().seb_assess_se2
+        args = (self._h, C.c_void_p(height.data_ptr()), height.stride(0), x0, y0, nx, ny,
+                C.byref(o), _stream_handle(stream))
+        keep = (height, out, o)
+
+        def launch():
+            rc = fn(*args)
+            if rc != SEB_OK:
+                _check(rc, "seb_assess_se2")
+            return keep
+        return launch
+
     def _field(self, t, name, dtype):
         import torch
         p = self.params
