@@ -319,6 +319,20 @@ void seb_fuser_destroy(seb_fuser* f);
 int seb_fuse_scan(seb_fuser* f, float* height, float* variance, int64_t ld, int64_t origin_x,
                   int64_t origin_y, const seb_scan* scan, int32_t* n_fused_dev, void* stream);
 
+/* seb_fuse_scan for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results, with the workspace in a file-scope device array of
+ * about 10 MiB that every GPU the library runs on holds until the process
+ * ends, instead of a seb_fuser.  Limits: W * H <= 2^18 cells and n_points <=
+ * 2^18 (larger calls fail with SEB_ERR_INVALID, nothing launched).  The first
+ * call on a device looks up the array's address there (SEB_ERR_HIP if that
+ * fails).  All calls on one GPU share the array, so calls that overlap on one
+ * GPU (several streams or threads) race; serialise them.  Arguments, ring
+ * storage, n_fused_dev and errors as for seb_fuse_scan; allocates nothing. */
+int seb_fuse_scan_static(seb_ctx* ctx, float* height, float* variance, int64_t ld,
+                         int64_t origin_x, int64_t origin_y, const seb_scan* scan,
+                         int32_t* n_fused_dev, void* stream);
+
 /* Ray-casting reset (Sec. V-A), run before the scan is fused: every finite
  * point's segment from the sensor (R_B p_BS + p_B) to the point, in the map
  * frame, resets to unknown (NaN) each known cell it crosses -- a cell whose

@@ -29,6 +29,7 @@
 // an LDS tile with a halo of that radius and a list of offsets sorted by
 // distance.
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <cstdint>
 
@@ -502,6 +503,62 @@ hipError_t launch_fuse_scan(const ScanArgs& s, const FuseArgs& f, const FuseWork
     hipLaunchKernelGGL(fuse_small_kernel, grid(n_cells), dim3(256), 0, stream, f, w);
     hipLaunchKernelGGL(fuse_large_kernel, dim3(8192), dim3(256), 0, stream, f, w);
     return hipGetLastError();
+}
+
+// Workspace of seb_fuse_scan_static: one file-scope array per device (each
+// GPU the library runs on holds its own copy until the process ends), carved
+// into the FuseWork buffers for up to STATIC_MAX_POINTS points and
+// STATIC_MAX_CELLS map cells.  Host code never passes the array's name to a
+// kernel (there it is a host-side stand-in); it uses the device address that
+// static_fuse_work looks up once per device.
+namespace {
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t STATIC_PARTIALS = (STATIC_MAX_CELLS + SCAN_CHUNK - 1) / SCAN_CHUNK;
+constexpr size_t STATIC_BYTES =
+    2 * align256((size_t)STATIC_MAX_POINTS * 4) + 2 * align256((size_t)STATIC_MAX_POINTS * 8) +
+    4 * align256((size_t)STATIC_MAX_CELLS * 4) + align256(STATIC_PARTIALS * 4) + 2 * 256;
+static_assert(STATIC_BYTES <= (size_t)16 << 20, "static fusion workspace above 16 MiB");
+__device__ __align__(256) unsigned char scratch[STATIC_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};     // device address of scratch, per device ordinal
+}  // namespace
+
+hipError_t static_fuse_work(FuseWork* w) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    unsigned char* base;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void* ptr = nullptr;
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            if (!ptr) return hipErrorInvalidSymbol;
+            g_scratch_ptr[dev] = ptr;
+        }
+        base = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+    }
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* p = base + o;
+        o += align256(bytes);
+        return p;
+    };
+    w->cell = (int32_t*)take((size_t)STATIC_MAX_POINTS * 4);
+    w->bucket = (int32_t*)take((size_t)STATIC_MAX_POINTS * 4);
+    w->z = (double*)take((size_t)STATIC_MAX_POINTS * 8);
+    w->var = (double*)take((size_t)STATIC_MAX_POINTS * 8);
+    w->count = (int32_t*)take((size_t)STATIC_MAX_CELLS * 4);
+    w->fill = (int32_t*)take((size_t)STATIC_MAX_CELLS * 4);
+    w->offs = (int32_t*)take((size_t)STATIC_MAX_CELLS * 4);
+    w->large = (int32_t*)take((size_t)STATIC_MAX_CELLS * 4);
+    w->partial = (int32_t*)take(STATIC_PARTIALS * 4);
+    w->n_large = (int32_t*)take(4);
+    w->n_fused = (int32_t*)take(4);
+    return o <= STATIC_BYTES ? hipSuccess : hipErrorInvalidValue;
 }
 
 hipError_t launch_raycast(const RayArgs& r, hipStream_t stream) {

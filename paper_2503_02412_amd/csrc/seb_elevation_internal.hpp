@@ -47,6 +47,13 @@ struct FuseWork {
 
 int64_t partial_blocks(int64_t n_cells);
 
+// Limits of seb_fuse_scan_static, whose workspace is a file-scope device array.
+constexpr int64_t STATIC_MAX_POINTS = int64_t(1) << 18;
+constexpr int64_t STATIC_MAX_CELLS = int64_t(1) << 18;
+// The FuseWork buffers inside that array on the current device (its address
+// is looked up once per device, on the first call there).  Allocates nothing.
+hipError_t static_fuse_work(FuseWork* w);
+
 struct FuseArgs {
     float* height;           // [H][ld] ring storage
     float* variance;

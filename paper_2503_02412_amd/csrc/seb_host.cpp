@@ -863,11 +863,14 @@ void seb_fuser_destroy(seb_fuser* f) {
     delete f;
 }
 
-int seb_fuse_scan(seb_fuser* f, float* height, float* variance, int64_t ld, int64_t origin_x,
-                  int64_t origin_y, const seb_scan* sc, int32_t* n_fused_dev, void* stream) {
-    if (!f || !height || !variance || !sc)
-        return fail(SEB_ERR_INVALID, "fuser, height, variance and scan must be non-NULL");
-    const seb_config& g = f->ctx->cfg;
+namespace {
+
+// Checks of a fusion call and its kernel arguments (shared by seb_fuse_scan
+// and seb_fuse_scan_static); returns SEB_OK or the error, nothing launched.
+int fuse_args(const seb_ctx* c, float* height, float* variance, int64_t ld, int64_t origin_x,
+              int64_t origin_y, const seb_scan* sc, int64_t max_points, elev::ScanArgs* out_s,
+              elev::FuseArgs* out_a) {
+    const seb_config& g = c->cfg;
     if (ld < g.width) return fail(SEB_ERR_INVALID, "ld must be >= width");
     {
         const char* h0 = (const char*)height;
@@ -876,7 +879,7 @@ int seb_fuse_scan(seb_fuser* f, float* height, float* variance, int64_t ld, int6
         const char* v1 = (const char*)(variance + (int64_t)(g.height - 1) * ld + g.width);
         if (h0 < v1 && v0 < h1) return fail(SEB_ERR_INVALID, "height and variance overlap");
     }
-    if (sc->n_points < 0 || sc->n_points > f->max_points)
+    if (sc->n_points < 0 || sc->n_points > max_points)
         return fail(SEB_ERR_INVALID, "n_points outside [0, max_points]");
     if (sc->n_points > 0 && !sc->points) return fail(SEB_ERR_INVALID, "points is NULL");
     const double* all[] = {sc->R_B, sc->p_B, sc->R_BS, sc->p_BS, sc->Sigma_R, sc->Sigma_B};
@@ -891,7 +894,7 @@ int seb_fuse_scan(seb_fuser* f, float* height, float* variance, int64_t ld, int6
         return fail(SEB_ERR_INVALID, "need z_min <= z_max and mahalanobis > 0");
     if (std::fabs((double)origin_x) > 1e15 || std::fabs((double)origin_y) > 1e15)
         return fail(SEB_ERR_INVALID, "origin out of range");
-    elev::ScanArgs s;
+    elev::ScanArgs& s = *out_s;
     s.pts = sc->points;
     s.n = sc->n_points;
     for (int i = 0; i < 9; ++i) {
@@ -916,7 +919,7 @@ int seb_fuse_scan(seb_fuser* f, float* height, float* variance, int64_t ld, int6
     s.H = g.height;
     s.ox = origin_x;
     s.oy = origin_y;
-    elev::FuseArgs a;
+    elev::FuseArgs& a = *out_a;
     a.height = height;
     a.variance = variance;
     a.ld = ld;
@@ -925,8 +928,45 @@ int seb_fuse_scan(seb_fuser* f, float* height, float* variance, int64_t ld, int6
     a.rx = (int32_t)pos_mod(origin_x, g.width);
     a.ry = (int32_t)pos_mod(origin_y, g.height);
     a.tau2 = sc->mahalanobis * sc->mahalanobis;
+    return SEB_OK;
+}
+
+}  // namespace
+
+int seb_fuse_scan(seb_fuser* f, float* height, float* variance, int64_t ld, int64_t origin_x,
+                  int64_t origin_y, const seb_scan* sc, int32_t* n_fused_dev, void* stream) {
+    if (!f || !height || !variance || !sc)
+        return fail(SEB_ERR_INVALID, "fuser, height, variance and scan must be non-NULL");
+    elev::ScanArgs s;
+    elev::FuseArgs a;
+    const int rc = fuse_args(f->ctx, height, variance, ld, origin_x, origin_y, sc, f->max_points,
+                             &s, &a);
+    if (rc != SEB_OK) return rc;
     a.n_fused = n_fused_dev ? n_fused_dev : f->w.n_fused;
     hipError_t e = elev::launch_fuse_scan(s, a, f->w, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fusion launch");
+    return SEB_OK;
+}
+
+int seb_fuse_scan_static(seb_ctx* c, float* height, float* variance, int64_t ld,
+                         int64_t origin_x, int64_t origin_y, const seb_scan* sc,
+                         int32_t* n_fused_dev, void* stream) {
+    if (!c || !height || !variance || !sc)
+        return fail(SEB_ERR_INVALID, "ctx, height, variance and scan must be non-NULL");
+    if ((int64_t)c->cfg.width * c->cfg.height > elev::STATIC_MAX_CELLS)
+        return fail(SEB_ERR_INVALID, "map larger than the static fusion workspace (2^18 cells)");
+    if (sc->n_points > elev::STATIC_MAX_POINTS)
+        return fail(SEB_ERR_INVALID, "more points than the static fusion workspace (2^18)");
+    elev::ScanArgs s;
+    elev::FuseArgs a;
+    const int rc = fuse_args(c, height, variance, ld, origin_x, origin_y, sc,
+                             elev::STATIC_MAX_POINTS, &s, &a);
+    if (rc != SEB_OK) return rc;
+    elev::FuseWork w;
+    hipError_t e = elev::static_fuse_work(&w);
+    if (e != hipSuccess) return hip_fail(e, "static fusion workspace lookup");
+    a.n_fused = n_fused_dev ? n_fused_dev : w.n_fused;
+    e = elev::launch_fuse_scan(s, a, w, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fusion launch");
     return SEB_OK;
 }

@@ -91,6 +91,9 @@ _SIGS = {
     "seb_fuser_destroy": (None, [C.c_void_p]),
     "seb_fuse_scan": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
                                 C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "seb_fuse_scan_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                       C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                                       C.c_void_p]),
     "seb_raycast_reset": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
                                     C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
     "seb_inpaint_nearest": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
@@ -360,6 +363,24 @@ class Fuser:
                                    C.c_void_p(variance.data_ptr()), height.stride(0),
                                    int(origin[0]), int(origin[1]), C.byref(sc), C.c_void_p(ptr),
                                    _stream_handle(stream)), "seb_fuse_scan")
+
+
+def fuse_scan_static(ctx: "Context", height, variance, origin, points, frames: dict,
+                     n_fused=None, stream=None):
+    """seb_fuse_scan_static: Fuser.fuse without a fuser (the library's static
+    workspace; maps of at most 2^18 cells, scans of at most 2^18 points)."""
+    p = ctx.params
+    _check_map(height, p)
+    _check_map(variance, p)
+    if height.stride(0) != variance.stride(0):
+        raise ValueError("height and variance must share a row stride")
+    sc = Fuser.scan_struct(points, frames)
+    ptr = None if n_fused is None else n_fused.data_ptr()
+    _check(lib().seb_fuse_scan_static(ctx._h, C.c_void_p(height.data_ptr()),
+                                      C.c_void_p(variance.data_ptr()), height.stride(0),
+                                      int(origin[0]), int(origin[1]), C.byref(sc),
+                                      C.c_void_p(ptr), _stream_handle(stream)),
+           "seb_fuse_scan_static")
 
 
 class Window:
