@@ -754,10 +754,10 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
     const int64_t max_items = flagged_work_items((int)W, (int)H, U, c->geo.R, c->fpitch);
     const int64_t n_blocks = flagged_blocks((int)W, (int)H, U, c->geo.R, c->fpitch);
     const bool ok =
-        al((void**)&w.o1map, (size_t)(H + 20) * (W + 20) * seb::net::C1 * 2) &&
+        al((void**)&w.yaw_sc, (size_t)U * sizeof(float2)) &&
         al((void**)&w.o2map, (size_t)(H + 16) * (W + 16) * seb::net::C2 * 2) &&
         al((void**)&w.T, (size_t)cells * seb::net::H1 * 4) &&
-        al((void**)&w.Y, (size_t)U * seb::net::H1 * 4) && al((void**)&w.known, (size_t)cells * 4) && al((void**)&w.need, (size_t)U * cells) &&
+        al((void**)&w.known, (size_t)cells * 4) && al((void**)&w.need, (size_t)U * cells) &&
         al((void**)&w.work_cells, (size_t)max_items * 64 * 2) &&
         al((void**)&w.block_count, (size_t)n_blocks * sizeof(int32_t)) &&
         al((void**)&w.item_box, (size_t)max_items * sizeof(int32_t));
@@ -765,11 +765,26 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
         seb_surrogate_destroy(s);
         return fail(SEB_ERR_ALLOC, "device allocation failed");
     }
+    {
+        // (sin, cos) of each evaluated yaw unit's angle 2 pi u / K, in FP64
+        std::vector<float2> sc(U);
+        for (int u = 0; u < U; ++u) {
+            const double th = 2.0 * M_PI * (double)u / (double)c->cfg.n_yaw;
+            sc[u] = make_float2((float)std::sin(th), (float)std::cos(th));
+        }
+        if (hipMemcpy((void*)w.yaw_sc, sc.data(), sc.size() * sizeof(float2),
+                      hipMemcpyHostToDevice) != hipSuccess) {
+            seb_surrogate_destroy(s);
+            return fail(SEB_ERR_HIP, "yaw table upload failed");
+        }
+    }
     w.W = (int)W;
     w.H = (int)H;
     w.inv_res = (float)(1.0 / c->cfg.resolution);
     w.K = c->cfg.n_yaw;
     w.U = U;
+    w.upw = U;
+    if (const char* e = std::getenv("SEB_HEAD_UPW")) w.upw = std::max(1, std::min(U, std::atoi(e)));
     w.mirror = c->geo.mirror;
     w.pitch = c->fpitch;
     w.risk_max = (float)c->cfg.risk_max;

@@ -354,10 +354,13 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* th, PackedWeight
         const float v = th[OFF_W4 + i];
         w.w4[i] = to_bf16(v);
         w.w4t[c * H2 + o] = to_bf16(v);
+        w.w4h[i] = (f16)(float)to_bf16(v);
     }
     if (i < 16 * H2) {                                // w5 [16][64], w5t [64][32]
         const int o = i / H2, c = i % H2;
-        w.w5[i] = to_bf16(o < NOUT ? th[OFF_W5 + o * H2 + c] : 0.f);
+        const bf16 b = to_bf16(o < NOUT ? th[OFF_W5 + o * H2 + c] : 0.f);
+        w.w5[i] = b;
+        w.w5h[i] = (f16)(float)b;
     }
     if (i < H2 * 32) {
         const int c = i / 32, o = i % 32;
@@ -616,7 +619,8 @@ int seb_net_create(uint64_t seed, int32_t max_batch, seb_net** out) {
               dalloc(n, &n->pw.w3, N::H1 * N::F) && dalloc(n, &n->pw.w4, N::H2 * N::H1) &&
               dalloc(n, &n->pw.w5, 16 * N::H2) && dalloc(n, &n->pw.w2t, N::K2P * N::C2) &&
               dalloc(n, &n->pw.w3t, N::F * N::H1) && dalloc(n, &n->pw.w4t, N::H1 * N::H2) &&
-              dalloc(n, &n->pw.w5t, N::H2 * 32) && dalloc(n, &n->A1, r1 * N::K1P) &&
+              dalloc(n, &n->pw.w5t, N::H2 * 32) && dalloc(n, &n->pw.w4h, N::H2 * N::H1) &&
+              dalloc(n, &n->pw.w5h, 16 * N::H2) && dalloc(n, &n->A1, r1 * N::K1P) &&
               dalloc(n, &n->A1t, r1 * N::K1P) && dalloc(n, &n->o1, r1 * N::C1) &&
               dalloc(n, &n->da1, r1 * N::C1) && dalloc(n, &n->da1t, r1 * N::C1) &&
               dalloc(n, &n->A2, r2 * N::K2P) && dalloc(n, &n->A2t, r2 * N::K2P) &&

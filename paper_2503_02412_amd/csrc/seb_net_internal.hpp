@@ -9,6 +9,7 @@ namespace seb {
 namespace net {
 
 typedef __bf16 bf16;
+typedef _Float16 f16;
 
 // Network shape: 24 x 24 patch, three input channels (x-slope, y-slope,
 // known), conv 3->16 (4x4, stride 2) -> 11x11, conv 16->32 (3x3, stride 2) ->
@@ -50,6 +51,8 @@ struct PackedWeights {
     bf16* w3t;   // [800][128]
     bf16* w4t;   // [128][64]
     bf16* w5t;   // [64][32]        columns 4..31 zero
+    f16* w4h;    // [64][128]       w4 in fp16 (the bf16 values, exactly): inference head
+    f16* w5h;    // [16][64]        w5 in fp16, rows 4..15 zero
 };
 
 struct GemmArgs {

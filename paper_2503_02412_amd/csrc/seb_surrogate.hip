@@ -81,120 +81,182 @@ __device__ __forceinline__ bool ref_height(const SurArgs& s, int cy, int cx, flo
     return n > 0.f;
 }
 
-// conv1 at every position (y1, x1) in [-12, H+8) x [-12, W+8): ReLU(b1 + W1 . input
-// window [y1, y1+4) x [x1, x1+4)); inputs and outputs rounded to bf16 as in training.
-__global__ __launch_bounds__(256) void conv1_map_kernel(const SurArgs s) {
-    __shared__ float4 w[net::K1][net::C1 / 4];      // [input][output], transposed
-    const int W1 = s.W + 20;
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool live = p < (int64_t)(s.H + 20) * W1;
-    const int64_t pc = live ? p : 0;
-    const int y1 = (int)(pc / W1) - 12, x1 = (int)(pc % W1) - 12;
-    // Every load of the thread is issued before the first wait: the 5 x 5
-    // heights the window's slopes use (clamped positions, masked afterwards:
-    // unknown and out-of-map cells read as 0 with weight 0), its three
-    // weights for the LDS table and the biases.
-    float hv[25], kv[25];
+// Trunk of the map form, one launch with two kinds of workgroups.
+//
+// Convolution tiles (the first tiles_y2 * tiles_x2 workgroups): conv1 and
+// conv2 for a 16 x 16 tile of conv2 positions (y2, x2) in [-12, H+4) x
+// [-12, W+4).  conv2 at (y2, x2) reads conv1 at (y2 + 2i, x2 + 2j), i, j < 3
+// (dilation 2), so the tile needs conv1 on 20 x 20 positions, whose 4 x 4
+// windows and slopes cover 25 x 25 cells.  Both layers run on MFMA with the
+// weights as A and the positions as B, so a lane receives four consecutive
+// output channels of one position:
+//   conv1: D (16 ch x 16 positions) = W1 (16 x 64) . im2col^T, K = (channel,
+//          row, column) of the 4 x 4 window (48 used);
+//   conv2: D (32 ch x 16 positions) = W2 (32 x 160) . im2col^T, K = (tap,
+//          channel) (144 used).
+// Inputs (x-slope, y-slope, known) and conv1's outputs are bf16 as in
+// training; conv1's output tile stays in LDS, conv2's goes to o2map.
+//
+// Known-fraction tiles (the remaining workgroups): the fraction of known
+// cells in each cell's 24 x 24 window [c - 12, c + 12), for 16 x 16 cells,
+// from an LDS tile of known flags (row sums, then column sums).  The first of
+// them also clears the fallback counter.
+constexpr int TT = 16;                       // conv2 positions per tile side
+constexpr int T1 = TT + 4;                   // conv1 positions per tile side
+constexpr int TC = T1 + 4;                   // input cells per side (window 4, slope +1 -> 25 heights)
+
+__global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
+    __shared__ float hs[TC + 1][TC + 1];     // heights (0 where unknown)
+    __shared__ float ks[TC + 1][TC + 1];     // known flags
+    __shared__ float cin[3][TC][TC + 1];     // bf16-rounded inputs: x-slope, y-slope, known
+    __shared__ bf16x8 o1s[T1 * T1][2];       // conv1 outputs [position][channels 0-7, 8-15]
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int tx2 = (s.W + 16 + TT - 1) / TT, ty2 = (s.H + 16 + TT - 1) / TT;
+    const int nconv = tx2 * ty2;
+    if ((int)blockIdx.x >= nconv) {
+        // ---- known fraction of 16 x 16 cells ----
+        constexpr int T = 16, SPAN = T + net::PATCH - 1;     // 39 rows / columns of flags
+        float (*kf)[SPAN + 1] = reinterpret_cast<float (*)[SPAN + 1]>(&cin[0][0][0]);
+        float (*rs)[T + 1] = reinterpret_cast<float (*)[T + 1]>(&o1s[0][0]);
+        static_assert(sizeof(cin) >= sizeof(float) * SPAN * (SPAN + 1), "flag tile fits");
+        static_assert(sizeof(o1s) >= sizeof(float) * SPAN * (T + 1), "row sums fit");
+        const int b = blockIdx.x - nconv;
+        const int kx = (s.W + T - 1) / T;
+        const int x0 = (b % kx) * T, y0 = (b / kx) * T;
+        if (b == 0 && tid == 0 && s.n_fallback) *s.n_fallback = 0;
+        // six loads per thread in flight, from clamped positions, masked afterwards
+        constexpr int NB = (SPAN * SPAN + 255) / 256;
+        float hv[NB];
 #pragma unroll
-    for (int k = 0; k < 25; ++k) {
-        const int y = y1 + k / 5, x = x1 + k % 5;
-        hv[k] = s.height[(int64_t)min(max(y, 0), s.H - 1) * s.ld + min(max(x, 0), s.W - 1)];
-        kv[k] = (y >= 0 && x >= 0 && y < s.H && x < s.W) ? 1.f : 0.f;
+        for (int j = 0; j < NB; ++j) {
+            const int i = min(tid + 256 * j, SPAN * SPAN - 1);
+            const int y = y0 - net::HALF + i / SPAN, x = x0 - net::HALF + i % SPAN;
+            hv[j] = s.height[(int64_t)min(max(y, 0), s.H - 1) * s.ld + min(max(x, 0), s.W - 1)];
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i = tid + 256 * j;
+            if (i >= SPAN * SPAN) continue;
+            const int rr = i / SPAN, cc = i % SPAN;
+            const int y = y0 - net::HALF + rr, x = x0 - net::HALF + cc;
+            const bool in = y >= 0 && x >= 0 && y < s.H && x < s.W;
+            kf[rr][cc] = (in && fabsf(hv[j]) < HEIGHT_LIMIT) ? 1.f : 0.f;
+        }
+        __syncthreads();
+        for (int i = tid; i < SPAN * T; i += 256) {
+            const int rr = i / T, cc = i % T;
+            float n = 0.f;
+            for (int d = 0; d < net::PATCH; ++d) n += kf[rr][cc + d];
+            rs[rr][cc] = n;
+        }
+        __syncthreads();
+        const int cc = tid % T, rr = tid / T;
+        const int x = x0 + cc, y = y0 + rr;
+        if (x < s.W && y < s.H) {
+            float n = 0.f;
+            for (int d = 0; d < net::PATCH; ++d) n += rs[rr + d][cc];
+            s.known[(int64_t)y * s.W + x] = n * (1.f / (net::PATCH * net::PATCH));
+        }
+        return;
     }
-    constexpr int NW1 = net::C1 * net::K1 / 256;
-    static_assert(net::C1 * net::K1 % 256 == 0, "conv1 weight staging assumes whole passes");
-    bf16 wv[NW1];
+    // ---- conv1 + conv2 of a 16 x 16 tile of conv2 positions ----
+    const int Y2 = (blockIdx.x / tx2) * TT - 12, X2 = (blockIdx.x % tx2) * TT - 12;
+    // Weights and biases first, with the cell loads, before any wait.
+    bf16x8 w1f[2];                           // W1[4g' .. ][..]: A fragments, rows r, K 32ks + 8g
 #pragma unroll
-    for (int j = 0; j < NW1; ++j) {
-        const int i = threadIdx.x + 256 * j;
-        wv[j] = s.pw.w1[(i / net::K1) * net::K1P + i % net::K1];
+    for (int k2 = 0; k2 < 2; ++k2) w1f[k2] = *(const bf16x8*)(s.pw.w1 + r * net::K1P + 32 * k2 + 8 * g);
+    const float4 b1 = *(const float4*)(s.theta + net::OFF_B1 + 4 * g);
+    float4 b2[2];
+    bf16x8 w2f[2][5];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        b2[t] = *(const float4*)(s.theta + net::OFF_B2 + 16 * t + 4 * g);
+#pragma unroll
+        for (int k2 = 0; k2 < 5; ++k2)
+            w2f[t][k2] = *(const bf16x8*)(s.pw.w2 + (16 * t + r) * net::K2P + 32 * k2 + 8 * g);
     }
-    float b1[net::C1];
+    static_assert(net::OFF_B1 % 4 == 0 && net::OFF_B2 % 4 == 0, "biases read as float4");
+    constexpr int NH = ((TC + 1) * (TC + 1) + 255) / 256;      // 3 cells per thread
+    float hv[NH];
 #pragma unroll
-    for (int o = 0; o < net::C1; ++o) b1[o] = s.theta[net::OFF_B1 + o];
+    for (int j = 0; j < NH; ++j) {
+        const int i = min(tid + 256 * j, (TC + 1) * (TC + 1) - 1);
+        const int y = Y2 + i / (TC + 1), x = X2 + i % (TC + 1);
+        hv[j] = s.height[(int64_t)min(max(y, 0), s.H - 1) * s.ld + min(max(x, 0), s.W - 1)];
+    }
 #pragma unroll
-    for (int j = 0; j < NW1; ++j) {
-        const int i = threadIdx.x + 256 * j;
-        reinterpret_cast<float*>(&w[i % net::K1][0])[i / net::K1] = from_bf16(wv[j]);
+    for (int j = 0; j < NH; ++j) {
+        const int i = tid + 256 * j;
+        if (i >= (TC + 1) * (TC + 1)) continue;
+        const int rr = i / (TC + 1), cc = i % (TC + 1);
+        const int y = Y2 + rr, x = X2 + cc;
+        const bool ok = y >= 0 && x >= 0 && y < s.H && x < s.W && fabsf(hv[j]) < HEIGHT_LIMIT;
+        hs[rr][cc] = ok ? hv[j] : 0.f;
+        ks[rr][cc] = ok ? 1.f : 0.f;
     }
     __syncthreads();
-    if (!live) return;
-#pragma unroll
-    for (int k = 0; k < 25; ++k) {
-        const bool ok = kv[k] > 0.f && fabsf(hv[k]) < HEIGHT_LIMIT;
-        kv[k] = ok ? 1.f : 0.f;
-        hv[k] = ok ? hv[k] : 0.f;
+    // Input channels of the 24 x 24 cells, rounded to bf16 as in training.
+    for (int i = tid; i < TC * TC; i += 256) {
+        const int rr = i / TC, cc = i % TC;
+        const float v0 = ks[rr][cc], vx = ks[rr][cc + 1], vy = ks[rr + 1][cc];
+        const float h0 = hs[rr][cc];
+        cin[0][rr][cc] = (float)(bf16)(v0 * vx * (hs[rr][cc + 1] - h0) * s.inv_res);
+        cin[1][rr][cc] = (float)(bf16)(v0 * vy * (hs[rr + 1][cc] - h0) * s.inv_res);
+        cin[2][rr][cc] = v0;
     }
-    float in[net::K1];
+    __syncthreads();
+    // conv1: 25 groups of 16 positions, spread over the waves.  Lane (r, g)
+    // supplies position 16 m + r at K = 32 ks + 8 g .. + 7: channel 2 ks + g / 2,
+    // window rows 2 (g % 2) and 2 (g % 2) + 1, columns 0..3 (channel 3: zero).
+    for (int m = wave; m < (T1 * T1) / 16; m += 4) {
+        const int pp = 16 * m + r, py = pp / T1, px = pp % T1;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int k2 = 0; k2 < 2; ++k2) {
+            const int ch = 2 * k2 + (g >> 1), i0 = 2 * (g & 1);
+            bf16x8 bop = {};
+            if (ch < 3) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int k = i * 5 + j;
-            const float v0 = kv[k], vx = kv[k + 1], vy = kv[k + 5];
-            const float h0 = hv[k], hx = hv[k + 1], hy = hv[k + 5];
-            in[0 * 16 + i * 4 + j] = from_bf16(to_bf16(v0 * vx * (hx - h0) * s.inv_res));
-            in[1 * 16 + i * 4 + j] = from_bf16(to_bf16(v0 * vy * (hy - h0) * s.inv_res));
-            in[2 * 16 + i * 4 + j] = v0;
+                for (int e = 0; e < 8; ++e) bop[e] = (bf16)cin[ch][py + i0 + e / 4][px + e % 4];
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[k2], bop, acc, 0, 0, 0);
         }
-    // The 16 outputs accumulate side by side (16 independent chains), each
-    // input's 16 weights arriving in four vector LDS reads; every output still
-    // sums its 48 products in input order.
-    float acc[net::C1];
-#pragma unroll
-    for (int o = 0; o < net::C1; ++o) acc[o] = 0.f;
-#pragma unroll
-    for (int c = 0; c < net::K1; ++c) {
-#pragma unroll
-        for (int q = 0; q < net::C1 / 4; ++q) {
-            const float4 wq = w[c][q];
-            acc[4 * q + 0] = fmaf(wq.x, in[c], acc[4 * q + 0]);
-            acc[4 * q + 1] = fmaf(wq.y, in[c], acc[4 * q + 1]);
-            acc[4 * q + 2] = fmaf(wq.z, in[c], acc[4 * q + 2]);
-            acc[4 * q + 3] = fmaf(wq.w, in[c], acc[4 * q + 3]);
-        }
+        // rows 4g .. 4g+3 = channels of position pp
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        const bf16x4 o = {(bf16)fmaxf(acc[0] + b1.x, 0.f), (bf16)fmaxf(acc[1] + b1.y, 0.f),
+                          (bf16)fmaxf(acc[2] + b1.z, 0.f), (bf16)fmaxf(acc[3] + b1.w, 0.f)};
+        *reinterpret_cast<bf16x4*>(reinterpret_cast<bf16*>(&o1s[pp][0]) + 4 * g) = o;
     }
-    bf16* out = s.o1map + p * net::C1;
+    __syncthreads();
+    // conv2: 16 groups of 16 positions (one tile row each), 4 per wave.  Lane
+    // (r, g) supplies position (row, r) at K = 32 ks + 8 g .. + 7: tap
+    // 2 ks + g / 2, channels 8 (g % 2) .. + 7.
+    const int W2m = s.W + 16, H2m = s.H + 16;
+    for (int q = wave; q < TT; q += 4) {
+        const int y2 = Y2 + q, x2 = X2 + r;
+        f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-    for (int o = 0; o < net::C1; ++o) out[o] = to_bf16(fmaxf(acc[o] + b1[o], 0.f));
-}
-
-// conv2 at every position (y2, x2) in [-12, H+4) x [-12, W+4), dilation 2 on
-// conv1's map: implicit GEMM, M = positions, N = 32, K = 9 taps x 16 channels.
-__global__ __launch_bounds__(256) void conv2_map_kernel(const SurArgs s) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int W1 = s.W + 20, W2 = s.W + 16;
-    const int64_t M = (int64_t)(s.H + 16) * W2;
-    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
-    if (row0 >= M) return;
-    const int r = lane & 15, kq = lane >> 4;
-    const int64_t pr = min(row0 + r, M - 1);
-    const int y2 = (int)(pr / W2) - 12, x2 = (int)(pr % W2) - 12;
-    // Biases first: a load issued after the stores below would wait for them.
-    const float bias[2] = {s.theta[net::OFF_B2 + r], s.theta[net::OFF_B2 + 16 + r]};
-    f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
-    const bf16x8 zero8 = {};
-    for (int ks = 0; ks < net::K2P / 32; ++ks) {
-        const int k = 32 * ks + 8 * kq;
-        const int tap = k / 16, coff = k % 16;
-        bf16x8 a = zero8;
-        if (tap < 9) {
-            const int y1 = y2 + 2 * (tap / 3), x1 = x2 + 2 * (tap % 3);
-            a = *(const bf16x8*)(s.o1map + ((int64_t)(y1 + 12) * W1 + (x1 + 12)) * net::C1 + coff);
+        for (int k2 = 0; k2 < 5; ++k2) {
+            const int tap = 2 * k2 + (g >> 1);
+            bf16x8 bop = {};
+            if (tap < 9) bop = o1s[(q + 2 * (tap / 3)) * T1 + r + 2 * (tap % 3)][g & 1];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2f[t][k2], bop, acc[t], 0, 0, 0);
         }
-        for (int t = 0; t < 2; ++t) {
-            const bf16x8 b = *(const bf16x8*)(s.pw.w2 + (16 * t + r) * net::K2P + k);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+        if (y2 + 12 < H2m && x2 + 12 < W2m) {
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            bf16* dst = s.o2map + ((int64_t)(y2 + 12) * W2m + (x2 + 12)) * net::C2;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const float4 bb = b2[t];
+                const bf16x4 o = {(bf16)fmaxf(acc[t][0] + bb.x, 0.f), (bf16)fmaxf(acc[t][1] + bb.y, 0.f),
+                                  (bf16)fmaxf(acc[t][2] + bb.z, 0.f), (bf16)fmaxf(acc[t][3] + bb.w, 0.f)};
+                *reinterpret_cast<bf16x4*>(dst + 16 * t + 4 * g) = o;
+            }
         }
     }
-    for (int t = 0; t < 2; ++t)
-        for (int e = 0; e < 4; ++e) {
-            const int64_t row = row0 + 4 * kq + e;
-            const int n = 16 * t + r;
-            if (row >= M) continue;
-            const float v = fmaxf(acc[t][e] + bias[t], 0.f);
-            s.o2map[row * net::C2 + n] = to_bf16(v);
-        }
 }
 
 // fc1 without the yaw term, per cell: T[cell][n] = b3[n] + W3[n] . (conv2 at
@@ -272,172 +334,171 @@ __global__ __launch_bounds__(256) void fc1_map_kernel(const SurArgs s) {
             }
 }
 
-// Per-map preparation in one launch.  Workgroup (bx, by) computes, for its
-// 16 x 16 cells, the known fraction of each cell's 24 x 24 window
-// [c - 12, c + 12) from an LDS tile of known flags (row sums, then column
-// sums).  Workgroup (0, 0) also writes fc1's yaw term for the first U yaw
-// bins, Y[u][n] = Wy[n] . (sin, cos)(2 pi u / K), and clears the fallback
-// counters.
-__global__ __launch_bounds__(256) void prep_kernel(const SurArgs s) {
-    constexpr int T = 16, SPAN = T + net::PATCH - 1;     // 39 rows / columns of flags
-    __shared__ float kf[SPAN][SPAN + 1];
-    __shared__ float rs[SPAN][T + 1];
-    const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * T, y0 = blockIdx.y * T;
-    if (blockIdx.x == 0 && blockIdx.y == 0) {
-        if (tid == 0 && s.n_fallback) *s.n_fallback = 0;
-        for (int i = tid; i < s.U * net::H1; i += 256) {
-            const int u = i / net::H1, n = i % net::H1;
-            const double th = 2.0 * 3.14159265358979323846 * (double)u / (double)s.K;
-            const float sn = (float)sin(th), cs = (float)cos(th);
-            s.Y[i] = sn * s.theta[net::OFF_WY + 2 * n] + cs * s.theta[net::OFF_WY + 2 * n + 1];
-        }
-    }
-    {
-        // Known flags of the (16 + 23)^2 span: six loads per thread in flight,
-        // from clamped positions, masked afterwards.
-        constexpr int NB = (SPAN * SPAN + 255) / 256;
-        float hv[NB];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int i = min(tid + 256 * j, SPAN * SPAN - 1);
-            const int y = y0 - net::HALF + i / SPAN, x = x0 - net::HALF + i % SPAN;
-            hv[j] = s.height[(int64_t)min(max(y, 0), s.H - 1) * s.ld + min(max(x, 0), s.W - 1)];
-        }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int i = tid + 256 * j;
-            if (i >= SPAN * SPAN) continue;
-            const int r = i / SPAN, c = i % SPAN;
-            const int y = y0 - net::HALF + r, x = x0 - net::HALF + c;
-            const bool in = y >= 0 && x >= 0 && y < s.H && x < s.W;
-            kf[r][c] = (in && fabsf(hv[j]) < HEIGHT_LIMIT) ? 1.f : 0.f;
-        }
-    }
-    __syncthreads();
-    for (int i = tid; i < SPAN * T; i += 256) {
-        const int r = i / T, c = i % T;
-        float n = 0.f;
-        for (int d = 0; d < net::PATCH; ++d) n += kf[r][c + d];
-        rs[r][c] = n;
-    }
-    __syncthreads();
-    const int c = tid % T, r = tid / T;
-    const int x = x0 + c, y = y0 + r;
-    if (x < s.W && y < s.H) {
-        float n = 0.f;
-        for (int d = 0; d < net::PATCH; ++d) n += rs[r + d][c];
-        s.known[(int64_t)y * s.W + x] = n * (1.f / (net::PATCH * net::PATCH));
-    }
-}
-
 // Head of every state (cell, yaw unit): a wave owns 16 cells and loops over
-// the yaw units, keeping fc2's weights, its biases and the cells' fc1 values
-// (without the yaw term) in registers.  Both layers are computed transposed,
-// neurons x states:
-//   fc2: D2 (64 x 16) = W4 (64 x 128) . h1^T,   h1 = ReLU(T + Y[u]) in bf16
-//   fc3: D3 (16 x 16, rows 0..3 used) = W5' (16 x 64) . h2^T,  h2 = ReLU(D2 + b4)
+// a range of yaw units, keeping fc2's weights, its biases and the cells' fc1
+// values (without the yaw term) in registers.  Activations are fp16 (the
+// weights are the network's bf16 values, held exactly in fp16), so fc1's yaw
+// term and ReLU run as packed fp16 adds and maxima, two neurons per
+// instruction, and fc2's ReLU converts two neurons per instruction.  Both
+// layers are computed transposed, neurons x states:
+//   fc2: D2 (64 x 16) = W4 (64 x 128) . h1^T + b4,   h1 = ReLU(T + Y[u])
+//   fc3: D3 (16 x 16, rows 0..3 used) = W5' (16 x 64) . h2^T,  h2 = ReLU(D2)
 // In the 16x16x32 MFMA, lane (r, g) = (lane % 16, lane / 16) supplies A's row r
 // and B's column r at reduction indices 8g .. 8g+7 and receives D rows
 // 4g .. 4g+3 of column r.  The lane holding D2's rows 16t + 4g + e (t = 0..3)
 // is therefore the lane that supplies fc3's B column r: fc3 takes them as
 // reduction index 32ks + 8g + e' with neuron 32ks + 4g + e' for e' < 4 and
 // 32ks + 16 + 4g + (e' - 4) for e' >= 4, and W5' is gathered in the same
-// order, which leaves the sum unchanged and needs no trip through LDS.  Stores
-// go to 16 consecutive cells of one yaw plane.
-__global__ __launch_bounds__(256) void head_kernel(const SurArgs s, const AssessArgs a) {
-    extern __shared__ float ys[];            // [U][128] yaw term, shared by the workgroup
-    {
-        // Eight loads per thread in flight before the LDS writes.
-        const int n = s.U * net::H1;
-        for (int i0 = threadIdx.x; i0 < n; i0 += 256 * 8) {
-            float v[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = s.Y[min(i0 + 256 * j, n - 1)];
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (i0 + 256 * j < n) ys[i0 + 256 * j] = v[j];
-        }
-    }
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int r = lane & 15, g = lane >> 4;
-    const int64_t cells = (int64_t)s.H * s.W;
-    const int64_t c0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
-    if (c0 >= cells) return;
-    const bool real = c0 + r < cells;
-    const int64_t cell = real ? c0 + r : cells - 1;
+// order, which leaves the sum unchanged and needs no trip through LDS.  fc2's
+// bias enters as the accumulator of its first product.  Stores go to 16
+// consecutive cells of one yaw plane.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
-    bf16x8 w4[4][4];                         // [t][ks]: W4[16t + r][32ks + 8g + e]
-    float b4v[4][4];                         // [t][e]:  b4[16t + 4g + e]
-    float tv[4][8];                          // [ks][e]: T[cell][32ks + 8g + e]
-    bf16x8 w5[2];                            // [ks][e']: W5[r][neuron(ks, g, e')]
-    static_assert(net::OFF_B4 % 4 == 0, "fc2 biases are read as float4");
-    for (int t = 0; t < 4; ++t) {
-        for (int ks = 0; ks < 4; ++ks)
-            w4[t][ks] = *(const bf16x8*)(s.pw.w4 + (16 * t + r) * net::H1 + 32 * ks + 8 * g);
-        const float4 b = *(const float4*)(s.theta + net::OFF_B4 + 16 * t + 4 * g);
-        b4v[t][0] = b.x;
-        b4v[t][1] = b.y;
-        b4v[t][2] = b.z;
-        b4v[t][3] = b.w;
+__device__ __forceinline__ f16x2 pack_rtz(float x, float y) {
+    return __builtin_bit_cast(f16x2, __builtin_amdgcn_cvt_pkrtz(x, y));
+}
+
+__device__ __forceinline__ f16x8 cat(f16x2 a, f16x2 b, f16x2 c, f16x2 d) {
+    const f16x4 lo = __builtin_shufflevector(a, b, 0, 1, 2, 3);
+    const f16x4 hi = __builtin_shufflevector(c, d, 0, 1, 2, 3);
+    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void head_kernel(const SurArgs s, const AssessArgs a) {
+    // LDS: fc2's weights as fp16 MFMA fragments ([t][ks][lane]), shared by
+    // the four waves, then the yaw term [U][16] (eight fp16 neurons each).
+    extern __shared__ f16x8 lds[];
+    f16x8* w4s = lds;
+    f16x8* ys = lds + 16 * 64;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int r = lane & 15, g = lane >> 4;
+    const int cells = s.H * s.W;
+    const int c0 = (blockIdx.x * 4 + wave) * 16;
+    const int u0 = blockIdx.y * s.upw, u1 = min(s.U, u0 + s.upw);
+    const bool real = c0 + r < cells;
+    const int cell = real ? c0 + r : cells - 1;
+    // Every global load of the workgroup is issued here, before the first
+    // wait: fc2's weights and the yaw term for LDS, then the wave's own
+    // operands (its cells' fc1 values, fc2's biases, fc3's weights and
+    // biases, the nine heights of each cell's reference and its known
+    // fraction).
+    f16x8 wst[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int f = tid + 256 * j;                   // fragment (t, ks, lane')
+        const int t = f >> 8, ks = (f >> 6) & 3, ln = f & 63;
+        wst[j] = *(const f16x8*)(s.pw.w4h + (16 * t + (ln & 15)) * net::H1 + 32 * ks +
+                                 8 * (ln >> 4));
     }
+    // fc1's yaw term Y[u][n] = Wy[n] . (sin, cos)(theta_u), eight neurons per
+    // entry, entries tid and tid + 256 (more than 32 yaw units: see below).
+    const int ny = s.U * (net::H1 / 8);
+    float2 ysc[2];
+    float4 wy[2][4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int i = min(tid + 256 * j, ny - 1);
+        ysc[j] = s.yaw_sc[i >> 4];
+        const float4* wp = (const float4*)(s.theta + net::OFF_WY + 16 * (i & 15));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wy[j][q] = wp[q];
+    }
+    static_assert(net::OFF_WY % 4 == 0, "yaw weights read as float4");
+    f16x8 tv[4];                             // [ks]:    T[cell][32ks + 8g + e]
+    float4 traw[4][2];
+#pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-        const float4* tp = (const float4*)(s.T + cell * net::H1 + 32 * ks + 8 * g);
-        const float4 t0 = tp[0], t1 = tp[1];
-        tv[ks][0] = t0.x; tv[ks][1] = t0.y; tv[ks][2] = t0.z; tv[ks][3] = t0.w;
-        tv[ks][4] = t1.x; tv[ks][5] = t1.y; tv[ks][6] = t1.z; tv[ks][7] = t1.w;
+        const float4* tp = (const float4*)(s.T + (int64_t)cell * net::H1 + 32 * ks + 8 * g);
+        traw[ks][0] = tp[0];
+        traw[ks][1] = tp[1];
     }
-    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    f32x4 b4v[4];                            // [t]:     b4[16t + 4g + e]
+    static_assert(net::OFF_B4 % 4 == 0, "fc2 biases are read as float4");
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const float4 b = *(const float4*)(s.theta + net::OFF_B4 + 16 * t + 4 * g);
+        b4v[t] = f32x4{b.x, b.y, b.z, b.w};
+    }
+    f16x8 w5[2];                             // [ks]:    W5[r][neuron(ks, g, e')]
+#pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
         // neurons 32 ks + 4 g .. + 3, then 32 ks + 16 + 4 g .. + 3 (rows 4..15 of
         // the packed W5 are zero)
-        const bf16x4 lo = *(const bf16x4*)(s.pw.w5 + r * net::H2 + 32 * ks + 4 * g);
-        const bf16x4 hi = *(const bf16x4*)(s.pw.w5 + r * net::H2 + 32 * ks + 16 + 4 * g);
-        for (int e = 0; e < 4; ++e) {
-            w5[ks][e] = lo[e];
-            w5[ks][4 + e] = hi[e];
-        }
+        const f16x4 lo = *(const f16x4*)(s.pw.w5h + r * net::H2 + 32 * ks + 4 * g);
+        const f16x4 hi = *(const f16x4*)(s.pw.w5h + r * net::H2 + 32 * ks + 16 + 4 * g);
+        w5[ks] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
     }
-
     float b5[4];
     for (int j = 0; j < 4; ++j) b5[j] = s.theta[net::OFF_B5 + j];
-
     // Per-cell part of the fallback rule and the plane height offset.
-    const int cy = (int)(cell / s.W), cx = (int)(cell % s.W);
+    const int cy = cell / s.W, cx = cell - cy * s.W;
     float hc;
     const bool has_ref = ref_height(s, cy, cx, &hc);
     const bool out_of_dist = !has_ref || s.known[cell] < s.min_known;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w4s[tid + 256 * j] = wst[j];
+    auto to_f16x8 = [](float4 p, float4 q) {
+        return f16x8{(_Float16)p.x, (_Float16)p.y, (_Float16)p.z, (_Float16)p.w,
+                     (_Float16)q.x, (_Float16)q.y, (_Float16)q.z, (_Float16)q.w};
+    };
+    // (Wy is [n][2]: float4 q holds neurons 2q and 2q + 1 of the entry.)
+    auto yaw_entry = [](float2 sc, const float4 (&w)[4]) {
+        f16x8 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[2 * q] = (_Float16)(sc.x * w[q].x + sc.y * w[q].y);
+            v[2 * q + 1] = (_Float16)(sc.x * w[q].z + sc.y * w[q].w);
+        }
+        return v;
+    };
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int i = tid + 256 * j;
+        if (i < ny) ys[i] = yaw_entry(ysc[j], wy[j]);
+    }
+    for (int i = tid + 512; i < ny; i += 256) {          // more than 32 yaw units
+        const float4* wp = (const float4*)(s.theta + net::OFF_WY + 16 * (i & 15));
+        const float4 w[4] = {wp[0], wp[1], wp[2], wp[3]};
+        ys[i] = yaw_entry(s.yaw_sc[i >> 4], w);
+    }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) tv[ks] = to_f16x8(traw[ks][0], traw[ks][1]);
+    __syncthreads();
+    if (c0 >= cells) return;
+    f16x8 w4[4][4];                          // [t][ks]: W4[16t + r][32ks + 8g + e]
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) w4[t][ks] = w4s[(t * 4 + ks) * 64 + lane];
     // Every load above is complete before the loop: a wait inside it would
     // also wait for the previous unit's stores.
     __builtin_amdgcn_s_waitcnt(0);
 
-    for (int u = 0; u < s.U; ++u) {
+    const f16x8 zero8 = {};
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    const int64_t plane = (int64_t)cells;
+    for (int u = u0; u < u1; ++u) {
         f32x4 acc[4];
-        for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
-            const float4* yp = (const float4*)(ys + u * net::H1 + 32 * ks + 8 * g);
-            const float4 y0 = yp[0], y1 = yp[1];
-            bf16x8 h;
-            h[0] = to_bf16(fmaxf(tv[ks][0] + y0.x, 0.f));
-            h[1] = to_bf16(fmaxf(tv[ks][1] + y0.y, 0.f));
-            h[2] = to_bf16(fmaxf(tv[ks][2] + y0.z, 0.f));
-            h[3] = to_bf16(fmaxf(tv[ks][3] + y0.w, 0.f));
-            h[4] = to_bf16(fmaxf(tv[ks][4] + y1.x, 0.f));
-            h[5] = to_bf16(fmaxf(tv[ks][5] + y1.y, 0.f));
-            h[6] = to_bf16(fmaxf(tv[ks][6] + y1.z, 0.f));
-            h[7] = to_bf16(fmaxf(tv[ks][7] + y1.w, 0.f));
+            const f16x8 h = __builtin_elementwise_max(tv[ks] + ys[u * 16 + 4 * ks + g], zero8);
+#pragma unroll
             for (int t = 0; t < 4; ++t)
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4[t][ks], h, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w4[t][ks], h,
+                                                                 ks == 0 ? b4v[t] : acc[t], 0, 0, 0);
         }
-        f32x4 y3 = f32x4{0.f, 0.f, 0.f, 0.f};
+        f32x4 y3 = zero4;
+#pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-            bf16x8 h2;
-            for (int e = 0; e < 4; ++e) {
-                h2[e] = to_bf16(fmaxf(acc[2 * ks][e] + b4v[2 * ks][e], 0.f));
-                h2[4 + e] = to_bf16(fmaxf(acc[2 * ks + 1][e] + b4v[2 * ks + 1][e], 0.f));
-            }
-            y3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w5[ks], h2, y3, 0, 0, 0);
+            const f32x4 p = acc[2 * ks], q = acc[2 * ks + 1];
+            const f16x8 h2 = __builtin_elementwise_max(
+                cat(pack_rtz(p[0], p[1]), pack_rtz(p[2], p[3]), pack_rtz(q[0], q[1]),
+                    pack_rtz(q[2], q[3])),
+                zero8);
+            y3 = __builtin_amdgcn_mfma_f32_16x16x32_f16(w5[ks], h2, y3, 0, 0, 0);
         }
         // Lanes of group 0 hold the four outputs of state (cell, u).
         if (g == 0 && real) {
@@ -447,7 +508,7 @@ __global__ __launch_bounds__(256) void head_kernel(const SurArgs s, const Assess
             const float o3 = y3[3] + b5[3];
             const float risk = fminf(fmaxf(o3, 0.f), 1.f);
             const bool fb = out_of_dist || fabsf(risk - s.risk_max) < s.band;
-            s.need[(int64_t)u * cells + cell] = fb ? 1 : 0;
+            s.need[u * plane + cell] = fb ? 1 : 0;
             if (!fb) {
                 Result res;
                 res.z = hc + net::S_Z * o0;
@@ -467,14 +528,12 @@ __global__ __launch_bounds__(256) void head_kernel(const SurArgs s, const Assess
 hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, hipStream_t stream) {
     const int64_t cells = (int64_t)s.H * s.W;
     auto blocks = [](int64_t n, int b) { return (unsigned)((n + b - 1) / b); };
-    hipLaunchKernelGGL(prep_kernel, dim3((s.W + 15) / 16, (s.H + 15) / 16), dim3(256), 0, stream, s);
-    hipLaunchKernelGGL(conv1_map_kernel, dim3(blocks((int64_t)(s.H + 20) * (s.W + 20), 256)),
-                       dim3(256), 0, stream, s);
-    hipLaunchKernelGGL(conv2_map_kernel, dim3(blocks((int64_t)(s.H + 16) * (s.W + 16), 64)),
-                       dim3(256), 0, stream, s);
+    const int conv_tiles = ((s.H + 16 + TT - 1) / TT) * ((s.W + 16 + TT - 1) / TT);
+    const int known_tiles = ((s.H + 15) / 16) * ((s.W + 15) / 16);
+    hipLaunchKernelGGL(trunk_kernel, dim3(conv_tiles + known_tiles), dim3(256), 0, stream, s);
     hipLaunchKernelGGL(fc1_map_kernel, dim3(blocks(cells, FC1_CELLS)), dim3(256), 0, stream, s);
-    hipLaunchKernelGGL(head_kernel, dim3(blocks(cells, 64)), dim3(256),
-                       (size_t)s.U * net::H1 * sizeof(float), stream, s, a);
+    hipLaunchKernelGGL(head_kernel, dim3(blocks(cells, 64), (s.U + s.upw - 1) / s.upw), dim3(256),
+                       (size_t)(net::H2 * net::H1 + s.U * net::H1) * sizeof(net::f16), stream, s, a);
     return hipGetLastError();
 }
 

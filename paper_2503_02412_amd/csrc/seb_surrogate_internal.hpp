@@ -17,15 +17,15 @@ struct SurArgs {
     int W, H;
     float inv_res;
     int K, U, mirror;            // yaw bins, units evaluated (K/2 if mirrored), mirror offset
+    int upw;                     // yaw units per wave of the head kernel
     int pitch;                   // LDS pitch of the fallback kernel's table offsets
     // network
     const float* theta;          // float32 parameters (biases and Wy are read from here)
     net::PackedWeights pw;       // bf16 GEMM weights
     // workspace
-    net::bf16* o1map;            // [(H+20)(W+20)][16]  conv1 at positions -12 .. H+7
+    const float2* yaw_sc;        // [U]                 (sin, cos) of yaw unit u's angle
     net::bf16* o2map;            // [(H+16)(W+16)][32]  conv2 at positions -12 .. H+3
     float* T;                    // [H*W][128]          fc1 without the yaw term
-    float* Y;                    // [U][128]            fc1 yaw term
     float* known;                // [H*W]               known fraction of the 24 x 24 window
     uint8_t* need;               // [U][H*W]            1 = state falls back to the plain method
     int32_t* n_fallback;         // optional device counter of fallen-back states
