@@ -260,78 +260,102 @@ __global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
 }
 
 // fc1 without the yaw term, per cell: T[cell][n] = b3[n] + W3[n] . (conv2 at
-// the 5 x 5 positions cell - 12 + 4 (a, b)).  Implicit GEMM: a workgroup owns
-// FC1_CELLS cells.  For each row a of the 5 x 5 gather it stages the cells'
-// five conv2 vectors (FC1_CELLS x 5 x 32 bf16) in LDS once, so the four waves
-// share them instead of each fetching them from L2; wave w then multiplies
-// them with W3's rows [32 w, 32 w + 32).  Each output still accumulates its 25
-// k-steps in order.
-constexpr int FC1_CELLS = 128;
-constexpr int FC1_STRIDE = net::P2 * net::C2 + 8;     // bf16 per cell in LDS (16 B pad)
-constexpr int FC1_ITEMS = FC1_CELLS * net::P2 * 4;    // 16-byte pieces staged per gather row
-static_assert(FC1_ITEMS % 256 == 0, "fc1 staging assumes whole passes");
+// the 5 x 5 positions cell - 12 + 4 (a, b)), stored as fp16 for the head.
+// Implicit GEMM on MFMA, D (128 neurons x cells) = W3 (128 x 800) . gather^T.
+// A workgroup owns a tile of 2 x 32 cells.  Their gathered conv2 vectors come
+// from 10 rows x 48 columns of conv2 positions (rows cy + 4 a + {0, 1},
+// columns cx + 4 b + 0..31), which are staged in LDS at once (every load in
+// flight together: conv2's map was just written, so these reads miss in L2).
+// The two waves split K: wave 0 takes gathered positions 0..12, wave 1
+// positions 13..24, each for all 64 cells and all 128 neurons (32
+// accumulator tiles), streaming its own half of W3 (L2-resident) with the
+// next k-step's fragments in flight; wave 1's partial sums are added through
+// LDS at the end.  A lane receives four consecutive neurons of one cell.
+constexpr int F1_TY = 2, F1_TX = 32;                  // cells per tile
+constexpr int F1_ROWS = F1_TY * net::P2;              // 10 staged position rows
+constexpr int F1_COLS = F1_TX + 4 * (net::P2 - 1);    // 48 staged position columns
 
-__global__ __launch_bounds__(256) void fc1_map_kernel(const SurArgs s) {
-    __shared__ bf16x8 As[FC1_CELLS * FC1_STRIDE / 8];
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void fc1_kernel(const SurArgs s) {
+    // staged conv2 vectors [row][column][4 pieces of 8 channels]; the first
+    // 32 KB are reused for wave 1's partial sums [m * 8 + t][lane]
+    constexpr int NFP = F1_ROWS * F1_COLS * 4, NPART = 32 * 64;   // 16-byte entries
+    __shared__ bf16x8 fp[NFP > NPART ? NFP : NPART];
+    f32x4* part = reinterpret_cast<f32x4*>(fp);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int W2 = s.W + 16;
-    const int64_t cells = (int64_t)s.H * s.W;
-    const int64_t c0 = (int64_t)blockIdx.x * FC1_CELLS;
-    const int r = lane & 15, kq = lane >> 4;
-    // Biases first: a load issued after the stores below would wait for them.
-    const float bias[2] = {s.theta[net::OFF_B3 + 32 * wave + r],
-                           s.theta[net::OFF_B3 + 32 * wave + 16 + r]};
-    // Staging pieces of this thread: piece = tid + 256 j -> (cell, b, quarter).
-    constexpr int NJ = FC1_ITEMS / 256;
-    int64_t src[NJ];
-    int dst[NJ];
+    const int r = lane & 15, g = lane >> 4;
+    const int W2m = s.W + 16, H2m = s.H + 16;
+    const int tx = (s.W + F1_TX - 1) / F1_TX;
+    const int cy0 = (blockIdx.x / tx) * F1_TY, cx0 = (blockIdx.x % tx) * F1_TX;
+    constexpr int KS = net::P2 * net::P2;     // 25 gathered positions
+    constexpr int KH = (KS + 1) / 2;
+    const int k0 = wave == 0 ? 0 : KH, k1 = wave == 0 ? KH : KS;
+    const bf16* w3 = s.pw.w3 + r * net::F + 8 * g;
+    // Staging: 10 x 48 positions x 4 pieces, 15 per thread, all in flight.
+    constexpr int NP = F1_ROWS * F1_COLS * 4 / 128;
+    static_assert(F1_ROWS * F1_COLS * 4 % 128 == 0, "whole staging passes");
+    bf16x8 v[NP];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const int piece = tid + 256 * j;
-        const int cell = piece / (net::P2 * 4), rem = piece % (net::P2 * 4);
-        const int b5 = rem / 4, q = rem % 4;
-        const int64_t c = min(c0 + cell, cells - 1);
-        const int cy = (int)(c / s.W), cx = (int)(c % s.W);
-        // conv2 position (cy - 12 + 4 a, cx - 12 + 4 b) sits at row cy + 4 a, column cx + 4 b
-        src[j] = ((int64_t)cy * W2 + (cx + 4 * b5)) * net::C2 + 8 * q;
-        dst[j] = (cell * FC1_STRIDE + b5 * net::C2 + 8 * q) / 8;
+    for (int j = 0; j < NP; ++j) {
+        const int i = tid + 128 * j, piece = i & 3, pos = i >> 2;
+        const int rr = pos / F1_COLS, cc = pos - rr * F1_COLS;
+        // staged row rr = 2 a + dy is position row cy0 + 4 a + dy (o2map row)
+        const int y = min(cy0 + 4 * (rr >> 1) + (rr & 1), H2m - 1);
+        const int x = min(cx0 + cc, W2m - 1);
+        v[j] = *(const bf16x8*)(s.o2map + ((int64_t)y * W2m + x) * net::C2 + 8 * piece);
     }
-    f32x4 acc[FC1_CELLS / 16][2];
+    bf16x8 a_cur[8], a_nxt[8];
 #pragma unroll
-    for (int i = 0; i < FC1_CELLS / 16; ++i)
-        for (int t = 0; t < 2; ++t) acc[i][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int a5 = 0; a5 < net::P2; ++a5) {
-        bf16x8 v[NJ];
+    for (int t = 0; t < 8; ++t) a_cur[t] = *(const bf16x8*)(w3 + 16 * t * net::F + 32 * k0);
 #pragma unroll
-        for (int j = 0; j < NJ; ++j)
-            v[j] = *(const bf16x8*)(s.o2map + src[j] + (int64_t)a5 * 4 * W2 * net::C2);
-        bf16x8 bfr[net::P2][2];
+    for (int j = 0; j < NP; ++j) fp[tid + 128 * j] = v[j];
+    __syncthreads();
+    f32x4 acc[4][8];
 #pragma unroll
-        for (int b5 = 0; b5 < net::P2; ++b5)
-            for (int t = 0; t < 2; ++t)
-                bfr[b5][t] = *(const bf16x8*)(s.pw.w3 + (int64_t)(32 * wave + 16 * t + r) * net::F +
-                                              32 * (a5 * net::P2 + b5) + 8 * kq);
-        if (a5 > 0) __syncthreads();        // the previous row's products are done with As
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) As[dst[j]] = v[j];
-        __syncthreads();
+        for (int t = 0; t < 8; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k = k0; k < k1; ++k) {
+        if (k + 1 < k1) {
 #pragma unroll
-        for (int b5 = 0; b5 < net::P2; ++b5)
+            for (int t = 0; t < 8; ++t) a_nxt[t] = *(const bf16x8*)(w3 + 16 * t * net::F + 32 * (k + 1));
+        }
+        const int a5 = k / net::P2, b5 = k - a5 * net::P2;
+        bf16x8 bv[4];
 #pragma unroll
-            for (int i = 0; i < FC1_CELLS / 16; ++i) {
-                const bf16x8 a = As[((16 * i + r) * FC1_STRIDE + b5 * net::C2 + 8 * kq) / 8];
-                for (int t = 0; t < 2; ++t)
-                    acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[b5][t], acc[i][t], 0, 0, 0);
-            }
+        for (int m = 0; m < 4; ++m)           // cell (dy, dx) = (m / 2, 16 (m % 2) + r)
+            bv[m] = fp[((2 * a5 + (m >> 1)) * F1_COLS + 16 * (m & 1) + r + 4 * b5) * 4 + g];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_cur[t], bv[m], acc[m][t], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) a_cur[t] = a_nxt[t];
     }
+    __syncthreads();                          // every wave is done with the staged vectors
+    if (wave == 1) {
 #pragma unroll
-    for (int i = 0; i < FC1_CELLS / 16; ++i)
-        for (int t = 0; t < 2; ++t)
-            for (int e = 0; e < 4; ++e) {
-                const int64_t c = c0 + 16 * i + 4 * kq + e;
-                const int n = 32 * wave + 16 * t + r;
-                if (c < cells) s.T[c * net::H1 + n] = acc[i][t][e] + bias[t];
-            }
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) part[(m * 8 + t) * 64 + lane] = acc[m][t];
+    }
+    __syncthreads();
+    if (wave == 1) return;
+    static_assert(net::OFF_B3 % 4 == 0, "fc1 biases are read as float4");
+    typedef _Float16 f16x4v __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const float4 bb = *(const float4*)(s.theta + net::OFF_B3 + 16 * t + 4 * g);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int cy = cy0 + (m >> 1), cx = cx0 + 16 * (m & 1) + r;
+            const f32x4 vv = acc[m][t] + part[(m * 8 + t) * 64 + lane];
+            const f16x4v o = {(_Float16)(vv[0] + bb.x), (_Float16)(vv[1] + bb.y),
+                              (_Float16)(vv[2] + bb.z), (_Float16)(vv[3] + bb.w)};
+            if (cy < s.H && cx < s.W)
+                *reinterpret_cast<f16x4v*>(s.T + ((int64_t)cy * s.W + cx) * net::H1 + 16 * t + 4 * g) = o;
+        }
+    }
 }
 
 // Head of every state (cell, yaw unit): a wave owns 16 cells and loops over
@@ -408,13 +432,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void h
     }
     static_assert(net::OFF_WY % 4 == 0, "yaw weights read as float4");
     f16x8 tv[4];                             // [ks]:    T[cell][32ks + 8g + e]
-    float4 traw[4][2];
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-        const float4* tp = (const float4*)(s.T + (int64_t)cell * net::H1 + 32 * ks + 8 * g);
-        traw[ks][0] = tp[0];
-        traw[ks][1] = tp[1];
-    }
+    for (int ks = 0; ks < 4; ++ks)
+        tv[ks] = *(const f16x8*)(s.T + (int64_t)cell * net::H1 + 32 * ks + 8 * g);
     f32x4 b4v[4];                            // [t]:     b4[16t + 4g + e]
     static_assert(net::OFF_B4 % 4 == 0, "fc2 biases are read as float4");
 #pragma unroll
@@ -440,10 +460,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void h
     const bool out_of_dist = !has_ref || s.known[cell] < s.min_known;
 #pragma unroll
     for (int j = 0; j < 4; ++j) w4s[tid + 256 * j] = wst[j];
-    auto to_f16x8 = [](float4 p, float4 q) {
-        return f16x8{(_Float16)p.x, (_Float16)p.y, (_Float16)p.z, (_Float16)p.w,
-                     (_Float16)q.x, (_Float16)q.y, (_Float16)q.z, (_Float16)q.w};
-    };
     // (Wy is [n][2]: float4 q holds neurons 2q and 2q + 1 of the entry.)
     auto yaw_entry = [](float2 sc, const float4 (&w)[4]) {
         f16x8 v;
@@ -464,8 +480,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void h
         const float4 w[4] = {wp[0], wp[1], wp[2], wp[3]};
         ys[i] = yaw_entry(s.yaw_sc[i >> 4], w);
     }
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) tv[ks] = to_f16x8(traw[ks][0], traw[ks][1]);
     __syncthreads();
     if (c0 >= cells) return;
     f16x8 w4[4][4];                          // [t][ks]: W4[16t + r][32ks + 8g + e]
@@ -531,7 +545,8 @@ hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, hipStream_t s
     const int conv_tiles = ((s.H + 16 + TT - 1) / TT) * ((s.W + 16 + TT - 1) / TT);
     const int known_tiles = ((s.H + 15) / 16) * ((s.W + 15) / 16);
     hipLaunchKernelGGL(trunk_kernel, dim3(conv_tiles + known_tiles), dim3(256), 0, stream, s);
-    hipLaunchKernelGGL(fc1_map_kernel, dim3(blocks(cells, FC1_CELLS)), dim3(256), 0, stream, s);
+    hipLaunchKernelGGL(fc1_kernel, dim3(((s.H + F1_TY - 1) / F1_TY) * ((s.W + F1_TX - 1) / F1_TX)),
+                       dim3(128), 0, stream, s);
     hipLaunchKernelGGL(head_kernel, dim3(blocks(cells, 64), (s.U + s.upw - 1) / s.upw), dim3(256),
                        (size_t)(net::H2 * net::H1 + s.U * net::H1) * sizeof(net::f16), stream, s, a);
     return hipGetLastError();
