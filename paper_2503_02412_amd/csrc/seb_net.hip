@@ -348,6 +348,8 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* th, PackedWeight
         const float v = th[OFF_W3 + i];
         w.w3[i] = to_bf16(v);
         w.w3t[c * H1 + o] = to_bf16(v);
+        const int kk = c / 16, h = (c % 16) / 8, e = c % 8, t = o / 32, l = o % 32 + 32 * h;
+        w.w3f[(((int64_t)kk * 4 + t) * 64 + l) * 8 + e] = to_bf16(v);
     }
     if (i < H2 * H1) {                                // w4 [64][128], w4t [128][64]
         const int o = i / H1, c = i % H1;
@@ -620,6 +622,7 @@ int seb_net_create(uint64_t seed, int32_t max_batch, seb_net** out) {
               dalloc(n, &n->pw.w5, 16 * N::H2) && dalloc(n, &n->pw.w2t, N::K2P * N::C2) &&
               dalloc(n, &n->pw.w3t, N::F * N::H1) && dalloc(n, &n->pw.w4t, N::H1 * N::H2) &&
               dalloc(n, &n->pw.w5t, N::H2 * 32) && dalloc(n, &n->pw.w4h, N::H2 * N::H1) &&
+              dalloc(n, &n->pw.w3f, N::H1 * N::F) &&
               dalloc(n, &n->pw.w5h, 16 * N::H2) && dalloc(n, &n->A1, r1 * N::K1P) &&
               dalloc(n, &n->A1t, r1 * N::K1P) && dalloc(n, &n->o1, r1 * N::C1) &&
               dalloc(n, &n->da1, r1 * N::C1) && dalloc(n, &n->da1t, r1 * N::C1) &&

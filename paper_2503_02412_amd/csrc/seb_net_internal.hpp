@@ -51,6 +51,8 @@ struct PackedWeights {
     bf16* w3t;   // [800][128]
     bf16* w4t;   // [128][64]
     bf16* w5t;   // [64][32]        columns 4..31 zero
+    bf16* w3f;   // [50][4][64][8]  w3 as 32x32x16 MFMA A fragments: K step kk, neuron tile t,
+                 //                 lane l -> W3[32t + l % 32][16kk + 8 (l / 32) + e]
     f16* w4h;    // [64][128]       w4 in fp16 (the bf16 values, exactly): inference head
     f16* w5h;    // [16][64]        w5 in fp16, rows 4..15 zero
 };

@@ -260,39 +260,46 @@ __global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
 }
 
 // fc1 without the yaw term, per cell: T[cell][n] = b3[n] + W3[n] . (conv2 at
-// the 5 x 5 positions cell - 12 + 4 (a, b)), stored as fp16 for the head.
-// Implicit GEMM on MFMA, D (128 neurons x cells) = W3 (128 x 800) . gather^T.
-// A workgroup owns a tile of 2 x 32 cells.  Their gathered conv2 vectors come
-// from 10 rows x 48 columns of conv2 positions (rows cy + 4 a + {0, 1},
-// columns cx + 4 b + 0..31), which are staged in LDS at once (every load in
-// flight together: conv2's map was just written, so these reads miss in L2).
-// The two waves split K: wave 0 takes gathered positions 0..12, wave 1
-// positions 13..24, each for all 64 cells and all 128 neurons (32
-// accumulator tiles), streaming its own half of W3 (L2-resident) with the
-// next k-step's fragments in flight; wave 1's partial sums are added through
-// LDS at the end.  A lane receives four consecutive neurons of one cell.
+// the 5 x 5 positions cell - 12 + 4 (a, b)), stored as fp16 for the head in
+// chunks of eight neurons, [n / 8][cell][n % 8], so that both this kernel's
+// stores and the head's loads are contiguous across lanes.
+// Implicit GEMM on the 32x32x16 MFMA (measured about 1.5 times the throughput
+// of 16x16x32 on this device), D (128 neurons x cells) = W3 (128 x 800) .
+// gather^T.  A workgroup owns a tile of 2 x 32 cells.  Their gathered conv2
+// vectors come from 10 rows x 48 columns of conv2 positions (rows
+// cy + 4 a + {0, 1}, columns cx + 4 b + 0..31), staged in LDS at once (every
+// load in flight together: conv2's map was just written, so these reads miss
+// in L2).  The two waves split K: wave 0 takes gathered positions 0..12, wave
+// 1 positions 13..24, each for both cell rows and all 128 neurons (8
+// accumulator tiles), streaming its half of W3 from the fragment-ordered copy
+// (1 KB contiguous per fragment) with the next step's fragments in flight;
+// wave 1's partial sums are added through LDS at the end.  In the 32x32x16
+// MFMA lane l supplies A's row and B's column l % 32 at K 8 (l / 32) .. + 7 and
+// receives D's column l % 32, rows 8 q + 4 (l / 32) + (0..3), q = 0..3.
 constexpr int F1_TY = 2, F1_TX = 32;                  // cells per tile
 constexpr int F1_ROWS = F1_TY * net::P2;              // 10 staged position rows
 constexpr int F1_COLS = F1_TX + 4 * (net::P2 - 1);    // 48 staged position columns
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void fc1_kernel(const SurArgs s) {
-    // staged conv2 vectors [row][column][4 pieces of 8 channels]; the first
-    // 32 KB are reused for wave 1's partial sums [m * 8 + t][lane]
-    constexpr int NFP = F1_ROWS * F1_COLS * 4, NPART = 32 * 64;   // 16-byte entries
+    // staged conv2 vectors [row][piece of 8 channels][column] (consecutive
+    // lanes read consecutive 16-byte entries); the first 32 KB are reused for
+    // wave 1's partial sums [tile][quarter][lane]
+    constexpr int NFP = F1_ROWS * F1_COLS * 4, NPART = 8 * 16 * 64 / 4;   // 16-byte entries
     __shared__ bf16x8 fp[NFP > NPART ? NFP : NPART];
     f32x4* part = reinterpret_cast<f32x4*>(fp);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int r = lane & 15, g = lane >> 4;
-    const int W2m = s.W + 16, H2m = s.H + 16;
+    const int lc = lane & 31, lh = lane >> 5;
+    const int W2m = s.W + 16, H2m = s.H + 16, cells = s.H * s.W;
     const int tx = (s.W + F1_TX - 1) / F1_TX;
     const int cy0 = (blockIdx.x / tx) * F1_TY, cx0 = (blockIdx.x % tx) * F1_TX;
     constexpr int KS = net::P2 * net::P2;     // 25 gathered positions
     constexpr int KH = (KS + 1) / 2;
     const int k0 = wave == 0 ? 0 : KH, k1 = wave == 0 ? KH : KS;
-    const bf16* w3 = s.pw.w3 + r * net::F + 8 * g;
+    const bf16x8* w3f = reinterpret_cast<const bf16x8*>(s.pw.w3f) + lane;
     // Staging: 10 x 48 positions x 4 pieces, 15 per thread, all in flight.
-    constexpr int NP = F1_ROWS * F1_COLS * 4 / 128;
-    static_assert(F1_ROWS * F1_COLS * 4 % 128 == 0, "whole staging passes");
+    constexpr int NP = NFP / 128;
+    static_assert(NFP % 128 == 0, "whole staging passes");
     bf16x8 v[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
@@ -303,59 +310,90 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void f
         const int x = min(cx0 + cc, W2m - 1);
         v[j] = *(const bf16x8*)(s.o2map + ((int64_t)y * W2m + x) * net::C2 + 8 * piece);
     }
-    bf16x8 a_cur[8], a_nxt[8];
+    // A fragments of gathered position k: K16 steps 2k, 2k + 1, tiles 0..3
+    auto load_a = [&](int k, bf16x8 (&av)[2][4]) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) a_cur[t] = *(const bf16x8*)(w3 + 16 * t * net::F + 32 * k0);
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int j = 0; j < NP; ++j) fp[tid + 128 * j] = v[j];
-    __syncthreads();
-    f32x4 acc[4][8];
+            for (int t = 0; t < 4; ++t) av[h][t] = w3f[((2 * k + h) * 4 + t) * 64];
+    };
+    bf16x8 a_cur[2][4], a_nxt[2][4];
+    load_a(k0, a_cur);
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int t = 0; t < 8; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k = k0; k < k1; ++k) {
-        if (k + 1 < k1) {
-#pragma unroll
-            for (int t = 0; t < 8; ++t) a_nxt[t] = *(const bf16x8*)(w3 + 16 * t * net::F + 32 * (k + 1));
-        }
-        const int a5 = k / net::P2, b5 = k - a5 * net::P2;
-        bf16x8 bv[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m)           // cell (dy, dx) = (m / 2, 16 (m % 2) + r)
-            bv[m] = fp[((2 * a5 + (m >> 1)) * F1_COLS + 16 * (m & 1) + r + 4 * b5) * 4 + g];
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_cur[t], bv[m], acc[m][t], 0, 0, 0);
-#pragma unroll
-        for (int t = 0; t < 8; ++t) a_cur[t] = a_nxt[t];
+    for (int j = 0; j < NP; ++j) {
+        const int i = tid + 128 * j, piece = i & 3, pos = i >> 2;
+        const int rr = pos / F1_COLS, cc = pos - rr * F1_COLS;
+        fp[(rr * 4 + piece) * F1_COLS + cc] = v[j];
     }
+    __syncthreads();
+    f32x16 acc[2][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc[m][t][j] = 0.f;
+    auto step = [&](int k, const bf16x8 (&av)[2][4]) {
+        const int a5 = k / net::P2, b5 = k - a5 * net::P2;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            bf16x8 bv[2];
+#pragma unroll
+            for (int m = 0; m < 2; ++m)       // cell (dy, dx) = (m, lc): channels 16 h + 8 lh ..
+                bv[m] = fp[((2 * a5 + m) * 4 + 2 * h + lh) * F1_COLS + lc + 4 * b5];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+                    acc[m][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[h][t], bv[m], acc[m][t], 0, 0, 0);
+        }
+    };
+    // Two steps per iteration over two fragment buffers (no register copies).
+    int k = k0;
+    for (; k + 1 < k1; k += 2) {
+        load_a(k + 1, a_nxt);
+        step(k, a_cur);
+        if (k + 2 < k1) load_a(k + 2, a_cur);
+        step(k + 1, a_nxt);
+    }
+    if (k < k1) step(k, a_cur);
     __syncthreads();                          // every wave is done with the staged vectors
     if (wave == 1) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < 2; ++m)
 #pragma unroll
-            for (int t = 0; t < 8; ++t) part[(m * 8 + t) * 64 + lane] = acc[m][t];
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    part[((m * 4 + t) * 4 + q) * 64 + lane] =
+                        f32x4{acc[m][t][4 * q], acc[m][t][4 * q + 1], acc[m][t][4 * q + 2],
+                              acc[m][t][4 * q + 3]};
     }
     __syncthreads();
     if (wave == 1) return;
     static_assert(net::OFF_B3 % 4 == 0, "fc1 biases are read as float4");
     typedef _Float16 f16x4v __attribute__((ext_vector_type(4)));
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const float4 bb = *(const float4*)(s.theta + net::OFF_B3 + 16 * t + 4 * g);
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int cy = cy0 + (m >> 1), cx = cx0 + 16 * (m & 1) + r;
-            const f32x4 vv = acc[m][t] + part[(m * 8 + t) * 64 + lane];
-            const f16x4v o = {(_Float16)(vv[0] + bb.x), (_Float16)(vv[1] + bb.y),
-                              (_Float16)(vv[2] + bb.z), (_Float16)(vv[3] + bb.w)};
-            if (cy < s.H && cx < s.W)
-                *reinterpret_cast<f16x4v*>(s.T + ((int64_t)cy * s.W + cx) * net::H1 + 16 * t + 4 * g) = o;
+        for (int q = 0; q < 4; ++q) {
+            // neurons 32 t + 8 q + 4 lh + (0..3)
+            const int n = 32 * t + 8 * q + 4 * lh;
+            const float4 bb = *(const float4*)(s.theta + net::OFF_B3 + n);
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const int cy = cy0 + m, cx = cx0 + lc;
+                const f32x4 pv = part[((m * 4 + t) * 4 + q) * 64 + lane];
+                const f16x4v o = {(_Float16)(acc[m][t][4 * q] + pv[0] + bb.x),
+                                  (_Float16)(acc[m][t][4 * q + 1] + pv[1] + bb.y),
+                                  (_Float16)(acc[m][t][4 * q + 2] + pv[2] + bb.z),
+                                  (_Float16)(acc[m][t][4 * q + 3] + pv[3] + bb.w)};
+                // T is [neuron chunk of 8][cell][8]: chunk 4 t + q, half lh
+                if (cy < s.H && cx < s.W)
+                    *reinterpret_cast<f16x4v*>(s.T + ((int64_t)(4 * t + q) * cells + cy * s.W + cx) * 8 +
+                                               4 * lh) = o;
+            }
         }
-    }
 }
 
 // Head of every state (cell, yaw unit): a wave owns 16 cells and loops over
@@ -433,8 +471,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void h
     static_assert(net::OFF_WY % 4 == 0, "yaw weights read as float4");
     f16x8 tv[4];                             // [ks]:    T[cell][32ks + 8g + e]
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
-        tv[ks] = *(const f16x8*)(s.T + (int64_t)cell * net::H1 + 32 * ks + 8 * g);
+    for (int ks = 0; ks < 4; ++ks)           // chunk 4 ks + g of T [chunk][cell][8]
+        tv[ks] = *(const f16x8*)(s.T + ((int64_t)(4 * ks + g) * cells + cell) * 8);
     f32x4 b4v[4];                            // [t]:     b4[16t + 4g + e]
     static_assert(net::OFF_B4 % 4 == 0, "fc2 biases are read as float4");
 #pragma unroll

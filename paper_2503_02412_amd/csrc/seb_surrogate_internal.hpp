@@ -25,7 +25,8 @@ struct SurArgs {
     // workspace
     const float2* yaw_sc;        // [U]                 (sin, cos) of yaw unit u's angle
     net::bf16* o2map;            // [(H+16)(W+16)][32]  conv2 at positions -12 .. H+3
-    net::f16* T;                 // [H*W][128]          fc1 without the yaw term
+    net::f16* T;                 // [16][H*W][8]        fc1 without the yaw term, neuron n
+                                 //                     of cell c at [n / 8][c][n % 8]
     float* known;                // [H*W]               known fraction of the 24 x 24 window
     uint8_t* need;               // [U][H*W]            1 = state falls back to the plain method
     int32_t* n_fallback;         // optional device counter of fallen-back states
