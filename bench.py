@@ -33,6 +33,11 @@ from paper_2503_02412_amd import inputs as I  # noqa: E402
 METRIC = ("SE(2) cells/s and ms per 200×200×36 map; surrogate vs plain at matched error")
 VENDOR_FP32_PEAK_TFLOPS = 157.3       # 256 CU x 2.4 GHz x 64 lanes x 2 (FMA) x 2 (dual/packed)
 HBM_PEAK_GBS = 8000.0
+VENDOR_BF16_PEAK_TFLOPS = 2500.0       # dense bf16 MFMA
+# Surrogate network MACs per sample (24x24 window): conv1 121 x 16 x 48, conv2
+# 25 x 32 x 144, fc1 800 x 128 (+ 2 x 128 yaw), fc2 128 x 64, fc3 64 x 4.
+_FWD_MAC = 121 * 16 * 48 + 25 * 32 * 144 + (800 + 2) * 128 + 128 * 64 + 64 * 4
+TRAIN_FLOP_PER_SAMPLE = 2 * (3 * _FWD_MAC - 121 * 16 * 48)
 
 
 def flops_per_state(params) -> int:
@@ -120,6 +125,9 @@ def bench_rolling(torch, seb, n_moves: int = 100):
     wall = (time.perf_counter() - t0) * 1e3 / n_moves
     per = np.array([ev[s - 1].elapsed_time(ev[s]) for s in range(1, n_moves + 1)])
     full_ms = time_launches(torch, lambda: ctx.assess(win.ring, win.out), 20, 3)
+    # roofline: algorithmic flops of the recomputed states over the update time
+    upd_tflops = states / n_moves * flops_per_state(p) / (per.mean() * 1e-3) / 1e12
+    full_tflops = p.n_states * flops_per_state(p) / (full_ms * 1e-3) / 1e12
     return {
         "workload": "400x400 @0.05 m, 72 yaw bins, 1.0x0.6 m footprint on 20x12; "
                     "100 moves of 0.5 m in random headings",
@@ -128,6 +136,11 @@ def bench_rolling(torch, seb, n_moves: int = 100):
         "full_recompute_ms": full_ms,
         "states_recomputed_per_move": states / n_moves,
         "fraction_of_full_map": states / n_moves / p.n_states,
+        "roofline": {"bound": "alu", "peak": VENDOR_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "update_achieved": upd_tflops,
+                     "update_frac": upd_tflops / VENDOR_FP32_PEAK_TFLOPS,
+                     "full_recompute_achieved": full_tflops,
+                     "full_recompute_frac": full_tflops / VENDOR_FP32_PEAK_TFLOPS},
     }
 
 
@@ -150,9 +163,17 @@ def bench_sdf(torch, seb, n_poses: int = 1 << 20):
     trilinear SDF + risk query at 2^20 random poses."""
     res = {}
     for name, p, hmap, cap in (("config2", I.CONFIG2, I.config2_map(2), 20),
-                               ("config5", I.CONFIG5, I.config5_map(5), 40)):
+                               ("config5", I.CONFIG5, I.config5_map(5), 40),
+                               ("config5_synthetic_status", I.CONFIG5, None, 40)):
         ctx = seb.Context(p)
-        out = ctx.assess(torch.from_numpy(hmap).cuda())
+        if hmap is not None:
+            out = ctx.assess(torch.from_numpy(hmap).cuda())
+        else:
+            # the 800x800 map's assessment has almost no obstacles (2.0x1.2 m
+            # footprint); this status field has ~12% obstacle states in yaw-
+            # dependent blobs (the 200x200 map has ~4%)
+            st = torch.from_numpy(I.synthetic_status(p.width, p.height, p.n_yaw, seed=21)).cuda()
+            out = {"status": st, "risk": torch.rand(st.shape, device="cuda")}
         sdf = torch.empty_like(out["risk"])
         ms = time_launches(torch, lambda: ctx.sdf(out["status"], cap, True, out=sdf), 50, 5)
         rand = torch.from_numpy(I.query_poses(n_poses, p.width, p.height, p.resolution,
@@ -168,7 +189,8 @@ def bench_sdf(torch, seb, n_poses: int = 1 << 20):
         res[name] = {
             "workload": f"{p.width}x{p.height} @{p.resolution} m, {p.n_yaw} yaw bins, "
                         f"cap {cap} cells; {n_poses} query poses, uniform random or along "
-                        f"{n_poses >> 10} paths of 1024 samples",
+                        f"{n_poses >> 10} paths of 1024 samples"
+                        + ("; synthetic status field (obstacle blobs)" if hmap is None else ""),
             "obstacle_fraction": float(obst.float().mean()),
             "sdf_ms": ms, "sdf_states_per_s": p.n_states / (ms * 1e-3),
             # algorithmic bytes: one status byte in, one float out per state
@@ -287,6 +309,11 @@ def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4, p=N
                     f"{p.fp_length}x{p.fp_width} m on {p.fp_nl}x{p.fp_nw} samples",
         "train_steps": train_steps, "train_batch": 4096,
         "train_samples_per_s": train_steps * 4096 / t_train, "label_seconds": t_data,
+        # algorithmic MFMA work of a training sample: forward + two backward
+        # products per layer, minus conv1's unneeded data gradient
+        "train_mfma_tflops": train_steps * 4096 / t_train * TRAIN_FLOP_PER_SAMPLE / 1e12,
+        "train_mfma_frac_of_bf16_peak":
+            train_steps * 4096 / t_train * TRAIN_FLOP_PER_SAMPLE / 1e12 / VENDOR_BF16_PEAK_TFLOPS,
         "loss_first_last": [float(hist[:20].mean()), float(hist[-20:].mean())],
         "ms_per_map": ms_sur, "cells_per_s": p.n_states / (ms_sur * 1e-3),
         "plain_ms_per_map_same_maps": ms_plain, "speedup_vs_plain": ms_plain / ms_sur,
@@ -300,6 +327,80 @@ def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4, p=N
         "unsafe_traversable_fraction": unsafe / max(1, answered),
         "band": 0.1, "min_known": 0.5,
     }
+
+
+def host_cpu():
+    """lscpu's summary of the host (model, sockets, cores, threads, clock)."""
+    import subprocess
+    keys = ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+            "CPU(s)", "CPU max MHz", "CPU MHz", "L3 cache")
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return {"lscpu": "unavailable", "nproc": os.cpu_count()}
+    info = {}
+    for line in out.splitlines():
+        k, _, v = line.partition(":")
+        if k.strip() in keys:
+            info[k.strip()] = v.strip()
+    info["nproc"] = os.cpu_count()
+    return info
+
+
+def oracle_timings(threads: int):
+    """The FP64 oracle on the other workloads, all host threads: the 64x64x16
+    map in full; the 400x400x72 window in full and per rolling update (the
+    band rectangles of the first three moves of the trajectory); the 64x64x72
+    subregion of the 800x800 map (2.0x1.2 m footprint, 960 samples)."""
+    import oracle
+    res = {}
+
+    def timed(fn, n_states, reps=1):
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            t.append(time.perf_counter() - t0)
+        dt = float(np.median(t))
+        return {"seconds": dt, "states": int(n_states), "cells_per_s": n_states / dt}
+
+    p1 = I.CONFIG1
+    h1 = I.config1_map(1)
+    res["64x64x16_full"] = timed(lambda: oracle.assess_rect(p1, h1, threads=threads),
+                                 p1.n_states, reps=3)
+    p3 = I.CONFIG3
+    world, traj = I.rolling_world(p3, seed=3, n_steps=3)
+    plan0 = seb_plan(p3, 0, 0, *traj[0])
+    ox, oy = plan0.new_origin_x, plan0.new_origin_y
+    h3 = world.window(ox, oy, p3.width, p3.height)
+    res["400x400x72_full"] = timed(lambda: oracle.assess_rect(p3, h3, threads=threads),
+                                   p3.n_states)
+    upd = []
+    for s in range(1, 4):
+        plan = seb_plan(p3, ox, oy, *traj[s])
+        ox, oy = plan.new_origin_x, plan.new_origin_y
+        hw = world.window(ox, oy, p3.width, p3.height)
+        rects = [tuple(plan.rects[i]) for i in range(plan.n_rects)]
+        t0 = time.perf_counter()
+        for (x0, y0, nx, ny) in rects:
+            oracle.assess_rect(p3, hw, x0=x0, y0=y0, nx=nx, ny=ny, threads=threads)
+        upd.append((time.perf_counter() - t0, plan.n_states))
+    res["400x400x72_update"] = {"seconds_mean": float(np.mean([u[0] for u in upd])),
+                                "states_mean": float(np.mean([u[1] for u in upd])),
+                                "cells_per_s": float(sum(u[1] for u in upd) /
+                                                     sum(u[0] for u in upd))}
+    p5 = I.CONFIG5
+    h5 = I.config5_map(5)
+    x0 = y0 = 736           # the precision study's subregion
+    res["800x800x72_subregion_64x64"] = timed(
+        lambda: oracle.assess_rect(p5, h5, x0=x0, y0=y0, nx=64, ny=64, threads=threads),
+        64 * 64 * p5.n_yaw)
+    return res
+
+
+def seb_plan(params, ox, oy, x, y):
+    from paper_2503_02412_amd import seb
+    return seb.plan_window_move(params, ox, oy, x, y)
 
 
 def cpu_baseline(params, hmap, repeats: int = 3):
@@ -320,6 +421,7 @@ def cpu_baseline(params, hmap, repeats: int = 3):
     return {"value": params.n_states / dt, "unit": "SE(2) cells/s", "cores": threads,
             "kind": "oracle", "seconds_per_map": dt,
             "single_core_value": params.n_states / dt1,
+            "host": host_cpu(), "other_workloads": oracle_timings(threads),
             "sample": f"{repeats} full 200x200x36 maps (1,440,000 states each), FP64 oracle, "
                       f"OpenMP over rows, median per map; single core: rows 80-119 of the map, "
                       f"scaled to the full map"}
@@ -360,9 +462,17 @@ def main():
 
     if args.calibrate_copy:
         calibrate_copy(torch)
-    # The extra legs run first: several seconds of GPU work that bring the GPU
-    # to its sustained clock before the headline is timed (after an idle
-    # spell the first ~10 ms of launches run up to 10% slower).
+    p = I.CONFIG2
+    hmap = I.config2_map(2)
+    ctx = seb.Context(p)
+    h = torch.from_numpy(hmap).cuda()
+    out = seb.alloc_outputs(p)
+    # Arguments marshalled once: a step is then one C call and one kernel.
+    launch = ctx.launcher(h, out)
+    # The extra legs run first: seconds of GPU work that bring the GPU to its
+    # sustained clock, ending with the 800 x 800 map's launches, so the
+    # headline is timed at that clock (after an idle spell the first ~10 ms of
+    # launches run up to 10% slower).
     extras = {}
     if not args.no_extras:
         legs = {"rolling": bench_rolling, "large_map": bench_large,
@@ -371,17 +481,13 @@ def main():
                     lambda t, s: bench_surrogate(t, s, p=I.CONFIG2_LARGE_FOOTPRINT),
                 "sdf_query": bench_sdf,
                 "elevation": bench_elevation}
-        for name in args.extras.split(","):
+        names = args.extras.split(",")
+        for name in names:
             if name not in legs:
                 sys.exit(f"unknown extra leg {name!r}; choose from {', '.join(legs)}")
+        for name in sorted(names, key=lambda n: n == "large_map"):
             extras[name] = legs[name](torch, seb)
-    p = I.CONFIG2
-    hmap = I.config2_map(2)
-    ctx = seb.Context(p)
-    h = torch.from_numpy(hmap).cuda()
-    out = seb.alloc_outputs(p)
-    # Arguments marshalled once: a step is then one C call and one kernel.
-    ms = time_launches(torch, ctx.launcher(h, out), args.steps, args.warmup)
+    ms = time_launches(torch, launch, args.steps, args.warmup)
 
     flops = flops_per_state(p) * p.n_states
     achieved = flops / (ms * 1e-3) / 1e12
