@@ -783,8 +783,13 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
     w.inv_res = (float)(1.0 / c->cfg.resolution);
     w.K = c->cfg.n_yaw;
     w.U = U;
-    w.upw = U;
-    if (const char* e = std::getenv("SEB_HEAD_UPW")) w.upw = std::max(1, std::min(U, std::atoi(e)));
+    {
+        // Yaw units per head wave: split the units so that about three waves
+        // per SIMD (3 x 1024) cover the map (a wave owns 32 cells).
+        const int64_t cell_waves = (cells + 31) / 32;
+        const int64_t split = std::min<int64_t>(U, std::max<int64_t>(1, (3072 + cell_waves - 1) / cell_waves));
+        w.upw = (int)((U + split - 1) / split);
+    }
     w.mirror = c->geo.mirror;
     w.pitch = c->fpitch;
     w.risk_max = (float)c->cfg.risk_max;

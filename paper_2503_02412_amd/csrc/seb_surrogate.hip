@@ -396,27 +396,28 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void f
         }
 }
 
-// Head of every state (cell, yaw unit): a wave owns 16 cells and loops over
+// Head of every state (cell, yaw unit): a wave owns 32 cells and loops over
 // a range of yaw units, keeping fc2's weights, its biases and the cells' fc1
 // values (without the yaw term) in registers.  Activations are fp16 (the
 // weights are the network's bf16 values, held exactly in fp16), so fc1's yaw
 // term and ReLU run as packed fp16 adds and maxima, two neurons per
 // instruction, and fc2's ReLU converts two neurons per instruction.  Both
-// layers are computed transposed, neurons x states:
-//   fc2: D2 (64 x 16) = W4 (64 x 128) . h1^T + b4,   h1 = ReLU(T + Y[u])
-//   fc3: D3 (16 x 16, rows 0..3 used) = W5' (16 x 64) . h2^T,  h2 = ReLU(D2)
-// In the 16x16x32 MFMA, lane (r, g) = (lane % 16, lane / 16) supplies A's row r
-// and B's column r at reduction indices 8g .. 8g+7 and receives D rows
-// 4g .. 4g+3 of column r.  The lane holding D2's rows 16t + 4g + e (t = 0..3)
-// is therefore the lane that supplies fc3's B column r: fc3 takes them as
-// reduction index 32ks + 8g + e' with neuron 32ks + 4g + e' for e' < 4 and
-// 32ks + 16 + 4g + (e' - 4) for e' >= 4, and W5' is gathered in the same
-// order, which leaves the sum unchanged and needs no trip through LDS.  fc2's
-// bias enters as the accumulator of its first product.  Stores go to 16
-// consecutive cells of one yaw plane.
+// layers run on the 32x32x16 MFMA (measured 1.8 times the throughput of
+// 16x16x32 on this device), transposed, neurons x states:
+//   fc2: D2 (64 x 32) = W4 (64 x 128) . h1^T + b4,   h1 = ReLU(T + Y[u])
+//   fc3: D3 (32 x 32, rows 0..3 used) = W5' (32 x 64) . h2^T,  h2 = ReLU(D2)
+// Lane l = (c, h) = (l % 32, l / 32) supplies A's row and B's column c at
+// reduction indices 8h .. 8h+7 of each 16-wide K step, and receives D's
+// column c, rows 8q + 4h + j (q, j = 0..3).  So lane (c, h) holds, for
+// state c, fc2's neurons 32t + 8q + 4h + j; fc3's K step kk takes the eight
+// of them with t = kk / 2 and q = 2 (kk % 2) + {0, 1} as its indices 8h .. 8h+7,
+// and W5' is gathered in the same order, which leaves the sum unchanged and
+// needs no trip through LDS.  fc2's bias enters as the accumulator of its
+// first product.  Stores go to 32 consecutive cells of one yaw plane.
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ f16x2 pack_rtz(float x, float y) {
     return __builtin_bit_cast(f16x2, __builtin_amdgcn_cvt_pkrtz(x, y));
@@ -428,20 +429,22 @@ __device__ __forceinline__ f16x8 cat(f16x2 a, f16x2 b, f16x2 c, f16x2 d) {
     return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void head_kernel(const SurArgs s, const AssessArgs a) {
-    // LDS: fc2's weights as fp16 MFMA fragments ([t][ks][lane]), shared by
+constexpr int HEAD_CELLS = 32;               // cells per wave
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void head_kernel(const SurArgs s, const AssessArgs a) {
+    // LDS: fc2's weights as fp16 MFMA fragments ([t][kk][lane]), shared by
     // the four waves, then the yaw term [U][16] (eight fp16 neurons each).
     extern __shared__ f16x8 lds[];
     f16x8* w4s = lds;
     f16x8* ys = lds + 16 * 64;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int r = lane & 15, g = lane >> 4;
+    const int cl = lane & 31, lh = lane >> 5;
     const int cells = s.H * s.W;
-    const int c0 = (blockIdx.x * 4 + wave) * 16;
+    const int c0 = (blockIdx.x * 4 + wave) * HEAD_CELLS;
     const int u0 = blockIdx.y * s.upw, u1 = min(s.U, u0 + s.upw);
-    const bool real = c0 + r < cells;
-    const int cell = real ? c0 + r : cells - 1;
+    const bool real = c0 + cl < cells;
+    const int cell = real ? c0 + cl : cells - 1;
     // Every global load of the workgroup is issued here, before the first
     // wait: fc2's weights and the yaw term for LDS, then the wave's own
     // operands (its cells' fc1 values, fc2's biases, fc3's weights and
@@ -450,10 +453,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void h
     f16x8 wst[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int f = tid + 256 * j;                   // fragment (t, ks, lane')
-        const int t = f >> 8, ks = (f >> 6) & 3, ln = f & 63;
-        wst[j] = *(const f16x8*)(s.pw.w4h + (16 * t + (ln & 15)) * net::H1 + 32 * ks +
-                                 8 * (ln >> 4));
+        const int f = tid + 256 * j;                   // fragment (t, kk, lane')
+        const int t = f >> 9, kk = (f >> 6) & 7, ln = f & 63;
+        wst[j] = *(const f16x8*)(s.pw.w4h + (32 * t + (ln & 31)) * net::H1 + 16 * kk +
+                                 8 * (ln >> 5));
     }
     // fc1's yaw term Y[u][n] = Wy[n] . (sin, cos)(theta_u), eight neurons per
     // entry, entries tid and tid + 256 (more than 32 yaw units: see below).
@@ -469,25 +472,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void h
         for (int q = 0; q < 4; ++q) wy[j][q] = wp[q];
     }
     static_assert(net::OFF_WY % 4 == 0, "yaw weights read as float4");
-    f16x8 tv[4];                             // [ks]:    T[cell][32ks + 8g + e]
+    f16x8 tv[8];                             // [kk]: T[cell][16kk + 8lh + e] (chunk 2kk + lh)
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)           // chunk 4 ks + g of T [chunk][cell][8]
-        tv[ks] = *(const f16x8*)(s.T + ((int64_t)(4 * ks + g) * cells + cell) * 8);
-    f32x4 b4v[4];                            // [t]:     b4[16t + 4g + e]
+    for (int kk = 0; kk < 8; ++kk)
+        tv[kk] = *(const f16x8*)(s.T + ((int64_t)(2 * kk + lh) * cells + cell) * 8);
+    f32x16 b4v[2];                           // [t]: b4[32t + 8q + 4lh + j] at 4q + j
     static_assert(net::OFF_B4 % 4 == 0, "fc2 biases are read as float4");
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const float4 b = *(const float4*)(s.theta + net::OFF_B4 + 16 * t + 4 * g);
-        b4v[t] = f32x4{b.x, b.y, b.z, b.w};
-    }
-    f16x8 w5[2];                             // [ks]:    W5[r][neuron(ks, g, e')]
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-        // neurons 32 ks + 4 g .. + 3, then 32 ks + 16 + 4 g .. + 3 (rows 4..15 of
-        // the packed W5 are zero)
-        const f16x4 lo = *(const f16x4*)(s.pw.w5h + r * net::H2 + 32 * ks + 4 * g);
-        const f16x4 hi = *(const f16x4*)(s.pw.w5h + r * net::H2 + 32 * ks + 16 + 4 * g);
-        w5[ks] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+        for (int q = 0; q < 4; ++q) {
+            const float4 b = *(const float4*)(s.theta + net::OFF_B4 + 32 * t + 8 * q + 4 * lh);
+            b4v[t][4 * q] = b.x;
+            b4v[t][4 * q + 1] = b.y;
+            b4v[t][4 * q + 2] = b.z;
+            b4v[t][4 * q + 3] = b.w;
+        }
+    f16x8 w5[4];                             // [kk]: W5[cl][neuron(kk, lh, e)], rows >= 4 zero
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        // neurons 32 (kk / 2) + 8 (2 (kk % 2) + e / 4) + 4 lh + e % 4
+        const int nb = 32 * (kk >> 1) + 16 * (kk & 1) + 4 * lh;
+        const int row = min(cl, 3);
+        const f16x4 lo = *(const f16x4*)(s.pw.w5h + row * net::H2 + nb);
+        const f16x4 hi = *(const f16x4*)(s.pw.w5h + row * net::H2 + nb + 8);
+        const f16x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+        w5[kk] = cl < 4 ? v : f16x8{};
     }
     float b5[4];
     for (int j = 0; j < 4; ++j) b5[j] = s.theta[net::OFF_B5 + j];
@@ -520,40 +530,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void h
     }
     __syncthreads();
     if (c0 >= cells) return;
-    f16x8 w4[4][4];                          // [t][ks]: W4[16t + r][32ks + 8g + e]
+    f16x8 w4[2][8];                          // [t][kk]: W4[32t + cl][16kk + 8lh + e]
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) w4[t][ks] = w4s[(t * 4 + ks) * 64 + lane];
+        for (int kk = 0; kk < 8; ++kk) w4[t][kk] = w4s[(t * 8 + kk) * 64 + lane];
     // Every load above is complete before the loop: a wait inside it would
     // also wait for the previous unit's stores.
     __builtin_amdgcn_s_waitcnt(0);
 
     const f16x8 zero8 = {};
-    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
     const int64_t plane = (int64_t)cells;
     for (int u = u0; u < u1; ++u) {
-        f32x4 acc[4];
+        f32x16 acc[2];
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const f16x8 h = __builtin_elementwise_max(tv[ks] + ys[u * 16 + 4 * ks + g], zero8);
+        for (int kk = 0; kk < 8; ++kk) {
+            const f16x8 h = __builtin_elementwise_max(tv[kk] + ys[u * 16 + 2 * kk + lh], zero8);
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(w4[t][ks], h,
-                                                                 ks == 0 ? b4v[t] : acc[t], 0, 0, 0);
+            for (int t = 0; t < 2; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w4[t][kk], h,
+                                                                 kk == 0 ? b4v[t] : acc[t], 0, 0, 0);
         }
-        f32x4 y3 = zero4;
+        f32x16 y3 = {};
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const f32x4 p = acc[2 * ks], q = acc[2 * ks + 1];
+        for (int kk = 0; kk < 4; ++kk) {
+            const f32x16& p = acc[kk >> 1];
+            const int q0 = 4 * 2 * (kk & 1);             // first of the two q's, times 4
             const f16x8 h2 = __builtin_elementwise_max(
-                cat(pack_rtz(p[0], p[1]), pack_rtz(p[2], p[3]), pack_rtz(q[0], q[1]),
-                    pack_rtz(q[2], q[3])),
+                cat(pack_rtz(p[q0], p[q0 + 1]), pack_rtz(p[q0 + 2], p[q0 + 3]),
+                    pack_rtz(p[q0 + 4], p[q0 + 5]), pack_rtz(p[q0 + 6], p[q0 + 7])),
                 zero8);
-            y3 = __builtin_amdgcn_mfma_f32_16x16x32_f16(w5[ks], h2, y3, 0, 0, 0);
+            y3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(w5[kk], h2, y3, 0, 0, 0);
         }
-        // Lanes of group 0 hold the four outputs of state (cell, u).
-        if (g == 0 && real) {
+        // Lanes with lh = 0 hold rows 0..3, the four outputs of state (cell, u).
+        if (lh == 0 && real) {
             const float o0 = y3[0] + b5[0];
             const float o1 = y3[1] + b5[1];
             const float o2 = y3[2] + b5[2];
@@ -585,7 +595,8 @@ hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, hipStream_t s
     hipLaunchKernelGGL(trunk_kernel, dim3(conv_tiles + known_tiles), dim3(256), 0, stream, s);
     hipLaunchKernelGGL(fc1_kernel, dim3(((s.H + F1_TY - 1) / F1_TY) * ((s.W + F1_TX - 1) / F1_TX)),
                        dim3(128), 0, stream, s);
-    hipLaunchKernelGGL(head_kernel, dim3(blocks(cells, 64), (s.U + s.upw - 1) / s.upw), dim3(256),
+    hipLaunchKernelGGL(head_kernel, dim3(blocks(cells, 4 * HEAD_CELLS), (s.U + s.upw - 1) / s.upw),
+                       dim3(256),
                        (size_t)(net::H2 * net::H1 + s.U * net::H1) * sizeof(net::f16), stream, s, a);
     return hipGetLastError();
 }
