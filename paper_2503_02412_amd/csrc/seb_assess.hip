@@ -326,16 +326,6 @@ __global__ __launch_bounds__(BLOCK) void insert_kernel(const InsertArgs a) {
 
 }  // namespace
 
-int pick_pitch(int R) {
-    const int need = TILE + 2 * R;
-    static const int pitches[] = {48, 80, 112, 144};
-    for (int p : pitches)
-        if (p >= need) return p;
-    return 0;
-}
-
-bool has_row_kernel(int row_len) { return row_len == 4 || row_len == 12 || row_len == 24; }
-
 template <int P, int FIT>
 static void launch_pf(const AssessArgs& a, dim3 grid, size_t lds, hipStream_t stream) {
     switch (a.row_len) {
@@ -389,19 +379,6 @@ static void launch_flagged_p(const AssessArgs& a, int tf, dim3 grid, size_t lds,
         launch_flagged_pf<P, 1>(a, tf, grid, lds, stream);
     else
         launch_flagged_pf<P, 0>(a, tf, grid, lds, stream);
-}
-
-static int flagged_tile(int R, int pitch) { return (32 + 2 * R <= pitch) ? 32 : 16; }
-
-int64_t flagged_blocks(int W, int H, int n_units, int R, int pitch) {
-    const int tf = flagged_tile(R, pitch);
-    return (int64_t)((W + tf - 1) / tf) * ((H + tf - 1) / tf) * n_units;
-}
-
-int64_t flagged_work_items(int W, int H, int n_units, int R, int pitch) {
-    const int tf = flagged_tile(R, pitch);
-    const int64_t blocks = (int64_t)((W + tf - 1) / tf) * ((H + tf - 1) / tf);
-    return blocks * n_units * (tf * tf / 64);
 }
 
 hipError_t launch_assess_flagged(const AssessArgs& a, int pitch, hipStream_t stream) {

@@ -41,7 +41,6 @@ namespace seb {
 namespace elev {
 namespace {
 
-constexpr int SCAN_CHUNK = 4096;          // cells per prefix-sum block (256 x 16)
 constexpr int SMALL = 8;                  // points a thread folds alone, in registers
 constexpr int CAP = 2048;                 // points a workgroup ranks in LDS
 
@@ -481,8 +480,6 @@ __global__ __launch_bounds__(256) void inpaint_kernel(const InpaintArgs a) {
 }
 
 }  // namespace
-
-int64_t partial_blocks(int64_t n_cells) { return (n_cells + SCAN_CHUNK - 1) / SCAN_CHUNK; }
 
 hipError_t launch_fuse_scan(const ScanArgs& s, const FuseArgs& f, const FuseWork& w,
                             hipStream_t stream) {

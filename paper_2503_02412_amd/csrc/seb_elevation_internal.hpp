@@ -45,7 +45,8 @@ struct FuseWork {
     int32_t* n_fused;        // [1] internal counter when the caller passes none
 };
 
-int64_t partial_blocks(int64_t n_cells);
+constexpr int SCAN_CHUNK = 4096;          // cells per prefix-sum block (256 x 16)
+inline int64_t partial_blocks(int64_t n_cells) { return (n_cells + SCAN_CHUNK - 1) / SCAN_CHUNK; }
 
 // Limits of seb_fuse_scan_static, whose workspace is a file-scope device array.
 constexpr int64_t STATIC_MAX_POINTS = int64_t(1) << 18;

@@ -123,13 +123,27 @@ hipError_t launch_assess(const AssessArgs& a, int pitch, hipStream_t stream);
 // workspace holds flagged_work_items(...) items, 64 cells per item, one count
 // per (unit, block) and one box per item.
 hipError_t launch_assess_flagged(const AssessArgs& a, int pitch, hipStream_t stream);
-int64_t flagged_work_items(int W, int H, int n_units, int R, int pitch);
-int64_t flagged_blocks(int W, int H, int n_units, int R, int pitch);   // units x blocks
+// Block side of the flagged-state kernels: 32 when its halo fits the pitch.
+inline int flagged_tile(int R, int pitch) { return (32 + 2 * R <= pitch) ? 32 : 16; }
+inline int64_t flagged_blocks(int W, int H, int n_units, int R, int pitch) {   // units x blocks
+    const int tf = flagged_tile(R, pitch);
+    return (int64_t)((W + tf - 1) / tf) * ((H + tf - 1) / tf) * n_units;
+}
+inline int64_t flagged_work_items(int W, int H, int n_units, int R, int pitch) {
+    const int tf = flagged_tile(R, pitch);
+    return flagged_blocks(W, H, n_units, R, pitch) * (tf * tf / 64);
+}
 // Row lengths with a specialised (fully unrolled) inner loop.
-bool has_row_kernel(int row_len);
+inline bool has_row_kernel(int row_len) { return row_len == 4 || row_len == 12 || row_len == 24; }
 hipError_t launch_insert(const InsertArgs& a, hipStream_t stream);
-// LDS pitches (floats) the assessment kernel is instantiated for.
-int pick_pitch(int R);
+// LDS pitches (floats) the assessment kernel is instantiated for: the
+// smallest that holds a tile plus its halo, 0 if none does.
+inline int pick_pitch(int R) {
+    const int need = TILE + 2 * R;
+    for (int p : {48, 80, 112, 144})
+        if (p >= need) return p;
+    return 0;
+}
 // LDS bytes of a workgroup that runs a pair of edge tiles.
 inline size_t edge_pair_lds(int R, int pitch) {
     return (size_t)2 * (TILE + 2 * R) * pitch * sizeof(float);

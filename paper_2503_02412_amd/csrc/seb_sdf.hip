@@ -301,8 +301,6 @@ __device__ __forceinline__ void query_pose(const QueryArgs& q, int64_t n) {
 
 }  // namespace
 
-int sdf_max_cap() { return 64; }
-
 hipError_t launch_sdf(const uint8_t* status, float* sdf, int W, int H, int K, int rx, int ry,
                       int cap, float res, int unknown_is_obstacle, hipStream_t stream) {
     SdfArgs a;
