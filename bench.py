@@ -268,7 +268,7 @@ def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4, p=N
     measure its error on the states it answered against the plain kernel (which
     matches the FP64 oracle to within 1e-5 on these maps).  `p`: the map and
     footprint (default: the headline workload)."""
-    from paper_2503_02412_amd.surrogate import TrainingData, train
+    from paper_2503_02412_amd.surrogate import TrainingData, train, validation_loss
     p = I.CONFIG2 if p is None else p
     t0 = time.perf_counter()
     data = TrainingData(params=p.with_(width=64, height=64), count=2_000_000)
@@ -279,6 +279,9 @@ def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4, p=N
     hist = train(net, data, steps=train_steps, batch=4096)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    # held-out loss: maps of seeds never trained on, labelled the same way
+    val = TrainingData(seeds=I.SURROGATE_VAL_SEEDS, params=p.with_(width=64, height=64))
+    val_loss = validation_loss(net, val)
     ctx = seb.Context(p)
     sur = seb.Surrogate(ctx)
     out = seb.alloc_outputs(p)
@@ -315,6 +318,7 @@ def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4, p=N
         "train_mfma_frac_of_bf16_peak":
             train_steps * 4096 / t_train * TRAIN_FLOP_PER_SAMPLE / 1e12 / VENDOR_BF16_PEAK_TFLOPS,
         "loss_first_last": [float(hist[:20].mean()), float(hist[-20:].mean())],
+        "validation_loss": val_loss, "validation_samples": int(val.n_samples),
         "ms_per_map": ms_sur, "cells_per_s": p.n_states / (ms_sur * 1e-3),
         "plain_ms_per_map_same_maps": ms_plain, "speedup_vs_plain": ms_plain / ms_sur,
         "fallback_fraction": float(np.mean(fallback)),

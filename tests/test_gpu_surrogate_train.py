@@ -6,7 +6,7 @@ import pytest
 
 from paper_2503_02412_amd import inputs as I
 from paper_2503_02412_amd import seb
-from paper_2503_02412_amd.surrogate import TrainingData, train
+from paper_2503_02412_amd.surrogate import TrainingData, train, validation_loss
 
 pytestmark = pytest.mark.gpu
 
@@ -40,6 +40,11 @@ def test_trained_surrogate_beats_baselines(orc):
     print("loss", hist[0], hist[len(hist) // 2], hist[-1])
     assert hist[-50:].mean() < 0.5 * hist[:50].mean()
     untrained = seb.Net(seed=1, max_batch=4096)
+    # held-out maps (seeds never trained on): the loss generalises
+    val = TrainingData(seeds=I.SURROGATE_VAL_SEEDS)
+    vl, vl0 = validation_loss(net, val), validation_loss(untrained, val)
+    print("validation loss", vl, "untrained", vl0, "last training", hist[-50:].mean())
+    assert vl < 0.5 * vl0 and vl < 2.0 * hist[-50:].mean()
     # predict-the-mean baseline: constant output equal to the mean training target
     p = I.CONFIG2
     stats = {"trained": [], "untrained": [], "mean": []}

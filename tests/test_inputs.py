@@ -50,3 +50,15 @@ def test_world_window_extraction():
     assert np.array_equal(win, w.heights[5:12, 3:13], equal_nan=True)
     out = w.window(w.gx0 - 4, w.gy0, 10, 2)
     assert np.all(np.isnan(out[:, :4]))
+
+
+def test_pool2_means_known_cells_per_parity():
+    from paper_2503_02412_amd.surrogate import pool2
+    a = np.arange(16, dtype=np.float32).reshape(1, 4, 4)
+    a[0, 0, 0] = np.nan
+    a[0, 2, 3] = np.inf                       # not a known height
+    assert np.allclose(pool2(a, 0, 0)[0], [[10 / 3, 4.5], [10.5, (10 + 14 + 15) / 3]])
+    assert np.allclose(pool2(a, 1, 1)[0], [[7.5, 7.0], [13.5, 15.0]])
+    assert np.allclose(pool2(a, 0, 1)[0], [[3.5, 5.0], [11.5, 15.0]])
+    b = np.full((1, 2, 2), np.nan, np.float32)
+    assert np.isnan(pool2(b, 0, 0)).all() and pool2(b, 1, 1).shape == (1, 1, 1)
