@@ -756,7 +756,6 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
     const bool ok =
         al((void**)&w.yaw_sc, (size_t)U * sizeof(float2)) &&
         al((void**)&w.o2map, (size_t)(H + 16) * (W + 16) * seb::net::C2 * 2) &&
-        al((void**)&w.T, (size_t)cells * seb::net::H1 * 2) &&
         al((void**)&w.known, (size_t)cells * 4) && al((void**)&w.need, (size_t)U * cells) &&
         al((void**)&w.work_cells, (size_t)max_items * 64 * 2) &&
         al((void**)&w.block_count, (size_t)n_blocks * sizeof(int32_t)) &&
@@ -783,13 +782,6 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
     w.inv_res = (float)(1.0 / c->cfg.resolution);
     w.K = c->cfg.n_yaw;
     w.U = U;
-    {
-        // Yaw units per head wave: split the units so that about three waves
-        // per SIMD (3 x 1024) cover the map (a wave owns 32 cells).
-        const int64_t cell_waves = (cells + 31) / 32;
-        const int64_t split = std::min<int64_t>(U, std::max<int64_t>(1, (3072 + cell_waves - 1) / cell_waves));
-        w.upw = (int)((U + split - 1) / split);
-    }
     w.mirror = c->geo.mirror;
     w.pitch = c->fpitch;
     w.risk_max = (float)c->cfg.risk_max;

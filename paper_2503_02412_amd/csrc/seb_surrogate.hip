@@ -259,161 +259,41 @@ __global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
     }
 }
 
-// fc1 without the yaw term, per cell: T[cell][n] = b3[n] + W3[n] . (conv2 at
-// the 5 x 5 positions cell - 12 + 4 (a, b)), stored as fp16 for the head in
-// chunks of eight neurons, [n / 8][cell][n % 8], so that both this kernel's
-// stores and the head's loads are contiguous across lanes.
-// Implicit GEMM on the 32x32x16 MFMA (measured about 1.5 times the throughput
-// of 16x16x32 on this device), D (128 neurons x cells) = W3 (128 x 800) .
-// gather^T.  A workgroup owns a tile of 2 x 32 cells.  Their gathered conv2
-// vectors come from 10 rows x 48 columns of conv2 positions (rows
+// fc1, fc2 and fc3 of every state in one kernel: fc1's output stays in LDS.
+// A workgroup (four waves) owns a tile of 2 x 32 cells.
+//
+// fc1 without the yaw term, per cell: T[n] = b3[n] + W3[n] . (conv2 at the
+// 5 x 5 positions cell - 12 + 4 (a, b)).  Implicit GEMM on the 32x32x16 MFMA
+// (measured about 1.5 times the throughput of 16x16x32 on this device),
+// D (128 neurons x cells) = W3 (128 x 800) . gather^T.  The tile's gathered
+// conv2 vectors come from 10 rows x 48 columns of conv2 positions (rows
 // cy + 4 a + {0, 1}, columns cx + 4 b + 0..31), staged in LDS at once (every
 // load in flight together: conv2's map was just written, so these reads miss
-// in L2).  The two waves split K: wave 0 takes gathered positions 0..12, wave
-// 1 positions 13..24, each for both cell rows and all 128 neurons (8
-// accumulator tiles), streaming its half of W3 from the fragment-ordered copy
-// (1 KB contiguous per fragment) with the next step's fragments in flight;
-// wave 1's partial sums are added through LDS at the end.  In the 32x32x16
-// MFMA lane l supplies A's row and B's column l % 32 at K 8 (l / 32) .. + 7 and
-// receives D's column l % 32, rows 8 q + 4 (l / 32) + (0..3), q = 0..3.
-constexpr int F1_TY = 2, F1_TX = 32;                  // cells per tile
-constexpr int F1_ROWS = F1_TY * net::P2;              // 10 staged position rows
-constexpr int F1_COLS = F1_TX + 4 * (net::P2 - 1);    // 48 staged position columns
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(2))) void fc1_kernel(const SurArgs s) {
-    // staged conv2 vectors [row][piece of 8 channels][column] (consecutive
-    // lanes read consecutive 16-byte entries); the first 32 KB are reused for
-    // wave 1's partial sums [tile][quarter][lane]
-    constexpr int NFP = F1_ROWS * F1_COLS * 4, NPART = 8 * 16 * 64 / 4;   // 16-byte entries
-    __shared__ bf16x8 fp[NFP > NPART ? NFP : NPART];
-    f32x4* part = reinterpret_cast<f32x4*>(fp);
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int lc = lane & 31, lh = lane >> 5;
-    const int W2m = s.W + 16, H2m = s.H + 16, cells = s.H * s.W;
-    const int tx = (s.W + F1_TX - 1) / F1_TX;
-    const int cy0 = (blockIdx.x / tx) * F1_TY, cx0 = (blockIdx.x % tx) * F1_TX;
-    constexpr int KS = net::P2 * net::P2;     // 25 gathered positions
-    constexpr int KH = (KS + 1) / 2;
-    const int k0 = wave == 0 ? 0 : KH, k1 = wave == 0 ? KH : KS;
-    const bf16x8* w3f = reinterpret_cast<const bf16x8*>(s.pw.w3f) + lane;
-    // Staging: 10 x 48 positions x 4 pieces, 15 per thread, all in flight.
-    constexpr int NP = NFP / 128;
-    static_assert(NFP % 128 == 0, "whole staging passes");
-    bf16x8 v[NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        const int i = tid + 128 * j, piece = i & 3, pos = i >> 2;
-        const int rr = pos / F1_COLS, cc = pos - rr * F1_COLS;
-        // staged row rr = 2 a + dy is position row cy0 + 4 a + dy (o2map row)
-        const int y = min(cy0 + 4 * (rr >> 1) + (rr & 1), H2m - 1);
-        const int x = min(cx0 + cc, W2m - 1);
-        v[j] = *(const bf16x8*)(s.o2map + ((int64_t)y * W2m + x) * net::C2 + 8 * piece);
-    }
-    // A fragments of gathered position k: K16 steps 2k, 2k + 1, tiles 0..3
-    auto load_a = [&](int k, bf16x8 (&av)[2][4]) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) av[h][t] = w3f[((2 * k + h) * 4 + t) * 64];
-    };
-    bf16x8 a_cur[2][4], a_nxt[2][4];
-    load_a(k0, a_cur);
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        const int i = tid + 128 * j, piece = i & 3, pos = i >> 2;
-        const int rr = pos / F1_COLS, cc = pos - rr * F1_COLS;
-        fp[(rr * 4 + piece) * F1_COLS + cc] = v[j];
-    }
-    __syncthreads();
-    f32x16 acc[2][4];
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int j = 0; j < 16; ++j) acc[m][t][j] = 0.f;
-    auto step = [&](int k, const bf16x8 (&av)[2][4]) {
-        const int a5 = k / net::P2, b5 = k - a5 * net::P2;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            bf16x8 bv[2];
-#pragma unroll
-            for (int m = 0; m < 2; ++m)       // cell (dy, dx) = (m, lc): channels 16 h + 8 lh ..
-                bv[m] = fp[((2 * a5 + m) * 4 + 2 * h + lh) * F1_COLS + lc + 4 * b5];
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-                    acc[m][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[h][t], bv[m], acc[m][t], 0, 0, 0);
-        }
-    };
-    // Two steps per iteration over two fragment buffers (no register copies).
-    int k = k0;
-    for (; k + 1 < k1; k += 2) {
-        load_a(k + 1, a_nxt);
-        step(k, a_cur);
-        if (k + 2 < k1) load_a(k + 2, a_cur);
-        step(k + 1, a_nxt);
-    }
-    if (k < k1) step(k, a_cur);
-    __syncthreads();                          // every wave is done with the staged vectors
-    if (wave == 1) {
-#pragma unroll
-        for (int m = 0; m < 2; ++m)
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    part[((m * 4 + t) * 4 + q) * 64 + lane] =
-                        f32x4{acc[m][t][4 * q], acc[m][t][4 * q + 1], acc[m][t][4 * q + 2],
-                              acc[m][t][4 * q + 3]};
-    }
-    __syncthreads();
-    if (wave == 1) return;
-    static_assert(net::OFF_B3 % 4 == 0, "fc1 biases are read as float4");
-    typedef _Float16 f16x4v __attribute__((ext_vector_type(4)));
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            // neurons 32 t + 8 q + 4 lh + (0..3)
-            const int n = 32 * t + 8 * q + 4 * lh;
-            const float4 bb = *(const float4*)(s.theta + net::OFF_B3 + n);
-#pragma unroll
-            for (int m = 0; m < 2; ++m) {
-                const int cy = cy0 + m, cx = cx0 + lc;
-                const f32x4 pv = part[((m * 4 + t) * 4 + q) * 64 + lane];
-                const f16x4v o = {(_Float16)(acc[m][t][4 * q] + pv[0] + bb.x),
-                                  (_Float16)(acc[m][t][4 * q + 1] + pv[1] + bb.y),
-                                  (_Float16)(acc[m][t][4 * q + 2] + pv[2] + bb.z),
-                                  (_Float16)(acc[m][t][4 * q + 3] + pv[3] + bb.w)};
-                // T is [neuron chunk of 8][cell][8]: chunk 4 t + q, half lh
-                if (cy < s.H && cx < s.W)
-                    *reinterpret_cast<f16x4v*>(s.T + ((int64_t)(4 * t + q) * cells + cy * s.W + cx) * 8 +
-                                               4 * lh) = o;
-            }
-        }
-}
-
-// Head of every state (cell, yaw unit): a wave owns 32 cells and loops over
-// a range of yaw units, keeping fc2's weights, its biases and the cells' fc1
-// values (without the yaw term) in registers.  Activations are fp16 (the
-// weights are the network's bf16 values, held exactly in fp16), so fc1's yaw
-// term and ReLU run as packed fp16 adds and maxima, two neurons per
-// instruction, and fc2's ReLU converts two neurons per instruction.  Both
-// layers run on the 32x32x16 MFMA (measured 1.8 times the throughput of
-// 16x16x32 on this device), transposed, neurons x states:
+// in L2).  Wave w computes neurons 32 w .. 32 w + 31 of both cell rows over
+// the whole reduction, streaming its rows of W3 from the fragment-ordered copy
+// (1 KB contiguous per fragment, A_DEPTH fragments in flight), so no partial
+// sums have to be added across waves.  T goes to LDS as fp16,
+// [cell row][neuron / 8][column][neuron % 8].
+//
+// Head of every state (cell, yaw unit): wave w takes cell row w % 2 and half
+// of the yaw units, keeping fc2's weights, its biases and its cells' fc1
+// values in registers.  Activations are fp16 (the weights are the network's
+// bf16 values, held exactly in fp16), so fc1's yaw term and ReLU run as packed
+// fp16 adds and maxima, two neurons per instruction, and fc2's ReLU converts
+// two neurons per instruction.  Both layers run on the 32x32x16 MFMA
+// (measured 1.8 times the throughput of 16x16x32 on this device), transposed,
+// neurons x states:
 //   fc2: D2 (64 x 32) = W4 (64 x 128) . h1^T + b4,   h1 = ReLU(T + Y[u])
 //   fc3: D3 (32 x 32, rows 0..3 used) = W5' (32 x 64) . h2^T,  h2 = ReLU(D2)
-// Lane l = (c, h) = (l % 32, l / 32) supplies A's row and B's column c at
-// reduction indices 8h .. 8h+7 of each 16-wide K step, and receives D's
-// column c, rows 8q + 4h + j (q, j = 0..3).  So lane (c, h) holds, for
-// state c, fc2's neurons 32t + 8q + 4h + j; fc3's K step kk takes the eight
-// of them with t = kk / 2 and q = 2 (kk % 2) + {0, 1} as its indices 8h .. 8h+7,
-// and W5' is gathered in the same order, which leaves the sum unchanged and
-// needs no trip through LDS.  fc2's bias enters as the accumulator of its
-// first product.  Stores go to 32 consecutive cells of one yaw plane.
+// In the 32x32x16 MFMA lane l = (c, h) = (l % 32, l / 32) supplies A's row
+// and B's column c at reduction indices 8h .. 8h+7 of each 16-wide K step,
+// and receives D's column c, rows 8q + 4h + j (q, j = 0..3).  So lane (c, h)
+// holds, for state c, fc2's neurons 32t + 8q + 4h + j; fc3's K step kk takes
+// the eight of them with t = kk / 2 and q = 2 (kk % 2) + {0, 1} as its indices
+// 8h .. 8h+7, and W5' is gathered in the same order, which leaves the sum
+// unchanged and needs no trip through LDS.  fc2's bias enters as the
+// accumulator of its first product.  Stores go to 32 consecutive cells of one
+// yaw plane.
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
@@ -429,34 +309,66 @@ __device__ __forceinline__ f16x8 cat(f16x2 a, f16x2 b, f16x2 c, f16x2 d) {
     return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
-constexpr int HEAD_CELLS = 32;               // cells per wave
+constexpr int NT_Y = 2, NT_X = 32;                    // cells per tile
+constexpr int G_ROWS = NT_Y * net::P2;                // 10 staged position rows
+constexpr int G_COLS = NT_X + 4 * (net::P2 - 1);      // 48 staged position columns
+constexpr int G_ENTRIES = G_ROWS * G_COLS * 4;        // 16-byte entries, 8 channels each
+constexpr int T_ENTRIES = NT_Y * (net::H1 / 8) * NT_X;
+constexpr int W4_ENTRIES = (net::H2 / 32) * (net::H1 / 16) * 64;
+constexpr int REGION_A = G_ENTRIES > T_ENTRIES + W4_ENTRIES ? G_ENTRIES : T_ENTRIES + W4_ENTRIES;
+constexpr int KSTEPS = net::F / 16;                   // fc1's 16-wide reduction steps
+constexpr int A_DEPTH = 8;
+static_assert(net::H1 == 4 * 32 && net::H2 == 2 * 32, "one neuron tile of fc1 per wave, two of fc2");
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void head_kernel(const SurArgs s, const AssessArgs a) {
-    // LDS: fc2's weights as fp16 MFMA fragments ([t][kk][lane]), shared by
-    // the four waves, then the yaw term [U][16] (eight fp16 neurons each).
+inline size_t net_lds_bytes(int U) { return (size_t)(REGION_A + U * (net::H1 / 8)) * 16; }
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void net_kernel(const SurArgs s, const AssessArgs a) {
+    // LDS (16-byte entries): region A holds the staged conv2 vectors
+    // [row][piece of 8 channels][column] during fc1, then T [cell row][neuron
+    // chunk][column] and fc2's weights as fp16 MFMA fragments [t][kk][lane];
+    // after it, the yaw term [U][16] (eight fp16 neurons each).
     extern __shared__ f16x8 lds[];
-    f16x8* w4s = lds;
-    f16x8* ys = lds + 16 * 64;
+    bf16x8* gs = reinterpret_cast<bf16x8*>(lds);
+    f16x8* ts = lds;
+    f16x8* w4s = lds + T_ENTRIES;
+    f16x8* ys = lds + REGION_A;
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int cl = lane & 31, lh = lane >> 5;
-    const int cells = s.H * s.W;
-    const int c0 = (blockIdx.x * 4 + wave) * HEAD_CELLS;
-    const int u0 = blockIdx.y * s.upw, u1 = min(s.U, u0 + s.upw);
-    const bool real = c0 + cl < cells;
-    const int cell = real ? c0 + cl : cells - 1;
-    // Every global load of the workgroup is issued here, before the first
-    // wait: fc2's weights and the yaw term for LDS, then the wave's own
-    // operands (its cells' fc1 values, fc2's biases, fc3's weights and
-    // biases, the nine heights of each cell's reference and its known
-    // fraction).
+    const int W2m = s.W + 16, H2m = s.H + 16, cells = s.H * s.W;
+    const int tx = (s.W + NT_X - 1) / NT_X;
+    const int cy0 = (blockIdx.x / tx) * NT_Y, cx0 = (blockIdx.x % tx) * NT_X;
+
+    // Every global load of the workgroup is issued before the first wait:
+    // the gathered conv2 vectors, the first A_DEPTH fragments of W3, fc1's
+    // biases, fc2's weights, the yaw term's inputs and the head's per-cell
+    // operands.
+    constexpr int NG = (G_ENTRIES + 255) / 256;
+    bf16x8 g[NG];
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+        const int i = min(tid + 256 * j, G_ENTRIES - 1), piece = i & 3, pos = i >> 2;
+        const int rr = pos / G_COLS, cc = pos - rr * G_COLS;
+        // staged row rr = 2 a + dy is position row cy0 + 4 a + dy (o2map row)
+        const int y = min(cy0 + 4 * (rr >> 1) + (rr & 1), H2m - 1);
+        const int x = min(cx0 + cc, W2m - 1);
+        g[j] = *(const bf16x8*)(s.o2map + ((int64_t)y * W2m + x) * net::C2 + 8 * piece);
+    }
+    // fragment (K step st, neuron tile t) of W3 is w3f[(st * 4 + t) * 64 + lane]
+    const bf16x8* w3f = reinterpret_cast<const bf16x8*>(s.pw.w3f) + wave * 64 + lane;
+    bf16x8 ar[A_DEPTH];
+#pragma unroll
+    for (int st = 0; st < A_DEPTH; ++st) ar[st] = w3f[st * 256];
+    static_assert(net::OFF_B3 % 4 == 0, "fc1 biases are read as float4");
+    float4 b3[4];                            // [q]: b3[32 wave + 8q + 4lh + (0..3)]
+#pragma unroll
+    for (int q = 0; q < 4; ++q) b3[q] = *(const float4*)(s.theta + net::OFF_B3 + 32 * wave + 8 * q + 4 * lh);
     f16x8 wst[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int f = tid + 256 * j;                   // fragment (t, kk, lane')
         const int t = f >> 9, kk = (f >> 6) & 7, ln = f & 63;
-        wst[j] = *(const f16x8*)(s.pw.w4h + (32 * t + (ln & 31)) * net::H1 + 16 * kk +
-                                 8 * (ln >> 5));
+        wst[j] = *(const f16x8*)(s.pw.w4h + (32 * t + (ln & 31)) * net::H1 + 16 * kk + 8 * (ln >> 5));
     }
     // fc1's yaw term Y[u][n] = Wy[n] . (sin, cos)(theta_u), eight neurons per
     // entry, entries tid and tid + 256 (more than 32 yaw units: see below).
@@ -472,10 +384,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void h
         for (int q = 0; q < 4; ++q) wy[j][q] = wp[q];
     }
     static_assert(net::OFF_WY % 4 == 0, "yaw weights read as float4");
-    f16x8 tv[8];                             // [kk]: T[cell][16kk + 8lh + e] (chunk 2kk + lh)
+    // The head's cell: row cy0 + wave % 2, column cx0 + cl.
+    const int hy = cy0 + (wave & 1), hx = cx0 + cl;
+    const bool real = hy < s.H && hx < s.W;
+    const int cy = min(hy, s.H - 1), cx = min(hx, s.W - 1);
+    const int cell = cy * s.W + cx;
+    float hc;
+    const bool has_ref = ref_height(s, cy, cx, &hc);
+    const float kf = s.known[cell];
+
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk)
-        tv[kk] = *(const f16x8*)(s.T + ((int64_t)(2 * kk + lh) * cells + cell) * 8);
+    for (int j = 0; j < NG; ++j) {
+        const int i = tid + 256 * j, piece = i & 3, pos = i >> 2;
+        const int rr = pos / G_COLS, cc = pos - rr * G_COLS;
+        if (i < G_ENTRIES) gs[(rr * 4 + piece) * G_COLS + cc] = g[j];
+    }
+    __syncthreads();
+
+    f32x16 acc1[2];                          // [cell row m]: neurons 32 wave + 8q + 4lh + j at 4q + j
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc1[m][j] = 0.f;
+#pragma unroll
+    for (int st = 0; st < KSTEPS; ++st) {
+        const bf16x8 av = ar[st % A_DEPTH];
+        if (st + A_DEPTH < KSTEPS) ar[st % A_DEPTH] = w3f[(st + A_DEPTH) * 256];
+        // K step st covers channels 16 h .. 16 h + 15 of gathered position k
+        const int k = st >> 1, h = st & 1, a5 = k / net::P2, b5 = k - a5 * net::P2;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {         // cell (m, cl): channels 16 h + 8 lh ..
+            const bf16x8 bv = gs[((2 * a5 + m) * 4 + 2 * h + lh) * G_COLS + cl + 4 * b5];
+            acc1[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc1[m], 0, 0, 0);
+        }
+    }
+    // fc2's biases and fc3's weights and biases, for the head
     f32x16 b4v[2];                           // [t]: b4[32t + 8q + 4lh + j] at 4q + j
     static_assert(net::OFF_B4 % 4 == 0, "fc2 biases are read as float4");
 #pragma unroll
@@ -501,11 +444,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void h
     }
     float b5[4];
     for (int j = 0; j < 4; ++j) b5[j] = s.theta[net::OFF_B5 + j];
-    // Per-cell part of the fallback rule and the plane height offset.
-    const int cy = cell / s.W, cx = cell - cy * s.W;
-    float hc;
-    const bool has_ref = ref_height(s, cy, cx, &hc);
-    const bool out_of_dist = !has_ref || s.known[cell] < s.min_known;
+    __syncthreads();                          // every wave is done with the staged vectors
+    // T: neurons 32 wave + 8q + 4lh + (0..3) of cell (m, cl) are chunk
+    // 4 wave + q, half lh
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const f16x4 o = {(_Float16)(acc1[m][4 * q] + b3[q].x), (_Float16)(acc1[m][4 * q + 1] + b3[q].y),
+                             (_Float16)(acc1[m][4 * q + 2] + b3[q].z), (_Float16)(acc1[m][4 * q + 3] + b3[q].w)};
+            *reinterpret_cast<f16x4*>(reinterpret_cast<_Float16*>(ts + (m * 16 + 4 * wave + q) * NT_X + cl) +
+                                      4 * lh) = o;
+        }
 #pragma unroll
     for (int j = 0; j < 4; ++j) w4s[tid + 256 * j] = wst[j];
     // (Wy is [n][2]: float4 q holds neurons 2q and 2q + 1 of the entry.)
@@ -529,12 +479,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void h
         ys[i] = yaw_entry(s.yaw_sc[i >> 4], w);
     }
     __syncthreads();
-    if (c0 >= cells) return;
+    if (hy >= s.H) return;                    // a tile's second row past the map's edge
+    const int mh = wave & 1;
+    f16x8 tv[8];                             // [kk]: T[cell][16kk + 8lh + e] (chunk 2kk + lh)
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) tv[kk] = ts[(mh * 16 + 2 * kk + lh) * NT_X + cl];
     f16x8 w4[2][8];                          // [t][kk]: W4[32t + cl][16kk + 8lh + e]
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) w4[t][kk] = w4s[(t * 8 + kk) * 64 + lane];
+    const bool out_of_dist = !has_ref || kf < s.min_known;
+    const int uh = (s.U + 1) >> 1;
+    const int u0 = wave < 2 ? 0 : uh, u1 = wave < 2 ? uh : s.U;
     // Every load above is complete before the loop: a wait inside it would
     // also wait for the previous unit's stores.
     __builtin_amdgcn_s_waitcnt(0);
@@ -588,16 +545,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void h
 }  // namespace
 
 hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, hipStream_t stream) {
-    const int64_t cells = (int64_t)s.H * s.W;
-    auto blocks = [](int64_t n, int b) { return (unsigned)((n + b - 1) / b); };
     const int conv_tiles = ((s.H + 16 + TT - 1) / TT) * ((s.W + 16 + TT - 1) / TT);
     const int known_tiles = ((s.H + 15) / 16) * ((s.W + 15) / 16);
     hipLaunchKernelGGL(trunk_kernel, dim3(conv_tiles + known_tiles), dim3(256), 0, stream, s);
-    hipLaunchKernelGGL(fc1_kernel, dim3(((s.H + F1_TY - 1) / F1_TY) * ((s.W + F1_TX - 1) / F1_TX)),
-                       dim3(128), 0, stream, s);
-    hipLaunchKernelGGL(head_kernel, dim3(blocks(cells, 4 * HEAD_CELLS), (s.U + s.upw - 1) / s.upw),
-                       dim3(256),
-                       (size_t)(net::H2 * net::H1 + s.U * net::H1) * sizeof(net::f16), stream, s, a);
+    hipLaunchKernelGGL(net_kernel, dim3(((s.H + NT_Y - 1) / NT_Y) * ((s.W + NT_X - 1) / NT_X)), dim3(256),
+                       net_lds_bytes(s.U), stream, s, a);
     return hipGetLastError();
 }
 

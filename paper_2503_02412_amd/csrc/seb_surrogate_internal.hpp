@@ -17,7 +17,6 @@ struct SurArgs {
     int W, H;
     float inv_res;
     int K, U, mirror;            // yaw bins, units evaluated (K/2 if mirrored), mirror offset
-    int upw;                     // yaw units per wave of the head kernel
     int pitch;                   // LDS pitch of the fallback kernel's table offsets
     // network
     const float* theta;          // float32 parameters (biases and Wy are read from here)
@@ -25,8 +24,6 @@ struct SurArgs {
     // workspace
     const float2* yaw_sc;        // [U]                 (sin, cos) of yaw unit u's angle
     net::bf16* o2map;            // [(H+16)(W+16)][32]  conv2 at positions -12 .. H+3
-    net::f16* T;                 // [16][H*W][8]        fc1 without the yaw term, neuron n
-                                 //                     of cell c at [n / 8][c][n % 8]
     float* known;                // [H*W]               known fraction of the 24 x 24 window
     uint8_t* need;               // [U][H*W]            1 = state falls back to the plain method
     int32_t* n_fallback;         // optional device counter of fallen-back states
@@ -38,8 +35,8 @@ struct SurArgs {
 };
 
 // Network part: fills `a`'s outputs for the states it answers and s.need for
-// the others.  The caller then runs the tiled assessment kernel with
-// a.need = s.need over the whole map.
+// the others.  The caller then re-assesses the flagged states with the plain
+// method (launch_assess_flagged).
 hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, hipStream_t stream);
 
 }  // namespace sur
