@@ -756,6 +756,7 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
     const bool ok =
         al((void**)&w.yaw_sc, (size_t)U * sizeof(float2)) &&
         al((void**)&w.o2map, (size_t)(H + 16) * (W + 16) * seb::net::C2 * 2) &&
+        al((void**)&w.ymap, (size_t)U * seb::net::H1 * 2) &&
         al((void**)&w.known, (size_t)cells * 4) && al((void**)&w.need, (size_t)U * cells) &&
         al((void**)&w.work_cells, (size_t)max_items * 64 * 2) &&
         al((void**)&w.block_count, (size_t)n_blocks * sizeof(int32_t)) &&

@@ -100,7 +100,8 @@ __device__ __forceinline__ bool ref_height(const SurArgs& s, int cy, int cx, flo
 // Known-fraction tiles (the remaining workgroups): the fraction of known
 // cells in each cell's 24 x 24 window [c - 12, c + 12), for 16 x 16 cells,
 // from an LDS tile of known flags (row sums, then column sums).  The first of
-// them also clears the fallback counter.
+// them also clears the fallback counter and computes fc1's yaw term for every
+// yaw unit.
 constexpr int TT = 16;                       // conv2 positions per tile side
 constexpr int T1 = TT + 4;                   // conv1 positions per tile side
 constexpr int TC = T1 + 4;                   // input cells per side (window 4, slope +1 -> 25 heights)
@@ -124,7 +125,26 @@ __global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
         const int b = blockIdx.x - nconv;
         const int kx = (s.W + T - 1) / T;
         const int x0 = (b % kx) * T, y0 = (b / kx) * T;
-        if (b == 0 && tid == 0 && s.n_fallback) *s.n_fallback = 0;
+        if (b == 0) {
+            if (tid == 0 && s.n_fallback) *s.n_fallback = 0;
+            // fc1's yaw term Y[u][n] = Wy[n] . (sin, cos)(theta_u), eight fp16
+            // neurons per entry (Wy is [n][2]: float4 q of an entry holds
+            // neurons 2q and 2q + 1)
+            static_assert(net::OFF_WY % 4 == 0, "yaw weights read as float4");
+            for (int i = tid; i < s.U * (net::H1 / 8); i += 256) {
+                const float2 sc = s.yaw_sc[i >> 4];
+                const float4* wp = (const float4*)(s.theta + net::OFF_WY + 16 * (i & 15));
+                typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+                h8 v;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float4 w = wp[q];
+                    v[2 * q] = (_Float16)(sc.x * w.x + sc.y * w.y);
+                    v[2 * q + 1] = (_Float16)(sc.x * w.z + sc.y * w.w);
+                }
+                reinterpret_cast<h8*>(s.ymap)[i] = v;
+            }
+        }
         // six loads per thread in flight, from clamped positions, masked afterwards
         constexpr int NB = (SPAN * SPAN + 255) / 256;
         float hv[NB];
@@ -260,6 +280,7 @@ __global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
 }
 
 // fc1, fc2 and fc3 of every state in one kernel: fc1's output stays in LDS.
+// fc1's yaw term comes precomputed per yaw unit (trunk_kernel).
 // A workgroup (four waves) owns a tile of 2 x 32 cells.
 //
 // fc1 without the yaw term, per cell: T[n] = b3[n] + W3[n] . (conv2 at the
@@ -315,14 +336,16 @@ constexpr int G_COLS = NT_X + 4 * (net::P2 - 1);      // 48 staged position colu
 constexpr int G_ENTRIES = G_ROWS * G_COLS * 4;        // 16-byte entries, 8 channels each
 constexpr int T_ENTRIES = NT_Y * (net::H1 / 8) * NT_X;
 constexpr int W4_ENTRIES = (net::H2 / 32) * (net::H1 / 16) * 64;
-constexpr int REGION_A = G_ENTRIES > T_ENTRIES + W4_ENTRIES ? G_ENTRIES : T_ENTRIES + W4_ENTRIES;
+constexpr int W5_ENTRIES = (net::H2 / 16) * 64;
+constexpr int HEAD_ENTRIES = T_ENTRIES + W4_ENTRIES + W5_ENTRIES;
+constexpr int REGION_A = G_ENTRIES > HEAD_ENTRIES ? G_ENTRIES : HEAD_ENTRIES;
 constexpr int KSTEPS = net::F / 16;                   // fc1's 16-wide reduction steps
 constexpr int A_DEPTH = 8;
 static_assert(net::H1 == 4 * 32 && net::H2 == 2 * 32, "one neuron tile of fc1 per wave, two of fc2");
 
 inline size_t net_lds_bytes(int U) { return (size_t)(REGION_A + U * (net::H1 / 8)) * 16; }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void net_kernel(const SurArgs s, const AssessArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void net_kernel(const SurArgs s, const AssessArgs a) {
     // LDS (16-byte entries): region A holds the staged conv2 vectors
     // [row][piece of 8 channels][column] during fc1, then T [cell row][neuron
     // chunk][column] and fc2's weights as fp16 MFMA fragments [t][kk][lane];
@@ -331,6 +354,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
     bf16x8* gs = reinterpret_cast<bf16x8*>(lds);
     f16x8* ts = lds;
     f16x8* w4s = lds + T_ENTRIES;
+    f16x8* w5s = w4s + W4_ENTRIES;
     f16x8* ys = lds + REGION_A;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
@@ -341,8 +365,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
 
     // Every global load of the workgroup is issued before the first wait:
     // the gathered conv2 vectors, the first A_DEPTH fragments of W3, fc1's
-    // biases, fc2's weights, the yaw term's inputs and the head's per-cell
-    // operands.
+    // biases, fc2's weights, the yaw term and the head's per-cell operands.
     constexpr int NG = (G_ENTRIES + 255) / 256;
     bf16x8 g[NG];
 #pragma unroll
@@ -370,20 +393,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
         const int t = f >> 9, kk = (f >> 6) & 7, ln = f & 63;
         wst[j] = *(const f16x8*)(s.pw.w4h + (32 * t + (ln & 31)) * net::H1 + 16 * kk + 8 * (ln >> 5));
     }
-    // fc1's yaw term Y[u][n] = Wy[n] . (sin, cos)(theta_u), eight neurons per
-    // entry, entries tid and tid + 256 (more than 32 yaw units: see below).
+    // fc1's yaw term [U][16] (eight fp16 neurons per entry), entries tid and
+    // tid + 256 (more than 32 yaw units: see below)
     const int ny = s.U * (net::H1 / 8);
-    float2 ysc[2];
-    float4 wy[2][4];
+    const f16x8* ymap = reinterpret_cast<const f16x8*>(s.ymap);
+    f16x8 yv[2];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int i = min(tid + 256 * j, ny - 1);
-        ysc[j] = s.yaw_sc[i >> 4];
-        const float4* wp = (const float4*)(s.theta + net::OFF_WY + 16 * (i & 15));
-#pragma unroll
-        for (int q = 0; q < 4; ++q) wy[j][q] = wp[q];
-    }
-    static_assert(net::OFF_WY % 4 == 0, "yaw weights read as float4");
+    for (int j = 0; j < 2; ++j) yv[j] = ymap[min(tid + 256 * j, ny - 1)];
     // The head's cell: row cy0 + wave % 2, column cx0 + cl.
     const int hy = cy0 + (wave & 1), hx = cx0 + cl;
     const bool real = hy < s.H && hx < s.W;
@@ -419,29 +435,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
         }
     }
     // fc2's biases and fc3's weights and biases, for the head
-    f32x16 b4v[2];                           // [t]: b4[32t + 8q + 4lh + j] at 4q + j
-    static_assert(net::OFF_B4 % 4 == 0, "fc2 biases are read as float4");
+    // fc2's bias enters as one more product, D2 += B4 . ONES, with K index 0
+    // and 1 of lane row c carrying b4's fp16 high and low parts (their sum is
+    // b4 to 2^-22) and the other indices zero: b4's 32 per-lane values would
+    // otherwise take 32 registers.
+    f16x8 w4b[2];                            // [t]: A fragment, row 32t + cl
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float4 b = *(const float4*)(s.theta + net::OFF_B4 + 32 * t + 8 * q + 4 * lh);
-            b4v[t][4 * q] = b.x;
-            b4v[t][4 * q + 1] = b.y;
-            b4v[t][4 * q + 2] = b.z;
-            b4v[t][4 * q + 3] = b.w;
-        }
-    f16x8 w5[4];                             // [kk]: W5[cl][neuron(kk, lh, e)], rows >= 4 zero
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-        // neurons 32 (kk / 2) + 8 (2 (kk % 2) + e / 4) + 4 lh + e % 4
-        const int nb = 32 * (kk >> 1) + 16 * (kk & 1) + 4 * lh;
-        const int row = min(cl, 3);
+    for (int t = 0; t < 2; ++t) {
+        const float b = s.theta[net::OFF_B4 + 32 * t + cl];
+        const _Float16 hi = (_Float16)b, lo = (_Float16)(b - (float)hi);
+        w4b[t] = lh == 0 ? f16x8{hi, lo, 0, 0, 0, 0, 0, 0} : f16x8{};
+    }
+    const f16x8 ones = lh == 0 ? f16x8{1, 1, 0, 0, 0, 0, 0, 0} : f16x8{};
+    // fc3's A fragment (kk, lane') = W5[c'][neuron(kk, h', e)] for lane'
+    // (c', h'), rows c' >= 4 zero; this thread's fragment is (tid / 64, tid % 64)
+    f16x8 w5f;
+    {
+        const int kk = tid >> 6, c5 = tid & 31, h5 = (tid >> 5) & 1;
+        // neurons 32 (kk / 2) + 8 (2 (kk % 2) + e / 4) + 4 h' + e % 4
+        const int nb = 32 * (kk >> 1) + 16 * (kk & 1) + 4 * h5;
+        const int row = min(c5, 3);
         const f16x4 lo = *(const f16x4*)(s.pw.w5h + row * net::H2 + nb);
         const f16x4 hi = *(const f16x4*)(s.pw.w5h + row * net::H2 + nb + 8);
         const f16x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
-        w5[kk] = cl < 4 ? v : f16x8{};
+        w5f = c5 < 4 ? v : f16x8{};
     }
+    static_assert(W5_ENTRIES == 256, "one fc3 fragment per thread");
     float b5[4];
     for (int j = 0; j < 4; ++j) b5[j] = s.theta[net::OFF_B5 + j];
     __syncthreads();                          // every wave is done with the staged vectors
@@ -458,32 +477,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
         }
 #pragma unroll
     for (int j = 0; j < 4; ++j) w4s[tid + 256 * j] = wst[j];
-    // (Wy is [n][2]: float4 q holds neurons 2q and 2q + 1 of the entry.)
-    auto yaw_entry = [](float2 sc, const float4 (&w)[4]) {
-        f16x8 v;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            v[2 * q] = (_Float16)(sc.x * w[q].x + sc.y * w[q].y);
-            v[2 * q + 1] = (_Float16)(sc.x * w[q].z + sc.y * w[q].w);
-        }
-        return v;
-    };
+    w5s[tid] = w5f;
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int i = tid + 256 * j;
-        if (i < ny) ys[i] = yaw_entry(ysc[j], wy[j]);
+        if (i < ny) ys[i] = yv[j];
     }
-    for (int i = tid + 512; i < ny; i += 256) {          // more than 32 yaw units
-        const float4* wp = (const float4*)(s.theta + net::OFF_WY + 16 * (i & 15));
-        const float4 w[4] = {wp[0], wp[1], wp[2], wp[3]};
-        ys[i] = yaw_entry(s.yaw_sc[i >> 4], w);
-    }
+    for (int i = tid + 512; i < ny; i += 256) ys[i] = ymap[i];     // more than 32 yaw units
     __syncthreads();
     if (hy >= s.H) return;                    // a tile's second row past the map's edge
     const int mh = wave & 1;
-    f16x8 tv[8];                             // [kk]: T[cell][16kk + 8lh + e] (chunk 2kk + lh)
-#pragma unroll
-    for (int kk = 0; kk < 8; ++kk) tv[kk] = ts[(mh * 16 + 2 * kk + lh) * NT_X + cl];
+    // T[cell][16kk + 8lh + e] (chunk 2kk + lh) is tc[(2kk + lh) * NT_X]
+    const f16x8* tc = ts + mh * 16 * NT_X + cl;
     f16x8 w4[2][8];                          // [t][kk]: W4[32t + cl][16kk + 8lh + e]
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -499,14 +504,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
     const f16x8 zero8 = {};
     const int64_t plane = (int64_t)cells;
     for (int u = u0; u < u1; ++u) {
+        // zero (u < 2^30), but not known to be: it keeps the per-unit LDS
+        // reads of T and W5 inside the loop instead of in registers
+        const int zo = u & (1 << 30);
         f32x16 acc[2];
 #pragma unroll
+        for (int t = 0; t < 2; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w4b[t], ones, f32x16{}, 0, 0, 0);
+#pragma unroll
         for (int kk = 0; kk < 8; ++kk) {
-            const f16x8 h = __builtin_elementwise_max(tv[kk] + ys[u * 16 + 2 * kk + lh], zero8);
+            const f16x8 h = __builtin_elementwise_max(tc[(2 * kk + lh) * NT_X + zo] + ys[u * 16 + 2 * kk + lh], zero8);
 #pragma unroll
             for (int t = 0; t < 2; ++t)
-                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w4[t][kk], h,
-                                                                 kk == 0 ? b4v[t] : acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(w4[t][kk], h, acc[t], 0, 0, 0);
         }
         f32x16 y3 = {};
 #pragma unroll
@@ -517,7 +526,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void n
                 cat(pack_rtz(p[q0], p[q0 + 1]), pack_rtz(p[q0 + 2], p[q0 + 3]),
                     pack_rtz(p[q0 + 4], p[q0 + 5]), pack_rtz(p[q0 + 6], p[q0 + 7])),
                 zero8);
-            y3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(w5[kk], h2, y3, 0, 0, 0);
+            y3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(w5s[kk * 64 + lane + zo], h2, y3, 0, 0, 0);
         }
         // Lanes with lh = 0 hold rows 0..3, the four outputs of state (cell, u).
         if (lh == 0 && real) {

@@ -24,6 +24,7 @@ struct SurArgs {
     // workspace
     const float2* yaw_sc;        // [U]                 (sin, cos) of yaw unit u's angle
     net::bf16* o2map;            // [(H+16)(W+16)][32]  conv2 at positions -12 .. H+3
+    net::f16* ymap;              // [U][128]            fc1's yaw term Wy . (sin, cos) per unit
     float* known;                // [H*W]               known fraction of the 24 x 24 window
     uint8_t* need;               // [U][H*W]            1 = state falls back to the plain method
     int32_t* n_fallback;         // optional device counter of fallen-back states
