@@ -110,89 +110,26 @@ void assess_kernel(const AssessArgs a) {
     }
 }
 
-// Re-assessment of the states flagged in a.need only, in two kernels.
+// Re-assessment of the listed (flagged) states only.
 //
-// compact_kernel: the map is cut into TF x TF blocks.  A wave per (block,
-// unit) lists the block's flagged cells for that yaw unit in 16 x 4
-// micro-block order (so a full item has the tiled kernel's lane pattern) into
-// the block's own slots, with the count and the bounding box of every 64-cell
-// item.
-//
-// flagged_kernel: one workgroup per possible item, item-major (workgroup
-// k * slots + slot takes item k of slot (unit, block)), so the first items of
-// every block come first and workgroups past a block's count return at once.
-// Its first workgroups also add the blocks' counts to the optional state
-// counter, 2048 blocks per workgroup and one atomic add per wave.  For its item, the workgroup
-// stages the block's heights, and each of its four waves accumulates a
-// quarter of the footprint rows for the same 64 states; wave 0 adds the four
-// partial moment sets and finishes the states.  Four short waves per 64
-// states keep many more SIMDs busy than one long wave would, for the few
-// thousand states a map sends back.  A state whose own cell is unknown takes,
-// in each wave, the first valid sample of that wave's rows as reference; the
-// partial sums are shifted exactly onto the first wave's reference (the first
-// valid sample in table order):
+// flagged_kernel: one workgroup per possible item of 64 listed states,
+// item-major (workgroup k * slots + slot takes item k of slot (unit, block)),
+// so the first items of every block come first and workgroups past a block's
+// count return at once.  A slot's states are its rows' lists in row order;
+// the workgroup finds its 64 from the slot's row counts (a prefix sum over the
+// lanes and a binary search), takes their bounding box (wave reductions) and
+// stages the box plus the footprint halo.  Its first workgroups also add the
+// listed states to the optional state counter, 2048 words of four row counts
+// per workgroup and one atomic add per wave.  Each of its four waves
+// accumulates a quarter of the footprint rows for the same 64 states; wave 0
+// adds the four partial moment sets and finishes the states.  Four short
+// waves per 64 states keep many more SIMDs busy than one long wave would, for
+// the few thousand states a map sends back.  A state whose own cell is
+// unknown takes, in each wave, the first valid sample of that wave's rows as
+// reference; the partial sums are shifted exactly onto the first wave's
+// reference (the first valid sample in table order):
 //   S(z - r) = S(z - r_w) + N_w d,  S q(z - r) = S q(z - r_w) + d S q,
 //   S (z - r)^2 = S (z - r_w)^2 + 2 d S(z - r_w) + N_w d^2,  d = r_w - r.
-template <int TF>
-__global__ __launch_bounds__(64) void compact_kernel(const AssessArgs a) {
-    constexpr int mbx = TF / 16;
-    constexpr int steps = TF * TF / 64;      // 16 (TF = 32) or 4 (TF = 16)
-    __shared__ uint16_t list[TF * TF];
-    const int lane = threadIdx.x;
-    const int blk = blockIdx.x, u = blockIdx.y;
-    const int tiles_x = (a.W + TF - 1) / TF;
-    const int64_t slot = (int64_t)u * gridDim.x + blk;
-    const int sx0 = (blk % tiles_x) * TF, sy0 = (blk / tiles_x) * TF;
-    const int64_t plane = (int64_t)a.W * a.H;
-    // Step k covers micro-block k: ordinal 64 k + lane.  Unrolled, with
-    // clamped unconditional loads, so the mask bytes of all steps are
-    // requested at once (a guarded load would wait for its own result).
-    uint8_t nb[steps];
-    uint32_t inside = 0u;
-#pragma unroll
-    for (int k = 0; k < steps; ++k) {
-        const int ly = (k / mbx) * 4 + (lane >> 4), lx = (k % mbx) * 16 + (lane & 15);
-        const int ix = sx0 + lx, iy = sy0 + ly;
-        inside |= (uint32_t)(ix < a.W && iy < a.H) << k;
-        const int cx = min(ix, a.W - 1), cy = min(iy, a.H - 1);
-        nb[k] = a.need[(int64_t)u * plane + (int64_t)wrap(cy + a.ry, a.H) * a.W + wrap(cx + a.rx, a.W)];
-    }
-    uint32_t flags = 0u;
-#pragma unroll
-    for (int k = 0; k < steps; ++k) flags |= (uint32_t)(nb[k] != 0) << k;
-    flags &= inside;
-    int pos = 0;
-#pragma unroll
-    for (int k = 0; k < steps; ++k) {
-        const bool f = (flags >> k) & 1u;
-        const uint64_t m = __ballot(f);
-        if (f) {
-            const int ly = (k / mbx) * 4 + (lane >> 4), lx = (k % mbx) * 16 + (lane & 15);
-            list[pos + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)(ly * TF + lx);
-        }
-        pos += __popcll(m);
-    }
-    __syncthreads();
-    if (lane == 0) a.block_count[slot] = pos;
-    for (int t = 0; 64 * t < pos; ++t) {
-        const int n = min(64, pos - 64 * t);
-        const bool v = lane < n;
-        const int c = list[64 * t + min(lane, n - 1)];
-        const int ly = c / TF, lx = c % TF;
-        if (v) a.work_cells[slot * (TF * TF) + 64 * t + lane] = (uint16_t)c;
-        // Bounding box of the item's cells (wave reductions).
-        int x0 = v ? lx : TF, y0 = v ? ly : TF, x1 = v ? lx : 0, y1 = v ? ly : 0;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            x0 = min(x0, __shfl_xor(x0, o));
-            y0 = min(y0, __shfl_xor(y0, o));
-            x1 = max(x1, __shfl_xor(x1, o));
-            y1 = max(y1, __shfl_xor(y1, o));
-        }
-        if (lane == 0) a.item_box[slot * steps + t] = x0 | (y0 << 5) | (x1 << 10) | (y1 << 15);
-    }
-}
-
 template <int P, int NW, int FIT>
 __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, const int TF) {
     extern __shared__ float tile[];
@@ -211,32 +148,64 @@ __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, cons
     {
         const int blocks = tiles_x * ((a.H + TF - 1) / TF);
         const int nslot = blocks * a.n_units;
-        if (a.count && (int64_t)blockIdx.x * (BLOCK * 8) < nslot) {
-            // Workgroup b sums slots [2048 b, 2048 b + 2048): eight loads per
+        const int nwords = nslot * TF / 4;       // row counts, four per word
+        if (a.count && (int64_t)blockIdx.x * (BLOCK * 8) < nwords) {
+            // Workgroup b sums words [2048 b, 2048 b + 2048): eight loads per
             // thread in flight, then one add per wave to the counter.
+            const uint32_t* words = reinterpret_cast<const uint32_t*>(a.row_count);
             int total = 0;
             const int q0 = blockIdx.x * (BLOCK * 8) + tid;
-            int v[8];
+            uint32_t v[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = a.block_count[min(q0 + BLOCK * j, nslot - 1)];
+            for (int j = 0; j < 8; ++j) v[j] = words[min(q0 + BLOCK * j, nwords - 1)];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) total += q0 + BLOCK * j < nslot ? v[j] : 0;
+            for (int j = 0; j < 8; ++j)
+                total += q0 + BLOCK * j < nwords ? (int)((v[j] & 0xffu) + ((v[j] >> 8) & 0xffu) +
+                                                         ((v[j] >> 16) & 0xffu) + (v[j] >> 24))
+                                                  : 0;
             for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o);
             if (lane == 0 && total > 0) atomicAdd(a.count, total * (a.mirror ? 2 : 1));
         }
         const int k = blockIdx.x / nslot, slot = blockIdx.x % nslot;
-        const int cnt = a.block_count[slot];
+        // Row counts of the slot on lanes 0..TF-1, inclusive prefix sums.
+        const int rc = lane < TF ? (int)a.row_count[slot * TF + lane] : 0;
+        int incl = rc;
+#pragma unroll
+        for (int o = 1; o < 32; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        const int cnt = __builtin_amdgcn_readfirstlane(__shfl(incl, TF - 1));
         if (64 * k >= cnt) return;
         const int u = slot / blocks, blk = slot % blocks;
-        const int box = a.item_box[(int64_t)slot * (TF * TF / 64) + k];
-        const int bx0 = box & 31, by0 = (box >> 5) & 31;
-        const int bw = ((box >> 10) & 31) - bx0 + 1 + 2 * R;
-        const int bh = ((box >> 15) & 31) - by0 + 1 + 2 * R;
+        // List position of the lane's state (lanes past the count take the
+        // item's first state: staged, not stored), its row (the first whose
+        // inclusive prefix exceeds it) and its column.
+        const bool act = 64 * k + lane < cnt;
+        const int lp = act ? 64 * k + lane : 64 * k;
+        int row = 0;
+        for (int st = TF >> 1; st > 0; st >>= 1)
+            if (__shfl(incl, row + st - 1) <= lp) row += st;
+        const int start = __shfl(incl, row) - __shfl(rc, row);
+        const int col = a.work_cols[((int64_t)slot * TF + row) * TF + (lp - start)];
+        // Bounding box of the item's cells (wave reductions).
+        int bx0 = col, by0 = row, bx1 = col, by1 = row;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            bx0 = min(bx0, __shfl_xor(bx0, o));
+            by0 = min(by0, __shfl_xor(by0, o));
+            bx1 = max(bx1, __shfl_xor(bx1, o));
+            by1 = max(by1, __shfl_xor(by1, o));
+        }
+        bx0 = __builtin_amdgcn_readfirstlane(bx0);
+        by0 = __builtin_amdgcn_readfirstlane(by0);
+        bx1 = __builtin_amdgcn_readfirstlane(bx1);
+        by1 = __builtin_amdgcn_readfirstlane(by1);
+        const int bw = bx1 - bx0 + 1 + 2 * R;
+        const int bh = by1 - by0 + 1 + 2 * R;
+        const int li = row * TF + col;
         // Block origin moved to the bounding box of the item's cells.
         const int sx0 = (blk % tiles_x) * TF + bx0, sy0 = (blk / tiles_x) * TF + by0;
-        const bool act = lane < min(64, cnt - 64 * k);
-        // Lanes past the item's count take the box corner (staged, not stored).
-        const int li = act ? a.work_cells[(int64_t)slot * (TF * TF) + 64 * k + lane] : by0 * TF + bx0;
         // Staging: SB elements of the box per thread and batch, loaded from
         // clamped positions without a guard so the batch's loads are all in
         // flight together; out-of-map and unknown cells become SENTINEL.
@@ -382,16 +351,9 @@ static void launch_flagged_p(const AssessArgs& a, int tf, dim3 grid, size_t lds,
 }
 
 hipError_t launch_assess_flagged(const AssessArgs& a, int pitch, hipStream_t stream) {
-    if (!a.need || !a.work_cells || !a.block_count || !a.item_box || a.W <= 0 || a.H <= 0 ||
-        a.n_units <= 0)
-        return hipErrorInvalidValue;
+    if (!a.row_count || !a.work_cols || a.W <= 0 || a.H <= 0 || a.n_units <= 0) return hipErrorInvalidValue;
     if (pitch != 48 && pitch != 80 && pitch != 112 && pitch != 144) return hipErrorInvalidValue;
     const int tf = flagged_tile(a.R, pitch);
-    const int blocks = ((a.W + tf - 1) / tf) * ((a.H + tf - 1) / tf);
-    if (tf == 32)
-        hipLaunchKernelGGL(compact_kernel<32>, dim3(blocks, a.n_units), dim3(64), 0, stream, a);
-    else
-        hipLaunchKernelGGL(compact_kernel<16>, dim3(blocks, a.n_units), dim3(64), 0, stream, a);
     // One workgroup per possible item; those past their block's count return.
     const int64_t max_items = flagged_work_items(a.W, a.H, a.n_units, a.R, pitch);
     const dim3 grid((unsigned)max_items);

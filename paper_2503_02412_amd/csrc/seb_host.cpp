@@ -751,20 +751,30 @@ int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
     };
     seb::sur::SurArgs& w = s->ws;
     std::memset(&w, 0, sizeof(w));
-    const int64_t max_items = flagged_work_items((int)W, (int)H, U, c->geo.R, c->fpitch);
-    const int64_t n_blocks = flagged_blocks((int)W, (int)H, U, c->geo.R, c->fpitch);
+    // fallback lists: per (unit, block of tf x tf cells) a count per block row
+    // and the row's columns
+    const int tf = flagged_tile(c->geo.R, c->fpitch);
+    const int64_t n_slots = flagged_blocks((int)W, (int)H, U, c->geo.R, c->fpitch);
     const bool ok =
         al((void**)&w.yaw_sc, (size_t)U * sizeof(float2)) &&
         al((void**)&w.o2map, (size_t)(H + 16) * (W + 16) * seb::net::C2 * 2) &&
         al((void**)&w.ymap, (size_t)U * seb::net::H1 * 2) &&
-        al((void**)&w.known, (size_t)cells * 4) && al((void**)&w.need, (size_t)U * cells) &&
-        al((void**)&w.work_cells, (size_t)max_items * 64 * 2) &&
-        al((void**)&w.block_count, (size_t)n_blocks * sizeof(int32_t)) &&
-        al((void**)&w.item_box, (size_t)max_items * sizeof(int32_t));
+        al((void**)&w.known, (size_t)cells * 4) &&
+        al((void**)&w.row_count, (size_t)n_slots * tf) &&
+        al((void**)&w.work_cols, (size_t)n_slots * tf * tf);
     if (!ok) {
         seb_surrogate_destroy(s);
         return fail(SEB_ERR_ALLOC, "device allocation failed");
     }
+    // Counts of block rows past the map's edge are never written: zero once.
+    const std::vector<uint8_t> zeros((size_t)n_slots * tf, 0);
+    if (hipMemcpy(w.row_count, zeros.data(), zeros.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        seb_surrogate_destroy(s);
+        return fail(SEB_ERR_HIP, "fallback list initialisation failed");
+    }
+    w.tf = tf;
+    w.blocks_x = (int)((W + tf - 1) / tf);
+    w.blocks = w.blocks_x * (int)((H + tf - 1) / tf);
     {
         // (sin, cos) of each evaluated yaw unit's angle 2 pi u / K, in FP64
         std::vector<float2> sc(U);
@@ -824,12 +834,10 @@ int seb_surrogate_infer(seb_surrogate* s, const seb_net* net, const float* heigh
     a.status = out->status;
     hipError_t e = seb::sur::launch_surrogate(w, a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "surrogate launch");
-    // The plain method for the flagged states, compacted tile by tile.
-    a.need = w.need;
+    // The plain method for the listed states.
     a.count = n_fallback_dev;
-    a.work_cells = w.work_cells;
-    a.block_count = w.block_count;
-    a.item_box = w.item_box;
+    a.row_count = w.row_count;
+    a.work_cols = w.work_cols;
     a.offs = s->ctx->d_offs_f;
     e = launch_assess_flagged(a, s->ctx->fpitch, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "fallback assessment launch");

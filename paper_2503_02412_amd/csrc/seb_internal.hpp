@@ -83,16 +83,15 @@ struct AssessArgs {
     int32_t min_valid;
     int32_t precision;
     int32_t fit;                 // 0 least-squares plane, 1 principal-component plane
-    const uint8_t* need;         // [n_units][H][W] (ring cells) for the flagged-state
-                                 // kernel: assess the states whose byte is nonzero
     int32_t* count;              // optional, zero on entry: the flagged-state
-                                 // kernels add the number of states they assess
+                                 // kernel adds the number of states it assesses
                                  // (both mirror bins)
-    // workspace of the flagged-state kernels (caller-owned, sized by
-    // flagged_work_items; see launch_assess_flagged)
-    uint16_t* work_cells;        // per (unit, block): its flagged cells, block-local
-    int32_t* block_count;        // per (unit, block): number of flagged cells
-    int32_t* item_box;           // per (unit, block, item): bounding box of the item's cells
+    // Flagged states, listed row by row per (unit, block) of TF x TF cells
+    // (TF = flagged_tile), slot = unit * blocks + block: row r of the slot's
+    // block lists row_count[slot * TF + r] block-local columns at
+    // work_cols[(slot * TF + r) * TF ..].  Rows past the map's edge count zero.
+    const uint8_t* row_count;
+    const uint8_t* work_cols;
     // state rectangles (logical coordinates) and their tile decomposition
     int32_t n_rects;
     int32_t rect[MAX_RECTS][4];
@@ -119,9 +118,8 @@ struct InsertArgs {
 
 // Launchers (seb_assess.hip).  Return hipSuccess or the launch error.
 hipError_t launch_assess(const AssessArgs& a, int pitch, hipStream_t stream);
-// Assess only the states whose a.need byte is set, anywhere in the map.  The
-// workspace holds flagged_work_items(...) items, 64 cells per item, one count
-// per (unit, block) and one box per item.
+// Assess only the states listed in a.row_count / a.work_cols, anywhere in the
+// map, 64 listed states per workgroup.
 hipError_t launch_assess_flagged(const AssessArgs& a, int pitch, hipStream_t stream);
 // Block side of the flagged-state kernels: 32 when its halo fits the pitch.
 inline int flagged_tile(int R, int pitch) { return (32 + 2 * R <= pitch) ? 32 : 16; }

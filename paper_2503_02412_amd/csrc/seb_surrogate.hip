@@ -32,24 +32,6 @@ using net::bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ bf16 to_bf16(float f) {
-    return (bf16)f;   // round to nearest even (v_cvt_pk_bf16_f32)
-}
-__device__ __forceinline__ float from_bf16(bf16 h) {
-    return __uint_as_float((uint32_t)__builtin_bit_cast(uint16_t, h) << 16);
-}
-
-__device__ __forceinline__ float height_at(const SurArgs& s, int y, int x, float* known) {
-    if (y < 0 || x < 0 || y >= s.H || x >= s.W) {
-        *known = 0.f;
-        return 0.f;
-    }
-    const float h = s.height[(int64_t)y * s.ld + x];
-    const bool ok = fabsf(h) < HEIGHT_LIMIT;
-    *known = ok ? 1.f : 0.f;
-    return ok ? h : 0.f;
-}
-
 // Height the z output is relative to: the cell's own height when known, else
 // the mean of its known 8-neighbours, summed in row-major order (false when
 // none is known).  The nine loads are issued together from clamped positions
@@ -81,7 +63,7 @@ __device__ __forceinline__ bool ref_height(const SurArgs& s, int cy, int cx, flo
     return n > 0.f;
 }
 
-// Trunk of the map form, one launch with two kinds of workgroups.
+// Trunk of the map form, one launch with three kinds of workgroups.
 //
 // Convolution tiles (the first tiles_y2 * tiles_x2 workgroups): conv1 and
 // conv2 for a 16 x 16 tile of conv2 positions (y2, x2) in [-12, H+4) x
@@ -99,9 +81,10 @@ __device__ __forceinline__ bool ref_height(const SurArgs& s, int cy, int cx, flo
 //
 // Known-fraction tiles (the remaining workgroups): the fraction of known
 // cells in each cell's 24 x 24 window [c - 12, c + 12), for 16 x 16 cells,
-// from an LDS tile of known flags (row sums, then column sums).  The first of
-// them also clears the fallback counter and computes fc1's yaw term for every
-// yaw unit.
+// from an LDS tile of known flags (row sums, then column sums).
+//
+// One more workgroup clears the fallback counter and computes fc1's yaw term
+// for every yaw unit.
 constexpr int TT = 16;                       // conv2 positions per tile side
 constexpr int T1 = TT + 4;                   // conv1 positions per tile side
 constexpr int TC = T1 + 4;                   // input cells per side (window 4, slope +1 -> 25 heights)
@@ -115,6 +98,28 @@ __global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
     const int r = lane & 15, g = lane >> 4;
     const int tx2 = (s.W + 16 + TT - 1) / TT, ty2 = (s.H + 16 + TT - 1) / TT;
     const int nconv = tx2 * ty2;
+    if (blockIdx.x == gridDim.x - 1) {
+        // ---- the last workgroup: clears the fallback counter and computes
+        // fc1's yaw term Y[u][n] = Wy[n] . (sin, cos)(theta_u), eight fp16
+        // neurons per entry (Wy is [n][2]: float4 q of an entry holds neurons
+        // 2q and 2q + 1) ----
+        if (tid == 0 && s.n_fallback) *s.n_fallback = 0;
+        static_assert(net::OFF_WY % 4 == 0, "yaw weights read as float4");
+        for (int i = tid; i < s.U * (net::H1 / 8); i += 256) {
+            const float2 sc = s.yaw_sc[i >> 4];
+            const float4* wp = (const float4*)(s.theta + net::OFF_WY + 16 * (i & 15));
+            typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+            h8 v;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 w = wp[q];
+                v[2 * q] = (_Float16)(sc.x * w.x + sc.y * w.y);
+                v[2 * q + 1] = (_Float16)(sc.x * w.z + sc.y * w.w);
+            }
+            reinterpret_cast<h8*>(s.ymap)[i] = v;
+        }
+        return;
+    }
     if ((int)blockIdx.x >= nconv) {
         // ---- known fraction of 16 x 16 cells ----
         constexpr int T = 16, SPAN = T + net::PATCH - 1;     // 39 rows / columns of flags
@@ -125,26 +130,6 @@ __global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
         const int b = blockIdx.x - nconv;
         const int kx = (s.W + T - 1) / T;
         const int x0 = (b % kx) * T, y0 = (b / kx) * T;
-        if (b == 0) {
-            if (tid == 0 && s.n_fallback) *s.n_fallback = 0;
-            // fc1's yaw term Y[u][n] = Wy[n] . (sin, cos)(theta_u), eight fp16
-            // neurons per entry (Wy is [n][2]: float4 q of an entry holds
-            // neurons 2q and 2q + 1)
-            static_assert(net::OFF_WY % 4 == 0, "yaw weights read as float4");
-            for (int i = tid; i < s.U * (net::H1 / 8); i += 256) {
-                const float2 sc = s.yaw_sc[i >> 4];
-                const float4* wp = (const float4*)(s.theta + net::OFF_WY + 16 * (i & 15));
-                typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-                h8 v;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float4 w = wp[q];
-                    v[2 * q] = (_Float16)(sc.x * w.x + sc.y * w.y);
-                    v[2 * q + 1] = (_Float16)(sc.x * w.z + sc.y * w.w);
-                }
-                reinterpret_cast<h8*>(s.ymap)[i] = v;
-            }
-        }
         // six loads per thread in flight, from clamped positions, masked afterwards
         constexpr int NB = (SPAN * SPAN + 255) / 256;
         float hv[NB];
@@ -359,7 +344,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int cl = lane & 31, lh = lane >> 5;
-    const int W2m = s.W + 16, H2m = s.H + 16, cells = s.H * s.W;
+    const int W2m = s.W + 16, H2m = s.H + 16;
     const int tx = (s.W + NT_X - 1) / NT_X;
     const int cy0 = (blockIdx.x / tx) * NT_Y, cx0 = (blockIdx.x % tx) * NT_X;
 
@@ -501,8 +486,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
     // also wait for the previous unit's stores.
     __builtin_amdgcn_s_waitcnt(0);
 
+    // Fallback lists: the cell's block (tf x tf cells), row and column in it;
+    // unit u's lists start at u * blocks * tf * tf.
+    const int bcol = hx % s.tf;
+    const int blk = (hy / s.tf) * s.blocks_x + hx / s.tf;
+    const int crow = blk * s.tf + hy % s.tf;               // row-count index
+    const int lrow = crow * s.tf;                           // row list start
+    const uint32_t bmask = s.tf == 32 ? 0xffffffffu : (cl < 16 ? 0xffffu : 0xffff0000u);
+    const bool first = lh == 0 && real && bcol == 0;
     const f16x8 zero8 = {};
-    const int64_t plane = (int64_t)cells;
     for (int u = u0; u < u1; ++u) {
         // zero (u < 2^30), but not known to be: it keeps the per-unit LDS
         // reads of T and W5 inside the loop instead of in registers
@@ -529,14 +521,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
             y3 = __builtin_amdgcn_mfma_f32_32x32x16_f16(w5s[kk * 64 + lane + zo], h2, y3, 0, 0, 0);
         }
         // Lanes with lh = 0 hold rows 0..3, the four outputs of state (cell, u).
+        bool fb = false;
         if (lh == 0 && real) {
             const float o0 = y3[0] + b5[0];
             const float o1 = y3[1] + b5[1];
             const float o2 = y3[2] + b5[2];
             const float o3 = y3[3] + b5[3];
             const float risk = fminf(fmaxf(o3, 0.f), 1.f);
-            const bool fb = out_of_dist || fabsf(risk - s.risk_max) < s.band;
-            s.need[u * plane + cell] = fb ? 1 : 0;
+            fb = out_of_dist || fabsf(risk - s.risk_max) < s.band;
             if (!fb) {
                 Result res;
                 res.z = hc + net::S_Z * o0;
@@ -548,6 +540,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
                 if (a.mirror) store(a, u + a.mirror, cell, res, true);
             }
         }
+        // The row segment's flagged states go to its blocks' row lists (one
+        // block of 32 columns, or two of 16): a flagged lane writes its column
+        // at its rank among the block's flagged lanes, each block's first lane
+        // the row's count.
+        const uint32_t mine = (uint32_t)__ballot(fb) & bmask;
+        const int64_t lists = (int64_t)u * s.blocks * s.tf * s.tf;
+        if (fb) s.work_cols[lists + lrow + __popc(mine & ((1u << cl) - 1u))] = (uint8_t)bcol;
+        if (first) s.row_count[lists / s.tf + crow] = (uint8_t)__popc(mine);
     }
 }
 
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
 hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, hipStream_t stream) {
     const int conv_tiles = ((s.H + 16 + TT - 1) / TT) * ((s.W + 16 + TT - 1) / TT);
     const int known_tiles = ((s.H + 15) / 16) * ((s.W + 15) / 16);
-    hipLaunchKernelGGL(trunk_kernel, dim3(conv_tiles + known_tiles), dim3(256), 0, stream, s);
+    hipLaunchKernelGGL(trunk_kernel, dim3(conv_tiles + known_tiles + 1), dim3(256), 0, stream, s);
     hipLaunchKernelGGL(net_kernel, dim3(((s.H + NT_Y - 1) / NT_Y) * ((s.W + NT_X - 1) / NT_X)), dim3(256),
                        net_lds_bytes(s.U), stream, s, a);
     return hipGetLastError();

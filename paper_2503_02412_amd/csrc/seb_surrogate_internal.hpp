@@ -26,18 +26,19 @@ struct SurArgs {
     net::bf16* o2map;            // [(H+16)(W+16)][32]  conv2 at positions -12 .. H+3
     net::f16* ymap;              // [U][128]            fc1's yaw term Wy . (sin, cos) per unit
     float* known;                // [H*W]               known fraction of the 24 x 24 window
-    uint8_t* need;               // [U][H*W]            1 = state falls back to the plain method
     int32_t* n_fallback;         // optional device counter of fallen-back states
-    uint16_t* work_cells;        // fallback workspace (see AssessArgs)
-    int32_t* block_count;
-    int32_t* item_box;
+    // flagged states, per (unit, block of tf x tf cells) and block row: the
+    // row's count and its block-local columns (see AssessArgs)
+    uint8_t* row_count;          // [U * blocks][tf]
+    uint8_t* work_cols;          // [U * blocks][tf][tf]
+    int tf, blocks_x, blocks;
     // fallback rule
     float risk_max, band, min_known;
 };
 
-// Network part: fills `a`'s outputs for the states it answers and s.need for
-// the others.  The caller then re-assesses the flagged states with the plain
-// method (launch_assess_flagged).
+// Network part: fills `a`'s outputs for the states it answers and lists the
+// others in s.row_count / s.work_cols.  The caller then re-assesses the listed
+// states with the plain method (launch_assess_flagged).
 hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, hipStream_t stream);
 
 }  // namespace sur
