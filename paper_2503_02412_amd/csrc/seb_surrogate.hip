@@ -372,12 +372,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
 #pragma unroll
     for (int q = 0; q < 4; ++q) b3[q] = *(const float4*)(s.theta + net::OFF_B3 + 32 * wave + 8 * q + 4 * lh);
     f16x8 wst[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int f = tid + 256 * j;                   // fragment (t, kk, lane')
-        const int t = f >> 9, kk = (f >> 6) & 7, ln = f & 63;
-        wst[j] = *(const f16x8*)(s.pw.w4h + (32 * t + (ln & 31)) * net::H1 + 16 * kk + 8 * (ln >> 5));
-    }
     // fc1's yaw term [U][16] (eight fp16 neurons per entry), entries tid and
     // tid + 256 (more than 32 yaw units: see below)
     const int ny = s.U * (net::H1 / 8);
@@ -411,6 +405,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
     for (int st = 0; st < KSTEPS; ++st) {
         const bf16x8 av = ar[st % A_DEPTH];
         if (st + A_DEPTH < KSTEPS) ar[st % A_DEPTH] = w3f[(st + A_DEPTH) * 256];
+        if (st == KSTEPS - A_DEPTH - 4) {
+            // fc2's weights for LDS, issued late in the loop so they do not
+            // add to the workgroup's first wave of loads
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int f = tid + 256 * j;                   // fragment (t, kk, lane')
+                const int t = f >> 9, kk = (f >> 6) & 7, ln = f & 63;
+                wst[j] = *(const f16x8*)(s.pw.w4h + (32 * t + (ln & 31)) * net::H1 + 16 * kk + 8 * (ln >> 5));
+            }
+        }
         // K step st covers channels 16 h .. 16 h + 15 of gathered position k
         const int k = st >> 1, h = st & 1, a5 = k / net::P2, b5 = k - a5 * net::P2;
 #pragma unroll
