@@ -284,27 +284,9 @@ def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4, p=N
     val_loss = validation_loss(net, val)
     ctx = seb.Context(p)
     sur = seb.Surrogate(ctx)
-    out = seb.alloc_outputs(p)
-    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
-    err = {f: [] for f in ("z", "roll", "pitch", "risk")}
-    mask_ok, answered, unsafe, fallback, t_sur, t_plain = 0, 0, 0, [], [], []
-    for seed in I.SURROGATE_EVAL_SEEDS[:eval_maps]:
-        h = I.config2_map(seed)
-        dh = torch.from_numpy(h).cuda()
-        t_sur.append(time_launches(torch, lambda: sur.infer(net, dh, out, band=0.1, min_known=0.5,
-                                                            n_fallback=nf), 50, 5))
-        fallback.append(int(nf.item()) / p.n_states)
-        g = {k: v.cpu().numpy() for k, v in out.items()}
-        t_plain.append(time_launches(torch, lambda: ctx.assess(dh, out), 50, 5))
-        o = {k: v.cpu().numpy() for k, v in out.items()}
-        m = ((g["status"] & seb.ST_SURROGATE) > 0) & ((o["status"] & 1) > 0)
-        answered += int(m.sum())
-        for f in err:
-            err[f].append(np.abs(g[f][m].astype(np.float64) - o[f][m]))
-        mask_ok += int(np.sum(((g["status"][m] & 16) > 0) == ((o["status"][m] & 16) > 0)))
-        # unsafe direction: answered traversable where the plain method sets an obstacle bit
-        unsafe += int(np.count_nonzero(m & ((g["status"] & 16) > 0) & ((o["status"] & 6) > 0)))
-    ms_sur, ms_plain = float(np.mean(t_sur)), float(np.mean(t_plain))
+    maps = [torch.from_numpy(I.config2_map(seed)).cuda() for seed in I.SURROGATE_EVAL_SEEDS[:eval_maps]]
+    points = [surrogate_point(torch, seb, p, ctx, sur, net, maps, band=0.1, min_known=mk)
+              for mk in SURROGATE_MIN_KNOWN]
     return {
         "workload": "2-conv + 3-layer MLP (bf16, MFMA) on 24x24 slope/known patches + yaw; "
                     "trained on 2M plain-kernel labels of 70 seeded 64x64 sinusoid terrains; "
@@ -319,6 +301,55 @@ def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4, p=N
             train_steps * 4096 / t_train * TRAIN_FLOP_PER_SAMPLE / 1e12 / VENDOR_BF16_PEAK_TFLOPS,
         "loss_first_last": [float(hist[:20].mean()), float(hist[-20:].mean())],
         "validation_loss": val_loss, "validation_samples": int(val.n_samples),
+        **points[0],
+        "other_operating_points": points[1:],
+    }
+
+
+# Fallback thresholds on the known fraction of a state's 24 x 24 window: the
+# first is the reported operating point.  The training windows include the
+# maps' edges and corners, where as little as a quarter of the window lies on
+# the map, so windows with a quarter of their cells known are inside the
+# training distribution; 0.5 is reported beside it.
+SURROGATE_MIN_KNOWN = (0.25, 0.5)
+
+
+def surrogate_point(torch, seb, p, ctx, sur, net, maps, band: float, min_known: float):
+    """Surrogate inference with the plain fallback at one operating point, on
+    the given maps: time per map against the plain kernel (each timed after a
+    sustained run of itself), the fallback fraction, and the error on the
+    answered states against the plain kernel (which matches the FP64 oracle to
+    within 1e-5 on these maps)."""
+    out = seb.alloc_outputs(p)
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    err = {f: [] for f in ("z", "roll", "pitch", "risk")}
+    mask_ok, answered, unsafe, fallback, t_sur, t_plain = 0, 0, 0, [], [], []
+    for dh in maps:
+        def surrogate():
+            sur.infer(net, dh, out, band=band, min_known=min_known, n_fallback=nf)
+
+        def plain():
+            ctx.assess(dh, out)
+
+        # each timed after 0.3 s of itself: the clock the GPU settles at
+        # depends on the work it runs
+        sustain(torch, plain, 0.3)
+        t_plain.append(time_launches(torch, plain, 200, 5))
+        o = {k: v.cpu().numpy() for k, v in out.items()}
+        sustain(torch, surrogate, 0.3)
+        t_sur.append(time_launches(torch, surrogate, 200, 5))
+        fallback.append(int(nf.item()) / p.n_states)
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+        m = ((g["status"] & seb.ST_SURROGATE) > 0) & ((o["status"] & 1) > 0)
+        answered += int(m.sum())
+        for f in err:
+            err[f].append(np.abs(g[f][m].astype(np.float64) - o[f][m]))
+        mask_ok += int(np.sum(((g["status"][m] & 16) > 0) == ((o["status"][m] & 16) > 0)))
+        # unsafe direction: answered traversable where the plain method sets an obstacle bit
+        unsafe += int(np.count_nonzero(m & ((g["status"] & 16) > 0) & ((o["status"] & 6) > 0)))
+    ms_sur, ms_plain = float(np.mean(t_sur)), float(np.mean(t_plain))
+    return {
+        "band": band, "min_known": min_known,
         "ms_per_map": ms_sur, "cells_per_s": p.n_states / (ms_sur * 1e-3),
         "plain_ms_per_map_same_maps": ms_plain, "speedup_vs_plain": ms_plain / ms_sur,
         "fallback_fraction": float(np.mean(fallback)),
@@ -329,8 +360,17 @@ def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4, p=N
         "mask_agreement": mask_ok / max(1, answered),
         "unsafe_traversable": unsafe,
         "unsafe_traversable_fraction": unsafe / max(1, answered),
-        "band": 0.1, "min_known": 0.5,
     }
+
+
+def sustain(torch, fn, seconds: float):
+    """Run fn back to back for about `seconds`, so that what is timed next
+    runs at the GPU's sustained clock."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(20):
+            fn()
+        torch.cuda.synchronize()
 
 
 def host_cpu():
