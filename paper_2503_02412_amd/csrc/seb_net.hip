@@ -283,39 +283,59 @@ __global__ __launch_bounds__(256) void reduce_split_kernel(const float* part, in
     }
 }
 
-// Column sums of a bf16 matrix D [M][ld] (optionally weighted by w[m][0/1]),
-// two-stage: per-block partials [gridDim.x][N][nw] then a final pass.
-__global__ __launch_bounds__(256) void colsum_kernel(const bf16* D, int64_t ld, int M, int N,
+// Column sums of the first N columns of a bf16 matrix D [M][ld] (N a power of
+// two <= 256), optionally weighted by w[m][0/1], in two passes.  Block b sums
+// rows [b * rows, (b + 1) * rows): thread t takes column t % N and every
+// (256 / N)-th row from row t / N on, so 256 / N rows are read per step; the
+// row lanes are then added in order through LDS into partial[b][N][nw].  The
+// final pass adds the blocks' partials of one output per block (a fixed-order
+// tree), so the sums are deterministic.
+__global__ __launch_bounds__(256) void colsum_kernel(const bf16* D, int64_t ld, int M, int N, int rows,
                                                      const float* w, float* partial) {
-    const int n = threadIdx.x;   // N <= 256
-    const int rows = (M + gridDim.x - 1) / gridDim.x;
+    __shared__ float red[2][256];
+    const int t = threadIdx.x, c = t & (N - 1), lanes = 256 / N;
     const int r0 = blockIdx.x * rows, r1 = min(M, r0 + rows);
-    if (n >= N) return;
-    float s = 0.f, s0 = 0.f, s1 = 0.f;
-    for (int m = r0; m < r1; ++m) {
-        const float v = from_bf16(D[(int64_t)m * ld + n]);
+    float s0 = 0.f, s1 = 0.f;
+    for (int m = r0 + t / N; m < r1; m += lanes) {
+        const float v = from_bf16(D[(int64_t)m * ld + c]);
         if (w) {
             s0 += v * w[2 * m];
             s1 += v * w[2 * m + 1];
         } else {
-            s += v;
+            s0 += v;
         }
     }
-    if (w) {
-        partial[((int64_t)blockIdx.x * N + n) * 2] = s0;
-        partial[((int64_t)blockIdx.x * N + n) * 2 + 1] = s1;
-    } else {
-        partial[(int64_t)blockIdx.x * N + n] = s;
+    red[0][t] = s0;
+    red[1][t] = s1;
+    __syncthreads();
+    if (t < N) {
+        float a0 = 0.f, a1 = 0.f;
+        for (int j = 0; j < lanes; ++j) {
+            a0 += red[0][t + N * j];
+            a1 += red[1][t + N * j];
+        }
+        if (w) {
+            partial[((int64_t)blockIdx.x * N + t) * 2] = a0;
+            partial[((int64_t)blockIdx.x * N + t) * 2 + 1] = a1;
+        } else {
+            partial[(int64_t)blockIdx.x * N + t] = a0;
+        }
     }
 }
 
 __global__ __launch_bounds__(256) void colsum_finish_kernel(const float* partial, int nblk, int cnt,
                                                             float* dst) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= cnt) return;
+    __shared__ float red[256];
+    const int i = blockIdx.x, t = threadIdx.x;       // output i
     float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * cnt + i];
-    dst[i] = s;
+    for (int b = t; b < nblk; b += 256) s += partial[(int64_t)b * cnt + i];
+    red[t] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+    }
+    if (t == 0) dst[i] = red[0];
 }
 
 __global__ __launch_bounds__(256) void adam_kernel(float* theta, float* m, float* v, const float* g,
@@ -432,7 +452,8 @@ struct seb_net {
 
 namespace {
 
-constexpr int kColBlocks = 64;
+constexpr int kColBlocks = 1024;     // most blocks of a column-sum pass
+constexpr int kColSteps = 32;        // row steps per block when blocks allow
 
 // Split-K partial buffer: the largest Z * M * N of the weight-gradient GEMMs.
 int64_t part_floats(int64_t Bm) {
@@ -498,11 +519,15 @@ void weight_grad(seb_net* n, const bf16* A, const bf16* B, int M, int Nn, int K,
 
 void colsum(seb_net* n, const bf16* D, int64_t ld, int M, int Nn, const float* w, float* dst,
             hipStream_t s) {
-    hipLaunchKernelGGL(N::colsum_kernel, dim3(kColBlocks), dim3(256), 0, s, D, ld, M, Nn, w,
-                       n->cpart);
+    // rows per block: kColSteps steps of 256 / Nn rows, more when that would
+    // need more than kColBlocks blocks
+    const int lanes = 256 / Nn;
+    const int64_t per = std::max<int64_t>((int64_t)lanes * kColSteps, ((int64_t)M + kColBlocks - 1) / kColBlocks);
+    const int rows = (int)((per + lanes - 1) / lanes * lanes);
+    const int blocks = std::max(1, (int)(((int64_t)M + rows - 1) / rows));
+    hipLaunchKernelGGL(N::colsum_kernel, dim3(blocks), dim3(256), 0, s, D, ld, M, Nn, rows, w, n->cpart);
     const int cnt = Nn * (w ? 2 : 1);
-    hipLaunchKernelGGL(N::colsum_finish_kernel, dim3(blocks_for(cnt)), dim3(256), 0, s, n->cpart,
-                       kColBlocks, cnt, dst);
+    hipLaunchKernelGGL(N::colsum_finish_kernel, dim3(cnt), dim3(256), 0, s, n->cpart, blocks, cnt, dst);
 }
 
 int check_batch(const seb_net* n, const seb_train_batch* b, bool need_labels) {
