@@ -23,6 +23,7 @@
 // least-squares plane is then a closed-form 2 x 2 solve.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "seb.h"
 #include "seb_internal.hpp"
@@ -36,6 +37,50 @@ using namespace dev;
 // The least-squares kernels are held to 8 waves per SIMD (64 VGPRs), which
 // the chunked sample loop would otherwise exceed by one register; the FP64
 // eigen epilogue of the principal-component fit needs more and runs at 5.
+// Cell i of a move's exposed cells (in plan order: the exposed row strip row
+// by row, then the exposed column strip), or of the whole window for a full
+// copy, written into the ring.
+__device__ __forceinline__ void insert_cell(const InsertArgs& a, int64_t i) {
+    int lx, ly;
+    float v;
+    if (a.full) {
+        if (i >= (int64_t)a.W * a.H) return;
+        ly = (int)(i / a.W);
+        lx = (int)(i - (int64_t)ly * a.W);
+        v = a.src ? a.src[(int64_t)ly * a.src_ld + lx] : __builtin_nanf("");
+    } else {
+        const int64_t nrow = (int64_t)a.rows_n * a.W;
+        const int rem = a.H - a.rows_n;
+        if (i < nrow) {
+            ly = a.rows_lo + (int)(i / a.W);
+            lx = (int)(i % a.W);
+        } else {
+            const int64_t j = i - nrow;
+            if (a.cols_n == 0 || j >= (int64_t)a.cols_n * rem) return;
+            const int r = (int)(j / a.cols_n);
+            ly = (a.rows_lo == 0 ? a.rows_n : 0) + r;
+            lx = a.cols_lo + (int)(j - (int64_t)r * a.cols_n);
+        }
+        v = a.src ? a.src[i] : __builtin_nanf("");
+    }
+    const int px = wrap(lx + a.rx, a.W), py = wrap(ly + a.ry, a.H);
+    a.ring[(int64_t)py * a.ld + px] = v;
+}
+
+// Height of logical cell (gx, gy) of a window being moved: an exposed cell's
+// from the move's source (NaN without one), any other from the ring.
+__device__ __forceinline__ float moved_height(const AssessArgs& a, int gx, int gy) {
+    const InsertArgs& s = a.ins;
+    int64_t i = -1;
+    if (gy >= s.rows_lo && gy < s.rows_lo + s.rows_n)
+        i = (int64_t)(gy - s.rows_lo) * s.W + gx;
+    else if (gx >= s.cols_lo && gx < s.cols_lo + s.cols_n)
+        i = (int64_t)s.rows_n * s.W + (int64_t)(gy - (s.rows_lo == 0 ? s.rows_n : 0)) * s.cols_n +
+            (gx - s.cols_lo);
+    if (i >= 0) return s.src ? s.src[i] : __builtin_nanf("");
+    return a.height[(int64_t)wrap(gy + a.ry, a.H) * a.ld + wrap(gx + a.rx, a.W)];
+}
+
 template <int P, int NW, int FIT>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FIT == 0 ? 8 : 1)))
 void assess_kernel(const AssessArgs a) {
@@ -44,6 +89,10 @@ void assess_kernel(const AssessArgs a) {
 
     // Which rectangle and which tile of it.
     const int b = blockIdx.x;
+    if (b >= a.tile_start[a.n_rects]) {           // the fused ring insert
+        insert_cell(a.ins, ((int64_t)(b - a.tile_start[a.n_rects]) * gridDim.y + blockIdx.y) * BLOCK + tid);
+        return;
+    }
     int ri = 0;
     while (ri + 1 < a.n_rects && b >= a.tile_start[ri + 1]) ++ri;
     const int lb = b - a.tile_start[ri];
@@ -72,20 +121,31 @@ void assess_kernel(const AssessArgs a) {
     // banks next to lanes 0-7).
     const int cw = paired ? TILE / 2 + 2 * R : tw;
     const int n_stage = (paired ? 2 : 1) * tw * cw;
-    for (int i = tid; i < n_stage; i += BLOCK) {
-        const int half = i >= tw * cw;
-        const int k = i - half * tw * cw;
-        const int ly = k / cw;
-        const int lx = k - ly * cw;
-        const int gx = sx0 - R + lx, gy = sy0 - R + ly + half * TILE;
-        float v = SENTINEL;
-        if (gx >= 0 && gx < a.W && gy >= 0 && gy < a.H) {
-            const int px = wrap(gx + a.rx, a.W), py = wrap(gy + a.ry, a.H);
-            const float h = a.height[(int64_t)py * a.ld + px];
-            if (fabsf(h) < HEIGHT_LIMIT) v = h;      // false for NaN and +-Inf
+    auto stage = [&](auto moved) {
+        for (int i = tid; i < n_stage; i += BLOCK) {
+            const int half = i >= tw * cw;
+            const int k = i - half * tw * cw;
+            const int ly = k / cw;
+            const int lx = k - ly * cw;
+            const int gx = sx0 - R + lx, gy = sy0 - R + ly + half * TILE;
+            float v = SENTINEL;
+            if (gx >= 0 && gx < a.W && gy >= 0 && gy < a.H) {
+                float h;
+                if constexpr (decltype(moved)::value) {
+                    h = moved_height(a, gx, gy);
+                } else {
+                    const int px = wrap(gx + a.rx, a.W), py = wrap(gy + a.ry, a.H);
+                    h = a.height[(int64_t)py * a.ld + px];
+                }
+                if (fabsf(h) < HEIGHT_LIMIT) v = h;      // false for NaN and +-Inf
+            }
+            tile[(half * tw + ly) * P + lx + half * (TILE / 2)] = v;
         }
-        tile[(half * tw + ly) * P + lx + half * (TILE / 2)] = v;
-    }
+    };
+    if (a.ins_on)
+        stage(std::true_type{});
+    else
+        stage(std::false_type{});
     __syncthreads();
 
     const int lane = tid & 63;
@@ -266,31 +326,7 @@ __global__ __launch_bounds__(BLOCK) void flagged_kernel(const AssessArgs a, cons
 
 // Write newly exposed cells (or unknown) into the ring.
 __global__ __launch_bounds__(BLOCK) void insert_kernel(const InsertArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    int lx, ly;
-    float v;
-    if (a.full) {
-        if (i >= (int64_t)a.W * a.H) return;
-        ly = (int)(i / a.W);
-        lx = (int)(i - (int64_t)ly * a.W);
-        v = a.src ? a.src[(int64_t)ly * a.src_ld + lx] : __builtin_nanf("");
-    } else {
-        const int64_t nrow = (int64_t)a.rows_n * a.W;
-        const int rem = a.H - a.rows_n;
-        if (i < nrow) {
-            ly = a.rows_lo + (int)(i / a.W);
-            lx = (int)(i % a.W);
-        } else {
-            const int64_t j = i - nrow;
-            if (a.cols_n == 0 || j >= (int64_t)a.cols_n * rem) return;
-            const int r = (int)(j / a.cols_n);
-            ly = (a.rows_lo == 0 ? a.rows_n : 0) + r;
-            lx = a.cols_lo + (int)(j - (int64_t)r * a.cols_n);
-        }
-        v = a.src ? a.src[i] : __builtin_nanf("");
-    }
-    const int px = wrap(lx + a.rx, a.W), py = wrap(ly + a.ry, a.H);
-    a.ring[(int64_t)py * a.ld + px] = v;
+    insert_cell(a, (int64_t)blockIdx.x * BLOCK + threadIdx.x);
 }
 
 }  // namespace
@@ -318,7 +354,7 @@ hipError_t launch_assess(const AssessArgs& a, int pitch, hipStream_t stream) {
     const int tiles = a.tile_start[a.n_rects];
     if (tiles == 0) return hipSuccess;
     const int groups = (a.n_units + a.units_per_group - 1) / a.units_per_group;
-    const dim3 grid(tiles, groups);
+    const dim3 grid(tiles + (a.ins_on ? a.ins_blocks : 0), groups);
     bool any_pair = false;
     for (int r = 0; r < a.n_rects; ++r) any_pair = any_pair || a.edge_pair[r];
     const size_t lds = any_pair ? edge_pair_lds(a.R, pitch)

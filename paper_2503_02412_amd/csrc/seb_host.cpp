@@ -17,6 +17,7 @@
 #include "seb_sdf_internal.hpp"
 #include "seb_elevation_internal.hpp"
 #include "seb_surrogate_internal.hpp"
+#include "seb_trace.hpp"
 
 using namespace seb;
 
@@ -363,7 +364,8 @@ int check_out(const seb_out* o) {
 }
 
 int run_assess(seb_ctx* c, const float* height, int64_t ld, int rx, int ry, const seb_out* out,
-               int n_rects, const int32_t (*rects)[4], hipStream_t stream) {
+               int n_rects, const int32_t (*rects)[4], hipStream_t stream,
+               const InsertArgs* ins = nullptr) {
     AssessArgs a;
     base_args(c, &a);
     a.height = height;
@@ -376,6 +378,16 @@ int run_assess(seb_ctx* c, const float* height, int64_t ld, int rx, int ry, cons
     a.risk = out->risk;
     a.status = out->status;
     set_rects(&a, n_rects, rects, c->pitch);
+    if (ins) {
+        // the move's ring insert rides on the assessment: its cells in chunks of
+        // BLOCK, spread over the launch's unit groups
+        a.ins = *ins;
+        a.ins_on = 1;
+        const int64_t n = (int64_t)ins->rows_n * ins->W + (int64_t)ins->cols_n * (ins->H - ins->rows_n);
+        const int64_t groups = (a.n_units + a.units_per_group - 1) / a.units_per_group;
+        const int64_t chunks = (n + BLOCK - 1) / BLOCK;
+        a.ins_blocks = (int32_t)((chunks + groups - 1) / groups);
+    }
     const hipError_t e = launch_assess(a, c->pitch, stream);
     if (e != hipSuccess) return hip_fail(e, "assessment kernel launch");
     return SEB_OK;
@@ -494,6 +506,7 @@ int seb_validate_config(const seb_config* cfg) {
 }
 
 int seb_create(const seb_config* cfg, seb_ctx** out) {
+    SEB_TRACE_RANGE();
     if (!out) return fail(SEB_ERR_INVALID, "out is NULL");
     *out = nullptr;
     int rc = seb_validate_config(cfg);
@@ -604,6 +617,7 @@ void seb_destroy(seb_ctx* c) {
 
 int seb_assess_se2(seb_ctx* c, const float* height, int64_t ld, int32_t x0, int32_t y0,
                    int32_t nx, int32_t ny, const seb_out* out, void* stream) {
+    SEB_TRACE_RANGE();
     if (!c) return fail(SEB_ERR_INVALID, "ctx is NULL");
     if (nx < 0 || ny < 0) return fail(SEB_ERR_INVALID, "nx and ny must be >= 0");
     if (nx == 0 || ny == 0) return SEB_OK;
@@ -619,6 +633,7 @@ int seb_assess_se2(seb_ctx* c, const float* height, int64_t ld, int32_t x0, int3
 
 int seb_window_create(seb_ctx* c, float* height_ring, int64_t ld, const seb_out* out_ring,
                       double x, double y, seb_window** out) {
+    SEB_TRACE_RANGE();
     if (!out) return fail(SEB_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (!c || !height_ring) return fail(SEB_ERR_INVALID, "ctx and height_ring must be non-NULL");
@@ -651,6 +666,7 @@ int seb_window_origin(const seb_window* w, int64_t* origin_x, int64_t* origin_y,
 
 int seb_window_reset(seb_window* w, double x, double y, const float* heights, int64_t ld,
                      void* stream) {
+    SEB_TRACE_RANGE();
     if (!w) return fail(SEB_ERR_INVALID, "window is NULL");
     if (!std::isfinite(x) || !std::isfinite(y)) return fail(SEB_ERR_INVALID, "position not finite");
     seb_ctx* c = w->ctx;
@@ -699,6 +715,7 @@ int seb_plan_window_move(const seb_config* cfg, int64_t origin_x, int64_t origin
 
 int seb_update_window(seb_window* w, double x, double y, const float* new_cells, void* stream,
                       int64_t* n_states_recomputed) {
+    SEB_TRACE_RANGE();
     seb_window_plan p;
     int rc = seb_window_plan_move(w, x, y, &p);
     if (rc != SEB_OK) return rc;
@@ -723,17 +740,24 @@ int seb_update_window(seb_window* w, double x, double y, const float* new_cells,
         ia.cols_n = p.exposed_cols;
         ia.cols_lo = dx > 0 ? W - (int)dx : 0;
     }
-    hipError_t e = launch_insert(ia, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "ring insert launch");
     w->ox = p.new_origin_x;
     w->oy = p.new_origin_y;
     if (n_states_recomputed) *n_states_recomputed = p.n_states;
-    if (p.n_rects == 0) return SEB_OK;
+    if (p.full_reset || p.n_rects == 0) {
+        hipError_t e = launch_insert(ia, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "ring insert launch");
+        if (p.n_rects == 0) return SEB_OK;
+        return run_assess(c, w->ring, w->ld, ia.rx, ia.ry, &w->out, p.n_rects, p.rects,
+                          (hipStream_t)stream);
+    }
+    // A partial move: one launch assesses the band, staging the exposed cells
+    // from new_cells, and writes them into the ring.
     return run_assess(c, w->ring, w->ld, ia.rx, ia.ry, &w->out, p.n_rects, p.rects,
-                      (hipStream_t)stream);
+                      (hipStream_t)stream, &ia);
 }
 
 int seb_surrogate_create(seb_ctx* c, seb_surrogate** out) {
+    SEB_TRACE_RANGE();
     if (!out) return fail(SEB_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (!c) return fail(SEB_ERR_INVALID, "ctx is NULL");
@@ -809,6 +833,7 @@ void seb_surrogate_destroy(seb_surrogate* s) {
 int seb_surrogate_infer(seb_surrogate* s, const seb_net* net, const float* height, int64_t ld,
                         const seb_out* out, float band, float min_known, int32_t* n_fallback_dev,
                         void* stream) {
+    SEB_TRACE_RANGE();
     if (!s || !net || !height) return fail(SEB_ERR_INVALID, "surrogate, net and height must be set");
     int rc = check_out(out);
     if (rc != SEB_OK) return rc;
@@ -845,6 +870,7 @@ int seb_surrogate_infer(seb_surrogate* s, const seb_net* net, const float* heigh
 }
 
 int seb_fuser_create(seb_ctx* c, int64_t max_points, seb_fuser** out) {
+    SEB_TRACE_RANGE();
     if (!out) return fail(SEB_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (!c) return fail(SEB_ERR_INVALID, "ctx is NULL");
@@ -956,6 +982,7 @@ int fuse_args(const seb_ctx* c, float* height, float* variance, int64_t ld, int6
 
 int seb_fuse_scan(seb_fuser* f, float* height, float* variance, int64_t ld, int64_t origin_x,
                   int64_t origin_y, const seb_scan* sc, int32_t* n_fused_dev, void* stream) {
+    SEB_TRACE_RANGE();
     if (!f || !height || !variance || !sc)
         return fail(SEB_ERR_INVALID, "fuser, height, variance and scan must be non-NULL");
     elev::ScanArgs s;
@@ -972,6 +999,7 @@ int seb_fuse_scan(seb_fuser* f, float* height, float* variance, int64_t ld, int6
 int seb_fuse_scan_static(seb_ctx* c, float* height, float* variance, int64_t ld,
                          int64_t origin_x, int64_t origin_y, const seb_scan* sc,
                          int32_t* n_fused_dev, void* stream) {
+    SEB_TRACE_RANGE();
     if (!c || !height || !variance || !sc)
         return fail(SEB_ERR_INVALID, "ctx, height, variance and scan must be non-NULL");
     if ((int64_t)c->cfg.width * c->cfg.height > elev::STATIC_MAX_CELLS)
@@ -994,6 +1022,7 @@ int seb_fuse_scan_static(seb_ctx* c, float* height, float* variance, int64_t ld,
 
 int seb_raycast_reset(seb_ctx* c, float* height, int64_t ld, int64_t origin_x, int64_t origin_y,
                       const seb_scan* sc, double margin, int32_t* n_reset_dev, void* stream) {
+    SEB_TRACE_RANGE();
     if (!c || !height || !sc) return fail(SEB_ERR_INVALID, "ctx, height and scan must be non-NULL");
     const seb_config& g = c->cfg;
     if (ld < g.width) return fail(SEB_ERR_INVALID, "ld must be >= width");
@@ -1041,6 +1070,7 @@ int seb_raycast_reset(seb_ctx* c, float* height, int64_t ld, int64_t origin_x, i
 
 int seb_inpaint_nearest(seb_ctx* c, const float* height, int64_t ld, int32_t ring_x,
                         int32_t ring_y, int32_t radius, float* out, int64_t out_ld, void* stream) {
+    SEB_TRACE_RANGE();
     if (!c || !height || !out) return fail(SEB_ERR_INVALID, "ctx, height and out must be non-NULL");
     const seb_config& g = c->cfg;
     if (ld < g.width || out_ld < g.width) return fail(SEB_ERR_INVALID, "row strides must be >= width");
@@ -1072,6 +1102,7 @@ int seb_inpaint_nearest(seb_ctx* c, const float* height, int64_t ld, int32_t rin
 
 int seb_sdf_se2(seb_ctx* c, const uint8_t* status, int32_t ring_x, int32_t ring_y,
                 int32_t cap_cells, int32_t unknown_is_obstacle, float* sdf, void* stream) {
+    SEB_TRACE_RANGE();
     if (!c || !status || !sdf) return fail(SEB_ERR_INVALID, "ctx, status and sdf must be non-NULL");
     const seb_config& g = c->cfg;
     if (ring_x < 0 || ring_x >= g.width || ring_y < 0 || ring_y >= g.height)
@@ -1089,6 +1120,7 @@ int seb_sdf_se2(seb_ctx* c, const uint8_t* status, int32_t ring_x, int32_t ring_
 
 int seb_query_se2(seb_ctx* c, const float* sdf, const float* risk, int32_t ring_x, int32_t ring_y,
                   const float* poses, int64_t n, float* out, void* stream) {
+    SEB_TRACE_RANGE();
     if (!c) return fail(SEB_ERR_INVALID, "ctx is NULL");
     if (n < 0) return fail(SEB_ERR_INVALID, "n must be >= 0");
     if (!sdf && !risk) return fail(SEB_ERR_INVALID, "sdf and risk are both NULL");

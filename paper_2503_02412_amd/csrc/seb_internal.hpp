@@ -42,6 +42,18 @@ struct Segment {
     int32_t pad;
 };
 
+struct InsertArgs {
+    float* ring;
+    int64_t ld;
+    int32_t W, H;
+    int32_t rx, ry;              // ring offset of the NEW window
+    const float* src;            // exposed cells in plan order, or null (unknown)
+    int64_t src_ld;              // for full copies: row stride of src
+    int32_t rows_lo, rows_n;     // exposed row strip [rows_lo, rows_lo + rows_n)
+    int32_t cols_lo, cols_n;     // exposed column strip
+    int32_t full;                // 1: copy the whole logical window from src
+};
+
 struct AssessArgs {
     // map (ring storage) and outputs
     const float* height;
@@ -102,18 +114,13 @@ struct AssessArgs {
     // upper tile, lanes 8-15 the lower), after its full tiles.
     int32_t edge_pair[MAX_RECTS];
     int32_t tile_start[MAX_RECTS + 1];
-};
-
-struct InsertArgs {
-    float* ring;
-    int64_t ld;
-    int32_t W, H;
-    int32_t rx, ry;              // ring offset of the NEW window
-    const float* src;            // exposed cells in plan order, or null (unknown)
-    int64_t src_ld;              // for full copies: row stride of src
-    int32_t rows_lo, rows_n;     // exposed row strip [rows_lo, rows_lo + rows_n)
-    int32_t cols_lo, cols_n;     // exposed column strip
-    int32_t full;                // 1: copy the whole logical window from src
+    // Ring insert of a window move, fused into the assessment (ins_on, never
+    // with ins.full): the exposed cells are staged from ins.src instead of the
+    // ring, and ins_blocks x gridDim.y more workgroups, after the tiles, write
+    // them into the ring.  The ring cells they overwrite lie outside the new
+    // window, so no workgroup of the launch reads them.
+    InsertArgs ins;
+    int32_t ins_on, ins_blocks;
 };
 
 // Launchers (seb_assess.hip).  Return hipSuccess or the launch error.

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include "seb_trace.hpp"
 #include <string>
 #include <vector>
 
@@ -630,6 +631,7 @@ void seb_net_destroy(seb_net* n) {
 }
 
 int seb_net_create(uint64_t seed, int32_t max_batch, seb_net** out) {
+    SEB_TRACE_RANGE();
     if (!out) return net_fail(SEB_ERR_INVALID, "out is NULL");
     *out = nullptr;
     if (max_batch < 32 || max_batch % 32 != 0 || max_batch > (1 << 16))
@@ -753,6 +755,7 @@ int seb_net_load(seb_net* n, const char* path) {
 }
 
 int seb_net_forward(seb_net* n, const seb_train_batch* b, float* y_dev, void* stream) {
+    SEB_TRACE_RANGE();
     int rc = check_batch(n, b, false);
     if (rc != SEB_OK) return rc;
     if (!y_dev) return net_fail(SEB_ERR_INVALID, "y_dev is NULL");
@@ -763,6 +766,7 @@ int seb_net_forward(seb_net* n, const seb_train_batch* b, float* y_dev, void* st
 
 int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* loss_dev,
                        float* grad_dev, void* stream) {
+    SEB_TRACE_RANGE();
     int rc = check_batch(n, bt, true);
     if (rc != SEB_OK) return rc;
     if (!(lr >= 0.f) || !std::isfinite(lr)) return net_fail(SEB_ERR_INVALID, "bad learning rate");
