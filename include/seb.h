@@ -97,9 +97,12 @@ typedef struct seb_window seb_window;
 int seb_validate_config(const seb_config* cfg);
 
 /* Build the FP64 footprint/yaw table for `cfg` on the host and upload it to
- * the current HIP device.  *out receives the new context (library-owned;
- * release with seb_destroy).  Errors: SEB_ERR_INVALID, SEB_ERR_UNSUPPORTED,
- * SEB_ERR_ALLOC, SEB_ERR_HIP. */
+ * the current HIP device: for every yaw bin theta_k = 2 pi k / K of the SE(2)
+ * grid and every sample of the footprint of Sec. V-B (the vehicle's extent
+ * under the yaw-rotated body frame of Sec. III, Eq. 1-3), the sample's map
+ * offset split into an integer cell and bilinear weights.  *out receives the
+ * new context (library-owned; release with seb_destroy).  Errors:
+ * SEB_ERR_INVALID, SEB_ERR_UNSUPPORTED, SEB_ERR_ALLOC, SEB_ERR_HIP. */
 int seb_create(const seb_config* cfg, seb_ctx** out);
 
 /* Release a context and its device table.  NULL is ignored.  The caller must
