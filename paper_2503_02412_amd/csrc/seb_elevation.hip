@@ -361,6 +361,8 @@ __device__ __forceinline__ int ray_cell(const RayArgs& r, const Ray& q, int64_t 
 
 __global__ __launch_bounds__(256) void zero_kernel(int32_t* v) { *v = 0; }
 
+constexpr int RAY_PARTS = 8;
+
 __global__ __launch_bounds__(256) void raycast_kernel(const RayArgs r) {
 #pragma clang fp contract(off)
     __shared__ int32_t cnt_lds[256];
@@ -368,7 +370,13 @@ __global__ __launch_bounds__(256) void raycast_kernel(const RayArgs r) {
     const double X0 = (double)r.ox * r.res, X1 = (double)(r.ox + r.W) * r.res;
     const double Y0 = (double)r.oy * r.res, Y1 = (double)(r.oy + r.H) * r.res;
     int32_t count = 0;
-    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < r.n; n += stride) {
+    // Work item w walks part w % RAY_PARTS of ray w / RAY_PARTS (adjacent lanes
+    // share a ray), so that a wave waits on the longest part of a ray, not on
+    // the longest ray (2, 4 and 8 parts measured 0.29, 0.26 and 0.245 ms
+    // against 0.36 ms for whole rays on a 190k-ray scan).
+    for (int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x; w < r.n * RAY_PARTS; w += stride) {
+        const int64_t n = w / RAY_PARTS;
+        const int part = (int)(w - n * RAY_PARTS);
         const double px = r.pts[3 * n], py = r.pts[3 * n + 1], pz = r.pts[3 * n + 2];
         const double q0 = r.A[0] * px + r.A[1] * py + r.A[2] * pz + r.a[0];
         const double q1 = r.A[3] * px + r.A[4] * py + r.A[5] * pz + r.a[1];
@@ -406,7 +414,14 @@ __global__ __launch_bounds__(256) void raycast_kernel(const RayArgs r) {
             continue;
         }
         if (!(tb >= ta)) continue;
-        const double xa = r.sx + ta * q.dx, ya = r.sy + ta * q.dy;
+        // This part's share [tl, th] of [ta, tb].  It starts from the cell that
+        // holds the point at tl and, like the whole walk, stops once both next
+        // crossings lie past its end: the parts overlap at their ends, so every
+        // cell the whole walk would try is tried by some part (a cell tried
+        // twice gets the same decision).
+        const double tl = ta + (tb - ta) * ((double)part / RAY_PARTS);
+        const double th = part + 1 == RAY_PARTS ? tb : ta + (tb - ta) * ((double)(part + 1) / RAY_PARTS);
+        const double xa = r.sx + tl * q.dx, ya = r.sy + tl * q.dy;
         int64_t i = (int64_t)floor(xa / r.res), j = (int64_t)floor(ya / r.res);
         i = i < r.ox ? r.ox : (i >= r.ox + r.W ? r.ox + r.W - 1 : i);
         j = j < r.oy ? r.oy : (j >= r.oy + r.H ? r.oy + r.H - 1 : j);
@@ -422,7 +437,7 @@ __global__ __launch_bounds__(256) void raycast_kernel(const RayArgs r) {
                 count += ray_cell(r, q, i + step_x, j);
                 count += ray_cell(r, q, i, j + step_y);
             }
-            if (fmin(tmx, tmy) > tb + 1e-9) break;
+            if (fmin(tmx, tmy) > th + 1e-9) break;
             if (tmx < tmy) {
                 i += step_x;
                 tmx += tdx;
@@ -561,7 +576,7 @@ hipError_t static_fuse_work(FuseWork* w) {
 hipError_t launch_raycast(const RayArgs& r, hipStream_t stream) {
     if (r.n_reset) hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(1), 0, stream, r.n_reset);
     if (r.n > 0) {
-        const unsigned blocks = (unsigned)std::min<int64_t>((r.n + 255) / 256, 4096);
+        const unsigned blocks = (unsigned)std::min<int64_t>((r.n * RAY_PARTS + 255) / 256, 16384);
         hipLaunchKernelGGL(raycast_kernel, dim3(blocks), dim3(256), 0, stream, r);
     }
     return hipGetLastError();
