@@ -46,19 +46,45 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmArgs g) {
     f32x4 acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const bf16x8 zero8 = {};
     if (m0 < g.M && n0 < g.N) {
-        for (int k = kb; k < ke; k += 32) {
-            bf16x8 a[2], b[2];
+        // Fragments of the next GD K steps in flight.  Rows past M and columns
+        // past N read the last row or column: they only feed accumulator
+        // entries that are never stored.
+        const bf16* arow[2];
+        const bf16* brow[2];
+        for (int t = 0; t < 2; ++t) {
+            arow[t] = g.A + (int64_t)min(m0 + 16 * t + r, g.M - 1) * g.lda + kq;
+            brow[t] = g.B + (int64_t)min(n0 + 16 * t + r, g.N - 1) * g.ldb + kq;
+        }
+        constexpr int GD = 4;
+        bf16x8 a[GD][2], b[GD][2];
+        const int steps = (ke - kb) / 32;
+#pragma unroll
+        for (int p = 0; p < GD; ++p) {
+            const int k = kb + 32 * min(p, steps - 1);
             for (int t = 0; t < 2; ++t) {
-                const int m = m0 + 16 * t + r;
-                a[t] = (m < g.M) ? *(const bf16x8*)(g.A + (int64_t)m * g.lda + k + kq) : zero8;
-                const int n = n0 + 16 * t + r;
-                b[t] = (n < g.N) ? *(const bf16x8*)(g.B + (int64_t)n * g.ldb + k + kq) : zero8;
+                a[p][t] = *(const bf16x8*)(arow[t] + k);
+                b[p][t] = *(const bf16x8*)(brow[t] + k);
             }
-            for (int i = 0; i < 2; ++i)
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        for (int s0 = 0; s0 < steps; s0 += GD) {
+#pragma unroll
+            for (int p = 0; p < GD; ++p) {
+                if (s0 + p < steps) {
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[p][i], b[p][j], acc[i][j], 0, 0, 0);
+                    // the next loads of this slot (the last GD steps re-load a valid step)
+                    const int k = kb + 32 * min(s0 + p + GD, steps - 1);
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        a[p][t] = *(const bf16x8*)(arow[t] + k);
+                        b[p][t] = *(const bf16x8*)(brow[t] + k);
+                    }
+                }
+            }
         }
     }
     for (int i = 0; i < 2; ++i)
