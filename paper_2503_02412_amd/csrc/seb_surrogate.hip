@@ -78,6 +78,9 @@ __device__ __forceinline__ bool ref_height(const SurArgs& s, int cy, int cx, flo
 //          channel) (144 used).
 // Inputs (x-slope, y-slope, known) and conv1's outputs are bf16 as in
 // training; conv1's output tile stays in LDS, conv2's goes to o2map.
+// Workgroups have eight waves: with one or two workgroups per CU the launch
+// is bound by each wave's chain of dependent LDS reads and products, which
+// twice the waves per tile halves.
 //
 // Known-fraction tiles (the remaining workgroups): the fraction of known
 // cells in each cell's 24 x 24 window [c - 12, c + 12), for 16 x 16 cells,
@@ -88,8 +91,9 @@ __device__ __forceinline__ bool ref_height(const SurArgs& s, int cy, int cx, flo
 constexpr int TT = 16;                       // conv2 positions per tile side
 constexpr int T1 = TT + 4;                   // conv1 positions per tile side
 constexpr int TC = T1 + 4;                   // input cells per side (window 4, slope +1 -> 25 heights)
+constexpr int TB = 512, TW = TB / 64;        // threads and waves of a workgroup
 
-__global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
+__global__ __launch_bounds__(TB) void trunk_kernel(const SurArgs s) {
     __shared__ float hs[TC + 1][TC + 1];     // heights (0 where unknown)
     __shared__ float ks[TC + 1][TC + 1];     // known flags
     __shared__ float cin[3][TC][TC + 1];     // bf16-rounded inputs: x-slope, y-slope, known
@@ -105,7 +109,7 @@ __global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
         // 2q and 2q + 1) ----
         if (tid == 0 && s.n_fallback) *s.n_fallback = 0;
         static_assert(net::OFF_WY % 4 == 0, "yaw weights read as float4");
-        for (int i = tid; i < s.U * (net::H1 / 8); i += 256) {
+        for (int i = tid; i < s.U * (net::H1 / 8); i += TB) {
             const float2 sc = s.yaw_sc[i >> 4];
             const float4* wp = (const float4*)(s.theta + net::OFF_WY + 16 * (i & 15));
             typedef _Float16 h8 __attribute__((ext_vector_type(8)));
@@ -130,18 +134,18 @@ __global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
         const int b = blockIdx.x - nconv;
         const int kx = (s.W + T - 1) / T;
         const int x0 = (b % kx) * T, y0 = (b / kx) * T;
-        // six loads per thread in flight, from clamped positions, masked afterwards
-        constexpr int NB = (SPAN * SPAN + 255) / 256;
+        // three loads per thread in flight, from clamped positions, masked afterwards
+        constexpr int NB = (SPAN * SPAN + TB - 1) / TB;
         float hv[NB];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
-            const int i = min(tid + 256 * j, SPAN * SPAN - 1);
+            const int i = min(tid + TB * j, SPAN * SPAN - 1);
             const int y = y0 - net::HALF + i / SPAN, x = x0 - net::HALF + i % SPAN;
             hv[j] = s.height[(int64_t)min(max(y, 0), s.H - 1) * s.ld + min(max(x, 0), s.W - 1)];
         }
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
-            const int i = tid + 256 * j;
+            const int i = tid + TB * j;
             if (i >= SPAN * SPAN) continue;
             const int rr = i / SPAN, cc = i % SPAN;
             const int y = y0 - net::HALF + rr, x = x0 - net::HALF + cc;
@@ -149,7 +153,7 @@ __global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
             kf[rr][cc] = (in && fabsf(hv[j]) < HEIGHT_LIMIT) ? 1.f : 0.f;
         }
         __syncthreads();
-        for (int i = tid; i < SPAN * T; i += 256) {
+        for (int i = tid; i < SPAN * T; i += TB) {
             const int rr = i / T, cc = i % T;
             float n = 0.f;
             for (int d = 0; d < net::PATCH; ++d) n += kf[rr][cc + d];
@@ -158,7 +162,7 @@ __global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
         __syncthreads();
         const int cc = tid % T, rr = tid / T;
         const int x = x0 + cc, y = y0 + rr;
-        if (x < s.W && y < s.H) {
+        if (rr < T && x < s.W && y < s.H) {
             float n = 0.f;
             for (int d = 0; d < net::PATCH; ++d) n += rs[rr + d][cc];
             s.known[(int64_t)y * s.W + x] = n * (1.f / (net::PATCH * net::PATCH));
@@ -182,17 +186,17 @@ __global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
             w2f[t][k2] = *(const bf16x8*)(s.pw.w2 + (16 * t + r) * net::K2P + 32 * k2 + 8 * g);
     }
     static_assert(net::OFF_B1 % 4 == 0 && net::OFF_B2 % 4 == 0, "biases read as float4");
-    constexpr int NH = ((TC + 1) * (TC + 1) + 255) / 256;      // 3 cells per thread
+    constexpr int NH = ((TC + 1) * (TC + 1) + TB - 1) / TB;      // 2 cells per thread
     float hv[NH];
 #pragma unroll
     for (int j = 0; j < NH; ++j) {
-        const int i = min(tid + 256 * j, (TC + 1) * (TC + 1) - 1);
+        const int i = min(tid + TB * j, (TC + 1) * (TC + 1) - 1);
         const int y = Y2 + i / (TC + 1), x = X2 + i % (TC + 1);
         hv[j] = s.height[(int64_t)min(max(y, 0), s.H - 1) * s.ld + min(max(x, 0), s.W - 1)];
     }
 #pragma unroll
     for (int j = 0; j < NH; ++j) {
-        const int i = tid + 256 * j;
+        const int i = tid + TB * j;
         if (i >= (TC + 1) * (TC + 1)) continue;
         const int rr = i / (TC + 1), cc = i % (TC + 1);
         const int y = Y2 + rr, x = X2 + cc;
@@ -202,7 +206,7 @@ __global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
     }
     __syncthreads();
     // Input channels of the 24 x 24 cells, rounded to bf16 as in training.
-    for (int i = tid; i < TC * TC; i += 256) {
+    for (int i = tid; i < TC * TC; i += TB) {
         const int rr = i / TC, cc = i % TC;
         const float v0 = ks[rr][cc], vx = ks[rr][cc + 1], vy = ks[rr + 1][cc];
         const float h0 = hs[rr][cc];
@@ -214,7 +218,7 @@ __global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
     // conv1: 25 groups of 16 positions, spread over the waves.  Lane (r, g)
     // supplies position 16 m + r at K = 32 ks + 8 g .. + 7: channel 2 ks + g / 2,
     // window rows 2 (g % 2) and 2 (g % 2) + 1, columns 0..3 (channel 3: zero).
-    for (int m = wave; m < (T1 * T1) / 16; m += 4) {
+    for (int m = wave; m < (T1 * T1) / 16; m += TW) {
         const int pp = 16 * m + r, py = pp / T1, px = pp % T1;
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -234,11 +238,11 @@ __global__ __launch_bounds__(256) void trunk_kernel(const SurArgs s) {
         *reinterpret_cast<bf16x4*>(reinterpret_cast<bf16*>(&o1s[pp][0]) + 4 * g) = o;
     }
     __syncthreads();
-    // conv2: 16 groups of 16 positions (one tile row each), 4 per wave.  Lane
+    // conv2: 16 groups of 16 positions (one tile row each), 2 per wave.  Lane
     // (r, g) supplies position (row, r) at K = 32 ks + 8 g .. + 7: tap
     // 2 ks + g / 2, channels 8 (g % 2) .. + 7.
     const int W2m = s.W + 16, H2m = s.H + 16;
-    for (int q = wave; q < TT; q += 4) {
+    for (int q = wave; q < TT; q += TW) {
         const int y2 = Y2 + q, x2 = X2 + r;
         f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
@@ -560,7 +564,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
 hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, hipStream_t stream) {
     const int conv_tiles = ((s.H + 16 + TT - 1) / TT) * ((s.W + 16 + TT - 1) / TT);
     const int known_tiles = ((s.H + 15) / 16) * ((s.W + 15) / 16);
-    hipLaunchKernelGGL(trunk_kernel, dim3(conv_tiles + known_tiles + 1), dim3(256), 0, stream, s);
+    hipLaunchKernelGGL(trunk_kernel, dim3(conv_tiles + known_tiles + 1), dim3(TB), 0, stream, s);
     hipLaunchKernelGGL(net_kernel, dim3(((s.H + NT_Y - 1) / NT_Y) * ((s.W + NT_X - 1) / NT_X)), dim3(256),
                        net_lds_bytes(s.U), stream, s, a);
     return hipGetLastError();
