@@ -153,33 +153,46 @@ __device__ __forceinline__ bool ref_height(const BatchArgs& a, int mi, int cy, i
     return n > 0.f;
 }
 
-// Channel c (0: x-slope, 1: y-slope, 2: known) of map cell (y, x).
-__device__ __forceinline__ float encode(const BatchArgs& a, int mi, int y, int x, int c) {
-    float v0, v1;
-    const float h0 = map_at(a, mi, y, x, &v0);
-    if (c == 2) return v0;
-    const float h1 = (c == 0) ? map_at(a, mi, y, x + 1, &v1) : map_at(a, mi, y + 1, x, &v1);
-    return v0 * v1 * (h1 - h0) * a.inv_res;
-}
-
 // conv1 im2col: A1[(b*121 + a*11 + bb)][c*16 + i*4 + j]; yaw features and targets.
+// One thread per row (sample b, conv1 position (a, bb)): the 5 x 5 cells
+// under its 4 x 4 window and the next row and column (for the slopes) are
+// read once, and the row's 64 entries leave as eight 16-byte stores.  Input
+// channels at cell (y, x), with k the known flag and h the height (0 where
+// unknown): x-slope k(y,x) k(y,x+1) (h(y,x+1) - h(y,x)) / res, y-slope the
+// same with (y+1, x), and k(y,x).
 __global__ __launch_bounds__(256) void im2col1_kernel(const BatchArgs a, bf16* A1, float* sc,
                                                       float* tgt) {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t total = (int64_t)a.B * P1 * P1 * K1P;
-    if (idx < total) {
-        const int col = (int)(idx % K1P);
-        const int64_t row = idx / K1P;
-        const int pos = (int)(row % (P1 * P1));
-        const int b = (int)(row / (P1 * P1));
-        float v = 0.f;
-        if (col < K1) {
-            const int c = col / 16, i = (col / 4) % 4, j = col % 4;
-            const int mi = a.samples[4 * b], cy = a.samples[4 * b + 1], cx = a.samples[4 * b + 2];
-            const int y = cy - HALF + 2 * (pos / P1) + i, x = cx - HALF + 2 * (pos % P1) + j;
-            v = encode(a, mi, y, x, c);
+    static_assert(K1 == 48 && K1P % 8 == 0, "three channels of 4 x 4, padded to 16-byte groups");
+    if (idx < (int64_t)a.B * P1 * P1) {
+        const int pos = (int)(idx % (P1 * P1));
+        const int b = (int)(idx / (P1 * P1));
+        const int mi = a.samples[4 * b], cy = a.samples[4 * b + 1], cx = a.samples[4 * b + 2];
+        const int y0 = cy - HALF + 2 * (pos / P1), x0 = cx - HALF + 2 * (pos % P1);
+        float h[5][5], v[5][5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+#pragma unroll
+            for (int j = 0; j < 5; ++j) h[i][j] = map_at(a, mi, y0 + i, x0 + j, &v[i][j]);
+        bf16x8* dst = reinterpret_cast<bf16x8*>(A1 + idx * K1P);
+#pragma unroll
+        for (int g = 0; g < K1P / 8; ++g) {
+            bf16x8 o;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int col = 8 * g + e;
+                const int c = col / 16, i = (col / 4) % 4, j = col % 4;
+                float val = 0.f;
+                if (c == 0)
+                    val = v[i][j] * v[i][j + 1] * (h[i][j + 1] - h[i][j]) * a.inv_res;
+                else if (c == 1)
+                    val = v[i][j] * v[i + 1][j] * (h[i + 1][j] - h[i][j]) * a.inv_res;
+                else if (c == 2)
+                    val = v[i][j];
+                o[e] = to_bf16(val);
+            }
+            dst[g] = o;
         }
-        A1[idx] = to_bf16(v);
     }
     if (idx < a.B) {
         const int b = (int)idx;
@@ -242,22 +255,47 @@ __global__ __launch_bounds__(256) void col2im2_kernel(const float* dA2, const bf
     da1[idx] = to_bf16(s);
 }
 
-// Tiled transpose of a bf16 matrix: dst[c][r] = src[r][c].
+// Tiled transpose of a bf16 matrix: dst[c][r] = src[r][c].  A workgroup
+// moves a 64 x 64 tile through LDS; each thread reads two 16-byte runs of a
+// source row and writes two 16-byte runs of a destination row (element by
+// element where a run is cut by the matrix edge or is not 16-byte aligned).
 __global__ __launch_bounds__(256) void transpose_kernel(const bf16* src, int R, int Ccols,
                                                         int64_t lds, bf16* dst, int64_t ldd) {
-    __shared__ uint16_t tile[32][33];
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-    const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
-    for (int k = 0; k < 32; k += 8) {
-        const int r = r0 + ty + k, c = c0 + tx;
-        if (r < R && c < Ccols)
-            tile[ty + k][tx] = __builtin_bit_cast(uint16_t, src[(int64_t)r * lds + c]);
+    typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+    __shared__ uint16_t tile[64][66];
+    const int t = threadIdx.x;
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    const uint16_t* s16 = reinterpret_cast<const uint16_t*>(src);
+    uint16_t* d16 = reinterpret_cast<uint16_t*>(dst);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int rr = (t >> 3) + 32 * k, cc = (t & 7) * 8;
+        const int r = r0 + rr, c = c0 + cc;
+        if (r >= R) continue;
+        const uint16_t* p = s16 + (int64_t)r * lds + c;
+        if (c + 8 <= Ccols && ((uintptr_t)p & 15) == 0) {
+            const u16x8 v = *reinterpret_cast<const u16x8*>(p);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) tile[rr][cc + e] = v[e];
+        } else {
+            for (int e = 0; e < 8 && c + e < Ccols; ++e) tile[rr][cc + e] = p[e];
+        }
     }
     __syncthreads();
-    for (int k = 0; k < 32; k += 8) {
-        const int c = c0 + ty + k, r = r0 + tx;
-        if (r < R && c < Ccols)
-            dst[(int64_t)c * ldd + r] = __builtin_bit_cast(bf16, tile[tx][ty + k]);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int cc = (t >> 3) + 32 * k, rr = (t & 7) * 8;
+        const int c = c0 + cc, r = r0 + rr;
+        if (c >= Ccols) continue;
+        uint16_t* p = d16 + (int64_t)c * ldd + r;
+        if (r + 8 <= R && ((uintptr_t)p & 15) == 0) {
+            u16x8 v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = tile[rr + e][cc];
+            *reinterpret_cast<u16x8*>(p) = v;
+        } else {
+            for (int e = 0; e < 8 && r + e < R; ++e) p[e] = tile[rr + e][cc];
+        }
     }
 }
 
@@ -526,7 +564,7 @@ N::GemmArgs gemm_args(const bf16* A, int64_t lda, const bf16* B, int64_t ldb, in
 }
 
 void transpose(const bf16* src, int R, int C, int64_t lds, bf16* dst, int64_t ldd, hipStream_t s) {
-    dim3 grid((C + 31) / 32, (R + 31) / 32);
+    dim3 grid((C + 63) / 64, (R + 63) / 64);
     hipLaunchKernelGGL(N::transpose_kernel, grid, dim3(256), 0, s, src, R, C, lds, dst, ldd);
 }
 
@@ -592,7 +630,7 @@ hipError_t forward_pass(seb_net* n, const seb_train_batch* bt, float* out, hipSt
     const int B = bt->batch;
     const N::BatchArgs ba = batch_args(bt);
     const int64_t r1 = (int64_t)B * N::P1 * N::P1, r2 = (int64_t)B * N::P2 * N::P2;
-    hipLaunchKernelGGL(N::im2col1_kernel, dim3(blocks_for(r1 * N::K1P)), dim3(256), 0, s, ba, n->A1,
+    hipLaunchKernelGGL(N::im2col1_kernel, dim3(blocks_for(r1)), dim3(256), 0, s, ba, n->A1,
                        n->sc, n->tgt);
     N::GemmArgs g = gemm_args(n->A1, N::K1P, n->pw.w1, N::K1P, (int)r1, N::C1, N::K1P);
     g.bias = n->theta + N::OFF_B1;
