@@ -214,33 +214,43 @@ __global__ __launch_bounds__(256) void im2col1_kernel(const BatchArgs a, bf16* A
 }
 
 // conv2 im2col: A2[(b*25 + a2*5 + b2)][(i*3 + j)*16 + c] = o1[b*121 + (2a2+i)*11 + 2b2+j][c].
+// One thread per (row, group of 16 columns): group t < 9 is tap t, whose 16
+// channels are 32 contiguous bytes of o1 and of A2; group 9 is the padding.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void im2col2_kernel(const bf16* o1, bf16* A2, int B) {
+    static_assert(C1 == 16 && K2 == 9 * 16 && K2P % 16 == 0, "a tap is 32 bytes of channels");
+    constexpr int G = K2P / 16;
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= (int64_t)B * P2 * P2 * K2P) return;
-    const int col = (int)(idx % K2P);
-    const int64_t row = idx / K2P;
+    if (idx >= (int64_t)B * P2 * P2 * G) return;
+    const int tap = (int)(idx % G);
+    const int64_t row = idx / G;
     const int pos = (int)(row % (P2 * P2));
     const int b = (int)(row / (P2 * P2));
-    bf16 v = to_bf16(0.f);
-    if (col < K2) {
-        const int tap = col / 16, c = col % 16;
+    u32x4 v0 = {0u, 0u, 0u, 0u}, v1 = {0u, 0u, 0u, 0u};
+    if (tap < 9) {
         const int y = 2 * (pos / P2) + tap / 3, x = 2 * (pos % P2) + tap % 3;
-        v = o1[((int64_t)b * P1 * P1 + y * P1 + x) * C1 + c];
+        const u32x4* src = reinterpret_cast<const u32x4*>(o1 + ((int64_t)b * P1 * P1 + y * P1 + x) * C1);
+        v0 = src[0];
+        v1 = src[1];
     }
-    A2[idx] = v;
+    u32x4* dst = reinterpret_cast<u32x4*>(A2 + row * K2P + tap * 16);
+    dst[0] = v0;
+    dst[1] = v1;
 }
 
-// Backward of im2col2, gated by conv1's ReLU: da1[b*121 + p][c].
+// Backward of im2col2, gated by conv1's ReLU: da1[b*121 + p][c], four
+// channels per thread (in each channel the same sum, in the same order, as
+// one channel at a time).
 __global__ __launch_bounds__(256) void col2im2_kernel(const float* dA2, const bf16* o1, bf16* da1,
                                                       int B) {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= (int64_t)B * P1 * P1 * C1) return;
-    const int c = (int)(idx % C1);
-    const int64_t row = idx / C1;
+    if (idx >= (int64_t)B * P1 * P1 * (C1 / 4)) return;
+    const int c = 4 * (int)(idx % (C1 / 4));
+    const int64_t row = idx / (C1 / 4);
     const int p = (int)(row % (P1 * P1));
     const int b = (int)(row / (P1 * P1));
     const int y = p / P1, x = p % P1;
-    float s = 0.f;
+    float4 s = {0.f, 0.f, 0.f, 0.f};
     for (int i = 0; i < 3; ++i) {
         const int ty = y - i;
         if (ty < 0 || (ty & 1) || ty / 2 >= P2) continue;
@@ -248,11 +258,19 @@ __global__ __launch_bounds__(256) void col2im2_kernel(const float* dA2, const bf
             const int tx = x - j;
             if (tx < 0 || (tx & 1) || tx / 2 >= P2) continue;
             const int pos = (ty / 2) * P2 + tx / 2;
-            s += dA2[((int64_t)b * P2 * P2 + pos) * K2P + (i * 3 + j) * 16 + c];
+            const float4 d =
+                *reinterpret_cast<const float4*>(dA2 + ((int64_t)b * P2 * P2 + pos) * K2P + (i * 3 + j) * 16 + c);
+            s.x += d.x;
+            s.y += d.y;
+            s.z += d.z;
+            s.w += d.w;
         }
     }
-    if (!(from_bf16(o1[idx]) > 0.f)) s = 0.f;
-    da1[idx] = to_bf16(s);
+    const int64_t o = row * C1 + c;
+    da1[o] = to_bf16(from_bf16(o1[o]) > 0.f ? s.x : 0.f);
+    da1[o + 1] = to_bf16(from_bf16(o1[o + 1]) > 0.f ? s.y : 0.f);
+    da1[o + 2] = to_bf16(from_bf16(o1[o + 2]) > 0.f ? s.z : 0.f);
+    da1[o + 3] = to_bf16(from_bf16(o1[o + 3]) > 0.f ? s.w : 0.f);
 }
 
 // Tiled transpose of a bf16 matrix: dst[c][r] = src[r][c].  A workgroup
@@ -638,7 +656,7 @@ hipError_t forward_pass(seb_net* n, const seb_train_batch* bt, float* out, hipSt
     g.Cb = n->o1;
     g.ldcb = N::C1;
     gemm(g, s);
-    hipLaunchKernelGGL(N::im2col2_kernel, dim3(blocks_for(r2 * N::K2P)), dim3(256), 0, s, n->o1,
+    hipLaunchKernelGGL(N::im2col2_kernel, dim3(blocks_for(r2 * (N::K2P / 16))), dim3(256), 0, s, n->o1,
                        n->A2, B);
     g = gemm_args(n->A2, N::K2P, n->pw.w2, N::K2P, (int)r2, N::C2, N::K2P);
     g.bias = n->theta + N::OFF_B2;
@@ -886,7 +904,7 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     ga.C = n->dA2;
     ga.ldc = N::K2P;
     gemm(ga, s);
-    hipLaunchKernelGGL(N::col2im2_kernel, dim3(blocks_for((int64_t)r1 * N::C1)), dim3(256), 0, s,
+    hipLaunchKernelGGL(N::col2im2_kernel, dim3(blocks_for((int64_t)r1 * (N::C1 / 4))), dim3(256), 0, s,
                        n->dA2, n->o1, n->da1, B);
     transpose(n->da2, r2, N::C2, N::C2, n->da2t, r2, s);
     transpose(n->A2, r2, N::K2P, N::K2P, n->A2t, r2, s);
