@@ -347,16 +347,28 @@ __global__ void finish_loss_kernel(const float* partial, int n, int B, float* ou
     *out = (float)(s / B);
 }
 
-// Sum split-K partials [Z][M][N] into the gradient vector.  kind 0: dst index
-// m * N + n; kind 1 (conv1): columns >= 48 dropped, m * 48 + n; kind 2 (conv2):
-// (tap, c) column -> m * 144 + c * 9 + tap, columns >= 144 dropped.
+// Sum of the split-K partial products part[z][M][N] over z, written to the
+// gradient in the parameter layout (kind 0: [M][N]; 1: conv1's first K1 of
+// K1P columns; 2: conv2's (tap, channel) columns to (channel, tap)).  A
+// workgroup adds `per` outputs (64, 16 or 8): thread (o, q) sums z = q,
+// q + L, ... with L = 256 / per lanes (coalesced over o), and the lanes are
+// added in a fixed order.
 __global__ __launch_bounds__(256) void reduce_split_kernel(const float* part, int Z, int M, int N,
-                                                           int kind, float* dst) {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= M * N) return;
-    const int m = idx / N, n = idx % N;
+                                                           int kind, int per, float* dst) {
+    __shared__ float red[256];
+    const int L = 256 / per;
+    const int o = threadIdx.x % per, q = threadIdx.x / per;
+    const int idx = blockIdx.x * per + o;
+    const int64_t mn = (int64_t)M * N;
     float s = 0.f;
-    for (int z = 0; z < Z; ++z) s += part[(int64_t)z * M * N + idx];
+    if (idx < mn)
+        for (int z = q; z < Z; z += L) s += part[(int64_t)z * mn + idx];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (q != 0 || idx >= mn) return;
+    s = red[o];
+    for (int j = 1; j < L; ++j) s += red[o + per * j];
+    const int m = idx / N, n = idx % N;
     if (kind == 0) {
         dst[idx] = s;
     } else if (kind == 1) {
@@ -539,13 +551,17 @@ constexpr int kColBlocks = 1024;     // most blocks of a column-sum pass
 constexpr int kColSteps = 32;        // row steps per block when blocks allow
 
 // Split-K partial buffer: the largest Z * M * N of the weight-gradient GEMMs.
+// Split-K chunks of the weight gradients (multiples of 32): a few hundred
+// workgroups per product.  The conv layers reduce over 0.1 M and 0.5 M rows.
+constexpr int kFcChunk = 256, kConvChunk = 1024;
+
 int64_t part_floats(int64_t Bm) {
     auto z = [](int64_t K, int64_t chunk) { return (K + chunk - 1) / chunk; };
-    int64_t m = z(Bm, 1024) * N::H1 * N::F;
-    m = std::max(m, z(Bm, 1024) * N::H2 * N::H1);
-    m = std::max(m, z(Bm, 1024) * N::NOUT * N::H2);
-    m = std::max(m, z(Bm * N::P2 * N::P2, 4096) * N::C2 * N::K2P);
-    m = std::max(m, z(Bm * N::P1 * N::P1, 8192) * N::C1 * N::K1P);
+    int64_t m = z(Bm, kFcChunk) * N::H1 * N::F;
+    m = std::max(m, z(Bm, kFcChunk) * N::H2 * N::H1);
+    m = std::max(m, z(Bm, kFcChunk) * N::NOUT * N::H2);
+    m = std::max(m, z(Bm * N::P2 * N::P2, kConvChunk) * N::C2 * N::K2P);
+    m = std::max(m, z(Bm * N::P1 * N::P1, kConvChunk) * N::C1 * N::K1P);
     return m;
 }
 
@@ -596,8 +612,9 @@ void weight_grad(seb_net* n, const bf16* A, const bf16* B, int M, int Nn, int K,
     g.ldc = Nn;
     gemm(g, s);
     const int Z = (K + kchunk - 1) / kchunk;
-    hipLaunchKernelGGL(N::reduce_split_kernel, dim3(blocks_for((int64_t)M * Nn)), dim3(256), 0, s,
-                       n->part, Z, M, Nn, kind, dst);
+    const int per = Z >= 64 ? 8 : Z >= 16 ? 16 : 64;      // outputs per workgroup
+    hipLaunchKernelGGL(N::reduce_split_kernel, dim3((unsigned)(((int64_t)M * Nn + per - 1) / per)), dim3(256),
+                       0, s, n->part, Z, M, Nn, kind, per, dst);
 }
 
 void colsum(seb_net* n, const bf16* D, int64_t ld, int M, int Nn, const float* w, float* dst,
@@ -874,7 +891,7 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     ga.ldcb = N::H2;
     gemm(ga, s);
     transpose(n->h2, B, N::H2, N::H2, n->h2t, B, s);
-    weight_grad(n, n->dyt, n->h2t, N::NOUT, N::H2, B, 1024, 0, g + N::OFF_W5, s);
+    weight_grad(n, n->dyt, n->h2t, N::NOUT, N::H2, B, kFcChunk, 0, g + N::OFF_W5, s);
     colsum(n, n->dy, 32, B, N::NOUT, nullptr, g + N::OFF_B5, s);
     // fc2
     transpose(n->da4, B, N::H2, N::H2, n->da4t, B, s);
@@ -885,7 +902,7 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     ga.ldcb = N::H1;
     gemm(ga, s);
     transpose(n->h1, B, N::H1, N::H1, n->h1t, B, s);
-    weight_grad(n, n->da4t, n->h1t, N::H2, N::H1, B, 1024, 0, g + N::OFF_W4, s);
+    weight_grad(n, n->da4t, n->h1t, N::H2, N::H1, B, kFcChunk, 0, g + N::OFF_W4, s);
     colsum(n, n->da4, N::H2, B, N::H2, nullptr, g + N::OFF_B4, s);
     // fc1
     transpose(n->da3, B, N::H1, N::H1, n->da3t, B, s);
@@ -896,7 +913,7 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     ga.ldcb = N::F;
     gemm(ga, s);
     transpose(n->f, B, N::F, N::F, n->ft, B, s);
-    weight_grad(n, n->da3t, n->ft, N::H1, N::F, B, 1024, 0, g + N::OFF_W3, s);
+    weight_grad(n, n->da3t, n->ft, N::H1, N::F, B, kFcChunk, 0, g + N::OFF_W3, s);
     colsum(n, n->da3, N::H1, B, N::H1, n->sc, g + N::OFF_WY, s);
     colsum(n, n->da3, N::H1, B, N::H1, nullptr, g + N::OFF_B3, s);
     // conv2 (da2 viewed as [B*25][32])
@@ -908,12 +925,12 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
                        n->dA2, n->o1, n->da1, B);
     transpose(n->da2, r2, N::C2, N::C2, n->da2t, r2, s);
     transpose(n->A2, r2, N::K2P, N::K2P, n->A2t, r2, s);
-    weight_grad(n, n->da2t, n->A2t, N::C2, N::K2P, r2, 4096, 2, g + N::OFF_W2, s);
+    weight_grad(n, n->da2t, n->A2t, N::C2, N::K2P, r2, kConvChunk, 2, g + N::OFF_W2, s);
     colsum(n, n->da2, N::C2, r2, N::C2, nullptr, g + N::OFF_B2, s);
     // conv1
     transpose(n->da1, r1, N::C1, N::C1, n->da1t, r1, s);
     transpose(n->A1, r1, N::K1P, N::K1P, n->A1t, r1, s);
-    weight_grad(n, n->da1t, n->A1t, N::C1, N::K1P, r1, 8192, 1, g + N::OFF_W1, s);
+    weight_grad(n, n->da1t, n->A1t, N::C1, N::K1P, r1, kConvChunk, 1, g + N::OFF_W1, s);
     colsum(n, n->da1, N::C1, r1, N::C1, nullptr, g + N::OFF_B1, s);
 
     if (grad_dev) {
