@@ -84,6 +84,21 @@ def time_launches(torch, fn, steps: int, warmup: int):
     return start.elapsed_time(stop) / steps          # ms per launch
 
 
+def per_call_times(torch, fn, n: int = 50):
+    """Durations of n back-to-back calls, each between two HIP events on the
+    launch stream (after the timed steps, at the same clock): median, p10, p90."""
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+    ev[0].record(stream)
+    for i in range(n):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    t = np.array([ev[i].elapsed_time(ev[i + 1]) * 1e3 for i in range(n)])
+    return {"calls": n, "median_us": float(np.median(t)), "p10_us": float(np.percentile(t, 10)),
+            "p90_us": float(np.percentile(t, 90))}
+
+
 def bench_rolling(torch, seb, n_moves: int = 100):
     p = I.CONFIG3
     W, H = p.width, p.height
@@ -532,6 +547,7 @@ def main():
         for name in sorted(names, key=lambda n: n == "large_map"):
             extras[name] = legs[name](torch, seb)
     ms = time_launches(torch, launch, args.steps, args.warmup)
+    per_call = per_call_times(torch, launch)
 
     flops = flops_per_state(p) * p.n_states
     achieved = flops / (ms * 1e-3) / 1e12
@@ -556,6 +572,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VENDOR_FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / VENDOR_FP32_PEAK_TFLOPS,
                      "traffic": traffic},
+        "per_call": per_call,
     }
     result.update(extras)
     if not args.no_cpu:
