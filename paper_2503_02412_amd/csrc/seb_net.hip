@@ -156,11 +156,13 @@ __device__ __forceinline__ bool ref_height(const BatchArgs& a, int mi, int cy, i
 // conv1 im2col: A1[(b*121 + a*11 + bb)][c*16 + i*4 + j]; yaw features and targets.
 // One thread per row (sample b, conv1 position (a, bb)): the 5 x 5 cells
 // under its 4 x 4 window and the next row and column (for the slopes) are
-// read once, and the row's 64 entries leave as eight 16-byte stores.  Input
+// read once, and the row's 64 entries leave as eight 16-byte stores (and,
+// when A1t is given, as the row's column of the transpose, where a wave's
+// lanes write 64 consecutive entries of each row of A1t).  Input
 // channels at cell (y, x), with k the known flag and h the height (0 where
 // unknown): x-slope k(y,x) k(y,x+1) (h(y,x+1) - h(y,x)) / res, y-slope the
 // same with (y+1, x), and k(y,x).
-__global__ __launch_bounds__(256) void im2col1_kernel(const BatchArgs a, bf16* A1, float* sc,
+__global__ __launch_bounds__(256) void im2col1_kernel(const BatchArgs a, bf16* A1, bf16* A1t, float* sc,
                                                       float* tgt) {
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     static_assert(K1 == 48 && K1P % 8 == 0, "three channels of 4 x 4, padded to 16-byte groups");
@@ -192,6 +194,10 @@ __global__ __launch_bounds__(256) void im2col1_kernel(const BatchArgs a, bf16* A
                 o[e] = to_bf16(val);
             }
             dst[g] = o;
+            if (A1t) {                          // training: the transpose too, A1t[col][row]
+#pragma unroll
+                for (int e = 0; e < 8; ++e) A1t[(int64_t)(8 * g + e) * ((int64_t)a.B * P1 * P1) + idx] = o[e];
+            }
         }
     }
     if (idx < a.B) {
@@ -661,12 +667,13 @@ N::BatchArgs batch_args(const seb_train_batch* b) {
 }
 
 // Forward pass of the patch-form network for a batch; outputs y [B][4] into out.
-hipError_t forward_pass(seb_net* n, const seb_train_batch* bt, float* out, hipStream_t s) {
+// train: also lay out conv1's im2col transposed (A1t), for its weight gradient.
+hipError_t forward_pass(seb_net* n, const seb_train_batch* bt, float* out, bool train, hipStream_t s) {
     const int B = bt->batch;
     const N::BatchArgs ba = batch_args(bt);
     const int64_t r1 = (int64_t)B * N::P1 * N::P1, r2 = (int64_t)B * N::P2 * N::P2;
     hipLaunchKernelGGL(N::im2col1_kernel, dim3(blocks_for(r1)), dim3(256), 0, s, ba, n->A1,
-                       n->sc, n->tgt);
+                       train ? n->A1t : nullptr, n->sc, n->tgt);
     N::GemmArgs g = gemm_args(n->A1, N::K1P, n->pw.w1, N::K1P, (int)r1, N::C1, N::K1P);
     g.bias = n->theta + N::OFF_B1;
     g.relu = 1;
@@ -858,7 +865,7 @@ int seb_net_forward(seb_net* n, const seb_train_batch* b, float* y_dev, void* st
     int rc = check_batch(n, b, false);
     if (rc != SEB_OK) return rc;
     if (!y_dev) return net_fail(SEB_ERR_INVALID, "y_dev is NULL");
-    hipError_t e = forward_pass(n, b, y_dev, (hipStream_t)stream);
+    hipError_t e = forward_pass(n, b, y_dev, false, (hipStream_t)stream);
     if (e != hipSuccess) return net_fail(SEB_ERR_HIP, hipGetErrorString(e));
     return SEB_OK;
 }
@@ -872,7 +879,7 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     hipStream_t s = (hipStream_t)stream;
     const int B = bt->batch;
     const int r1 = B * N::P1 * N::P1, r2 = B * N::P2 * N::P2;
-    hipError_t e = forward_pass(n, bt, n->y, s);
+    hipError_t e = forward_pass(n, bt, n->y, true, s);
     if (e != hipSuccess) return net_fail(SEB_ERR_HIP, hipGetErrorString(e));
     float* g = n->grad;
 
@@ -929,7 +936,6 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     colsum(n, n->da2, N::C2, r2, N::C2, nullptr, g + N::OFF_B2, s);
     // conv1
     transpose(n->da1, r1, N::C1, N::C1, n->da1t, r1, s);
-    transpose(n->A1, r1, N::K1P, N::K1P, n->A1t, r1, s);
     weight_grad(n, n->da1t, n->A1t, N::C1, N::K1P, r1, kConvChunk, 1, g + N::OFF_W1, s);
     colsum(n, n->da1, N::C1, r1, N::C1, nullptr, g + N::OFF_B1, s);
 
