@@ -65,7 +65,8 @@ __device__ __forceinline__ bool ref_height(const SurArgs& s, int cy, int cx, flo
 
 // Trunk of the map form, one launch with three kinds of workgroups.
 //
-// Convolution tiles (the first tiles_y2 * tiles_x2 workgroups): conv1 and
+// Convolution tiles (the first tiles_y2 * tiles_x2 workgroups, rounded up to
+// a multiple of 8; see the XCD bands below): conv1 and
 // conv2 for a 16 x 16 tile of conv2 positions (y2, x2) in [-12, H+4) x
 // [-12, W+4).  conv2 at (y2, x2) reads conv1 at (y2 + 2i, x2 + 2j), i, j < 3
 // (dilation 2), so the tile needs conv1 on 20 x 20 positions, whose 4 x 4
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(TB) void trunk_kernel(const SurArgs s) {
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int r = lane & 15, g = lane >> 4;
     const int tx2 = (s.W + 16 + TT - 1) / TT, ty2 = (s.H + 16 + TT - 1) / TT;
-    const int nconv = tx2 * ty2;
+    const int nconv = 8 * ((tx2 * ty2 + 7) / 8);   // convolution workgroups, a multiple of 8
     if (blockIdx.x == gridDim.x - 1) {
         // ---- the last workgroup: clears the fallback counter and computes
         // fc1's yaw term Y[u][n] = Wy[n] . (sin, cos)(theta_u), eight fp16
@@ -170,7 +171,12 @@ __global__ __launch_bounds__(TB) void trunk_kernel(const SurArgs s) {
         return;
     }
     // ---- conv1 + conv2 of a 16 x 16 tile of conv2 positions ----
-    const int Y2 = (blockIdx.x / tx2) * TT - 12, X2 = (blockIdx.x % tx2) * TT - 12;
+    // Tiles in XCD bands, as in net_kernel: workgroup i (on XCD i % 8) takes
+    // tile (i % 8) * per + i / 8, so each XCD writes one band of the conv2 map.
+    const int per = nconv / 8;
+    const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (tile >= tx2 * ty2) return;
+    const int Y2 = (tile / tx2) * TT - 12, X2 = (tile % tx2) * TT - 12;
     // Weights and biases first, with the cell loads, before any wait.
     bf16x8 w1f[2];                           // W1[4g' .. ][..]: A fragments, rows r, K 32ks + 8g
 #pragma unroll
@@ -350,7 +356,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
     const int cl = lane & 31, lh = lane >> 5;
     const int W2m = s.W + 16, H2m = s.H + 16;
     const int tx = (s.W + NT_X - 1) / NT_X;
-    const int cy0 = (blockIdx.x / tx) * NT_Y, cx0 = (blockIdx.x % tx) * NT_X;
+    // Tiles in XCD bands: the hardware hands workgroup i to XCD i % 8, so
+    // workgroup i takes tile (i % 8) * per + i / 8, and each XCD works through
+    // one contiguous band of tile rows, whose conv2 vectors its L2 then holds
+    // (row-major tiles would send every XCD over the whole conv2 map).
+    const int nt = ((s.H + NT_Y - 1) / NT_Y) * tx;
+    const int per = (nt + 7) / 8;
+    const int tile = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (tile >= nt) return;
+    const int cy0 = (tile / tx) * NT_Y, cx0 = (tile % tx) * NT_X;
 
     // Every global load of the workgroup is issued before the first wait:
     // the gathered conv2 vectors, the first A_DEPTH fragments of W3, fc1's
@@ -562,10 +576,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void n
 }  // namespace
 
 hipError_t launch_surrogate(const SurArgs& s, const AssessArgs& a, hipStream_t stream) {
-    const int conv_tiles = ((s.H + 16 + TT - 1) / TT) * ((s.W + 16 + TT - 1) / TT);
+    const int conv_tiles = 8 * ((((s.H + 16 + TT - 1) / TT) * ((s.W + 16 + TT - 1) / TT) + 7) / 8);
     const int known_tiles = ((s.H + 15) / 16) * ((s.W + 15) / 16);
     hipLaunchKernelGGL(trunk_kernel, dim3(conv_tiles + known_tiles + 1), dim3(TB), 0, stream, s);
-    hipLaunchKernelGGL(net_kernel, dim3(((s.H + NT_Y - 1) / NT_Y) * ((s.W + NT_X - 1) / NT_X)), dim3(256),
+    const int net_tiles = ((s.H + NT_Y - 1) / NT_Y) * ((s.W + NT_X - 1) / NT_X);
+    hipLaunchKernelGGL(net_kernel, dim3(8 * ((net_tiles + 7) / 8)), dim3(256),
                        net_lds_bytes(s.U), stream, s, a);
     return hipGetLastError();
 }
