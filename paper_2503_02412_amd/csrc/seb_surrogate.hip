@@ -13,8 +13,8 @@
 // mean of its known 8-neighbours.  Flagged states -- no reference, too few
 // known cells in the window (out of the training distribution), or predicted
 // risk within `band` of risk_max -- are marked in a per-state mask; the plain
-// method then re-assesses exactly those, compacted block by block
-// (launch_assess_flagged: compact_kernel, then flagged_kernel).
+// method then re-assesses exactly those, from the per-block row lists the
+// network's kernel writes (launch_assess_flagged: flagged_kernel).
 #include <cmath>
 
 #include "seb.h"
