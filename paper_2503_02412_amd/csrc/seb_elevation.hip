@@ -300,10 +300,20 @@ __global__ __launch_bounds__(256) void fuse_large_kernel(const FuseArgs f, FuseW
             const int64_t at = (int64_t)((ly + f.ry) % f.H) * f.ld + (lx + f.rx) % f.W;
             double h = (double)f.height[at], v = (double)f.variance[at];
             int32_t used = 0;
-            for (int k = 0; k < n; ++k) {
-                const double zi = n <= CAP ? zs[k] : w.z[b[k]];
-                const double si = n <= CAP ? ss[k] : w.var[b[k]];
-                used += fold_point(h, v, zi, si, f.tau2);
+            if (n <= CAP) {
+                // the next point's (z, var) is read from LDS while this one
+                // folds, so its latency hides behind the divisions
+                double zn = n > 0 ? zs[0] : 0.0, sn = n > 0 ? ss[0] : 0.0;
+                for (int k = 0; k < n; ++k) {
+                    const double zi = zn, si = sn;
+                    if (k + 1 < n) {
+                        zn = zs[k + 1];
+                        sn = ss[k + 1];
+                    }
+                    used += fold_point(h, v, zi, si, f.tau2);
+                }
+            } else {
+                for (int k = 0; k < n; ++k) used += fold_point(h, v, w.z[b[k]], w.var[b[k]], f.tau2);
             }
             f.height[at] = (float)h;
             f.variance[at] = (float)v;
