@@ -384,24 +384,48 @@ __global__ __launch_bounds__(256) void reduce_split_kernel(const float* part, in
     }
 }
 
-// Column sums of the first N columns of a bf16 matrix D [M][ld] (N a power of
-// two <= 256), optionally weighted by w[m][0/1], in two passes.  Block b sums
-// rows [b * rows, (b + 1) * rows): thread t takes column t % N and every
-// (256 / N)-th row from row t / N on, so 256 / N rows are read per step; the
-// row lanes are then added in order through LDS into partial[b][N][nw].  The
-// final pass adds the blocks' partials of one output per block (a fixed-order
-// tree), so the sums are deterministic.
-__global__ __launch_bounds__(256) void colsum_kernel(const bf16* D, int64_t ld, int M, int N, int rows,
-                                                     const float* w, float* partial) {
+// Column sums of the first N columns of bf16 matrices D [M][ld] (N a power
+// of two <= 256), optionally weighted by w[m][0/1]: the bias gradients of
+// every layer in one pair of launches at the end of the backward pass.  Job
+// j covers blocks [block0_j, block0_j + blocks_j) of the first pass, and
+// block b of a job sums rows [b * rows, (b + 1) * rows): thread t takes
+// column t % N and every (256 / N)-th row from row t / N on, so 256 / N rows
+// are read per step; the row lanes are then added in order through LDS into
+// the job's partial[b][N][nw].  The second pass adds the blocks' partials of
+// one output per workgroup (a fixed-order tree), so the sums are
+// deterministic.  Products and sums are rounded one at a time.
+struct ColJob {
+    const bf16* D;
+    int64_t ld;
+    int M, N, rows, blocks, block0, out0;
+    const float* w;     // [M][2] row weights, or null
+    float* part;        // the job's partial sums
+    float* dst;         // N (or 2N, interleaved) outputs
+};
+constexpr int kColJobs = 6;
+static_assert(NOUT + H2 + 2 * H1 + H1 + C2 + C1 <= 512, "partials of every job fit kColBlocks x 512");
+struct ColJobs {
+    ColJob j[kColJobs];
+    int n;
+};
+
+__global__ __launch_bounds__(256) void colsum_kernel(const ColJobs J) {
+#pragma clang fp contract(off)
     __shared__ float red[2][256];
+    int k = 0;
+    for (int q = 1; q < J.n; ++q)
+        if ((int)blockIdx.x >= J.j[q].block0) k = q;
+    const ColJob& jb = J.j[k];
+    const int N = jb.N, M = jb.M;
+    const int blk = blockIdx.x - jb.block0;
     const int t = threadIdx.x, c = t & (N - 1), lanes = 256 / N;
-    const int r0 = blockIdx.x * rows, r1 = min(M, r0 + rows);
+    const int r0 = blk * jb.rows, r1 = min(M, r0 + jb.rows);
     float s0 = 0.f, s1 = 0.f;
     for (int m = r0 + t / N; m < r1; m += lanes) {
-        const float v = from_bf16(D[(int64_t)m * ld + c]);
-        if (w) {
-            s0 += v * w[2 * m];
-            s1 += v * w[2 * m + 1];
+        const float v = from_bf16(jb.D[(int64_t)m * jb.ld + c]);
+        if (jb.w) {
+            s0 += v * jb.w[2 * m];
+            s1 += v * jb.w[2 * m + 1];
         } else {
             s0 += v;
         }
@@ -415,28 +439,32 @@ __global__ __launch_bounds__(256) void colsum_kernel(const bf16* D, int64_t ld, 
             a0 += red[0][t + N * j];
             a1 += red[1][t + N * j];
         }
-        if (w) {
-            partial[((int64_t)blockIdx.x * N + t) * 2] = a0;
-            partial[((int64_t)blockIdx.x * N + t) * 2 + 1] = a1;
+        if (jb.w) {
+            jb.part[((int64_t)blk * N + t) * 2] = a0;
+            jb.part[((int64_t)blk * N + t) * 2 + 1] = a1;
         } else {
-            partial[(int64_t)blockIdx.x * N + t] = a0;
+            jb.part[(int64_t)blk * N + t] = a0;
         }
     }
 }
 
-__global__ __launch_bounds__(256) void colsum_finish_kernel(const float* partial, int nblk, int cnt,
-                                                            float* dst) {
+__global__ __launch_bounds__(256) void colsum_finish_kernel(const ColJobs J) {
     __shared__ float red[256];
-    const int i = blockIdx.x, t = threadIdx.x;       // output i
+    int k = 0;
+    for (int q = 1; q < J.n; ++q)
+        if ((int)blockIdx.x >= J.j[q].out0) k = q;
+    const ColJob& jb = J.j[k];
+    const int cnt = jb.N * (jb.w ? 2 : 1);
+    const int i = blockIdx.x - jb.out0, t = threadIdx.x;       // output i of the job
     float s = 0.f;
-    for (int b = t; b < nblk; b += 256) s += partial[(int64_t)b * cnt + i];
+    for (int b = t; b < jb.blocks; b += 256) s += jb.part[(int64_t)b * cnt + i];
     red[t] = s;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (t < o) red[t] += red[t + o];
         __syncthreads();
     }
-    if (t == 0) dst[i] = red[0];
+    if (t == 0) jb.dst[i] = red[0];
 }
 
 __global__ __launch_bounds__(256) void adam_kernel(float* theta, float* m, float* v, const float* g,
@@ -623,17 +651,44 @@ void weight_grad(seb_net* n, const bf16* A, const bf16* B, int M, int Nn, int K,
                        0, s, n->part, Z, M, Nn, kind, per, dst);
 }
 
-void colsum(seb_net* n, const bf16* D, int64_t ld, int M, int Nn, const float* w, float* dst,
-            hipStream_t s) {
+// Adds a column-sum job (see colsum_kernel) to J; run_colsums launches them.
+void add_colsum(N::ColJobs& J, seb_net* n, const bf16* D, int64_t ld, int M, int Nn, const float* w,
+                float* dst) {
     // rows per block: kColSteps steps of 256 / Nn rows, more when that would
     // need more than kColBlocks blocks
     const int lanes = 256 / Nn;
     const int64_t per = std::max<int64_t>((int64_t)lanes * kColSteps, ((int64_t)M + kColBlocks - 1) / kColBlocks);
     const int rows = (int)((per + lanes - 1) / lanes * lanes);
     const int blocks = std::max(1, (int)(((int64_t)M + rows - 1) / rows));
-    hipLaunchKernelGGL(N::colsum_kernel, dim3(blocks), dim3(256), 0, s, D, ld, M, Nn, rows, w, n->cpart);
-    const int cnt = Nn * (w ? 2 : 1);
-    hipLaunchKernelGGL(N::colsum_finish_kernel, dim3(cnt), dim3(256), 0, s, n->cpart, blocks, cnt, dst);
+    N::ColJob& jb = J.j[J.n];
+    float* part = n->cpart;
+    int block0 = 0, out0 = 0;
+    if (J.n > 0) {
+        const N::ColJob& pj = J.j[J.n - 1];
+        const int pnw = pj.w ? 2 : 1;
+        part = pj.part + (int64_t)pj.blocks * pj.N * pnw;
+        block0 = pj.block0 + pj.blocks;
+        out0 = pj.out0 + pj.N * pnw;
+    }
+    jb.D = D;
+    jb.ld = ld;
+    jb.M = M;
+    jb.N = Nn;
+    jb.rows = rows;
+    jb.blocks = blocks;
+    jb.block0 = block0;
+    jb.out0 = out0;
+    jb.w = w;
+    jb.part = part;
+    jb.dst = dst;
+    J.n += 1;
+}
+
+void run_colsums(const N::ColJobs& J, hipStream_t s) {
+    const N::ColJob& last = J.j[J.n - 1];
+    hipLaunchKernelGGL(N::colsum_kernel, dim3(last.block0 + last.blocks), dim3(256), 0, s, J);
+    hipLaunchKernelGGL(N::colsum_finish_kernel, dim3(last.out0 + last.N * (last.w ? 2 : 1)), dim3(256), 0,
+                       s, J);
 }
 
 int check_batch(const seb_net* n, const seb_train_batch* b, bool need_labels) {
@@ -770,7 +825,7 @@ int seb_net_create(uint64_t seed, int32_t max_batch, seb_net** out) {
               dalloc(n, &n->dyt, Bm * 32) && dalloc(n, &n->y, Bm * N::NOUT) &&
               dalloc(n, &n->tgt, Bm * N::NOUT) && dalloc(n, &n->sc, Bm * 2) &&
               dalloc(n, &n->part, part_floats(Bm)) && dalloc(n, &n->lpart, Bm / 256 + 1) &&
-              dalloc(n, &n->cpart, kColBlocks * 512);
+              dalloc(n, &n->cpart, kColBlocks * 512);   // >= kColBlocks x (sum of N x nw of the jobs)
     if (!ok) {
         seb_net_destroy(n);
         return net_fail(SEB_ERR_ALLOC, "device allocation failed");
@@ -890,6 +945,8 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     if (loss_dev) hipLaunchKernelGGL(N::finish_loss_kernel, dim3(1), dim3(64), 0, s, n->lpart, lb, B,
                                      loss_dev);
     transpose(n->dy, B, 32, 32, n->dyt, B, s);
+    N::ColJobs cj;
+    cj.n = 0;
     // fc3
     N::GemmArgs ga = gemm_args(n->dy, 32, n->pw.w5t, 32, B, N::H2, 32);
     ga.gate = n->h2;
@@ -899,7 +956,7 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     gemm(ga, s);
     transpose(n->h2, B, N::H2, N::H2, n->h2t, B, s);
     weight_grad(n, n->dyt, n->h2t, N::NOUT, N::H2, B, kFcChunk, 0, g + N::OFF_W5, s);
-    colsum(n, n->dy, 32, B, N::NOUT, nullptr, g + N::OFF_B5, s);
+    add_colsum(cj, n, n->dy, 32, B, N::NOUT, nullptr, g + N::OFF_B5);
     // fc2
     transpose(n->da4, B, N::H2, N::H2, n->da4t, B, s);
     ga = gemm_args(n->da4, N::H2, n->pw.w4t, N::H2, B, N::H1, N::H2);
@@ -910,7 +967,7 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     gemm(ga, s);
     transpose(n->h1, B, N::H1, N::H1, n->h1t, B, s);
     weight_grad(n, n->da4t, n->h1t, N::H2, N::H1, B, kFcChunk, 0, g + N::OFF_W4, s);
-    colsum(n, n->da4, N::H2, B, N::H2, nullptr, g + N::OFF_B4, s);
+    add_colsum(cj, n, n->da4, N::H2, B, N::H2, nullptr, g + N::OFF_B4);
     // fc1
     transpose(n->da3, B, N::H1, N::H1, n->da3t, B, s);
     ga = gemm_args(n->da3, N::H1, n->pw.w3t, N::H1, B, N::F, N::H1);
@@ -921,8 +978,8 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     gemm(ga, s);
     transpose(n->f, B, N::F, N::F, n->ft, B, s);
     weight_grad(n, n->da3t, n->ft, N::H1, N::F, B, kFcChunk, 0, g + N::OFF_W3, s);
-    colsum(n, n->da3, N::H1, B, N::H1, n->sc, g + N::OFF_WY, s);
-    colsum(n, n->da3, N::H1, B, N::H1, nullptr, g + N::OFF_B3, s);
+    add_colsum(cj, n, n->da3, N::H1, B, N::H1, n->sc, g + N::OFF_WY);
+    add_colsum(cj, n, n->da3, N::H1, B, N::H1, nullptr, g + N::OFF_B3);
     // conv2 (da2 viewed as [B*25][32])
     ga = gemm_args(n->da2, N::C2, n->pw.w2t, N::C2, r2, N::K2P, N::C2);
     ga.C = n->dA2;
@@ -933,11 +990,12 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     transpose(n->da2, r2, N::C2, N::C2, n->da2t, r2, s);
     transpose(n->A2, r2, N::K2P, N::K2P, n->A2t, r2, s);
     weight_grad(n, n->da2t, n->A2t, N::C2, N::K2P, r2, kConvChunk, 2, g + N::OFF_W2, s);
-    colsum(n, n->da2, N::C2, r2, N::C2, nullptr, g + N::OFF_B2, s);
+    add_colsum(cj, n, n->da2, N::C2, r2, N::C2, nullptr, g + N::OFF_B2);
     // conv1
     transpose(n->da1, r1, N::C1, N::C1, n->da1t, r1, s);
     weight_grad(n, n->da1t, n->A1t, N::C1, N::K1P, r1, kConvChunk, 1, g + N::OFF_W1, s);
-    colsum(n, n->da1, N::C1, r1, N::C1, nullptr, g + N::OFF_B1, s);
+    add_colsum(cj, n, n->da1, N::C1, r1, N::C1, nullptr, g + N::OFF_B1);
+    run_colsums(cj, s);      // every bias gradient, in two launches
 
     if (grad_dev) {
         e = hipMemcpyAsync(grad_dev, g, N::N_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, s);
