@@ -353,34 +353,50 @@ __global__ void finish_loss_kernel(const float* partial, int n, int B, float* ou
     *out = (float)(s / B);
 }
 
-// Sum of the split-K partial products part[z][M][N] over z, written to the
-// gradient in the parameter layout (kind 0: [M][N]; 1: conv1's first K1 of
-// K1P columns; 2: conv2's (tap, channel) columns to (channel, tap)).  A
-// workgroup adds `per` outputs (64, 16 or 8): thread (o, q) sums z = q,
-// q + L, ... with L = 256 / per lanes (coalesced over o), and the lanes are
-// added in a fixed order.
-__global__ __launch_bounds__(256) void reduce_split_kernel(const float* part, int Z, int M, int N,
-                                                           int kind, int per, float* dst) {
+// Sums of the split-K partial products part[z][M][N] over z, written to the
+// gradients in the parameter layout (kind 0: [M][N]; 1: conv1's first K1 of
+// K1P columns; 2: conv2's (tap, channel) columns to (channel, tap)), for every
+// weight gradient in one launch at the end of the backward pass.  Job j
+// covers workgroups [block0_j, block0_j + blocks_j); a workgroup adds `per`
+// outputs (64, 16 or 8): thread (o, q) sums z = q, q + L, ... with
+// L = 256 / per lanes (coalesced over o), and the lanes are added in a fixed
+// order.
+struct RedJob {
+    const float* part;
+    int Z, M, N, kind, per, blocks, block0;
+    float* dst;
+};
+constexpr int kRedJobs = 5;
+struct RedJobs {
+    RedJob j[kRedJobs];
+    int n;
+};
+
+__global__ __launch_bounds__(256) void reduce_split_kernel(const RedJobs J) {
     __shared__ float red[256];
-    const int L = 256 / per;
+    int k = 0;
+    for (int q = 1; q < J.n; ++q)
+        if ((int)blockIdx.x >= J.j[q].block0) k = q;
+    const RedJob& jb = J.j[k];
+    const int per = jb.per, L = 256 / per, N = jb.N;
     const int o = threadIdx.x % per, q = threadIdx.x / per;
-    const int idx = blockIdx.x * per + o;
-    const int64_t mn = (int64_t)M * N;
+    const int idx = ((int)blockIdx.x - jb.block0) * per + o;
+    const int64_t mn = (int64_t)jb.M * N;
     float s = 0.f;
     if (idx < mn)
-        for (int z = q; z < Z; z += L) s += part[(int64_t)z * mn + idx];
+        for (int z = q; z < jb.Z; z += L) s += jb.part[(int64_t)z * mn + idx];
     red[threadIdx.x] = s;
     __syncthreads();
     if (q != 0 || idx >= mn) return;
     s = red[o];
     for (int j = 1; j < L; ++j) s += red[o + per * j];
     const int m = idx / N, n = idx % N;
-    if (kind == 0) {
-        dst[idx] = s;
-    } else if (kind == 1) {
-        if (n < K1) dst[m * K1 + n] = s;
+    if (jb.kind == 0) {
+        jb.dst[idx] = s;
+    } else if (jb.kind == 1) {
+        if (n < K1) jb.dst[m * K1 + n] = s;
     } else {
-        if (n < K2) dst[m * K2 + (n % 16) * 9 + n / 16] = s;
+        if (n < K2) jb.dst[m * K2 + (n % 16) * 9 + n / 16] = s;
     }
 }
 
@@ -591,11 +607,12 @@ constexpr int kFcChunk = 256, kConvChunk = 1024;
 
 int64_t part_floats(int64_t Bm) {
     auto z = [](int64_t K, int64_t chunk) { return (K + chunk - 1) / chunk; };
+    // every layer's partial products side by side (one reduction launch)
     int64_t m = z(Bm, kFcChunk) * N::H1 * N::F;
-    m = std::max(m, z(Bm, kFcChunk) * N::H2 * N::H1);
-    m = std::max(m, z(Bm, kFcChunk) * N::NOUT * N::H2);
-    m = std::max(m, z(Bm * N::P2 * N::P2, kConvChunk) * N::C2 * N::K2P);
-    m = std::max(m, z(Bm * N::P1 * N::P1, kConvChunk) * N::C1 * N::K1P);
+    m += z(Bm, kFcChunk) * N::H2 * N::H1;
+    m += z(Bm, kFcChunk) * N::NOUT * N::H2;
+    m += z(Bm * N::P2 * N::P2, kConvChunk) * N::C2 * N::K2P;
+    m += z(Bm * N::P1 * N::P1, kConvChunk) * N::C1 * N::K1P;
     return m;
 }
 
@@ -636,19 +653,42 @@ void transpose(const bf16* src, int R, int C, int64_t lds, bf16* dst, int64_t ld
     hipLaunchKernelGGL(N::transpose_kernel, grid, dim3(256), 0, s, src, R, C, lds, dst, ldd);
 }
 
-// Weight gradient dst = A^T-style NT GEMM of [M][K] and [Nn][K] with split-K.
-void weight_grad(seb_net* n, const bf16* A, const bf16* B, int M, int Nn, int K, int kchunk,
-                 int kind, float* dst, hipStream_t s) {
+// Weight gradient dst = A^T-style NT GEMM of [M][K] and [Nn][K] with split-K
+// into the layer's own region of n->part; its reduction is added to R and
+// runs with the others (run_reductions).
+void weight_grad(seb_net* n, N::RedJobs& R, const bf16* A, const bf16* B, int M, int Nn, int K,
+                 int kchunk, int kind, float* dst, hipStream_t s) {
+    float* part = n->part;
+    int block0 = 0;
+    if (R.n > 0) {
+        const N::RedJob& pj = R.j[R.n - 1];
+        part = const_cast<float*>(pj.part) + (int64_t)pj.Z * pj.M * pj.N;
+        block0 = pj.block0 + pj.blocks;
+    }
     N::GemmArgs g = gemm_args(A, K, B, K, M, Nn, K);
     g.kchunk = kchunk;
     g.split = (int64_t)M * Nn;
-    g.C = n->part;
+    g.C = part;
     g.ldc = Nn;
     gemm(g, s);
     const int Z = (K + kchunk - 1) / kchunk;
     const int per = Z >= 64 ? 8 : Z >= 16 ? 16 : 64;      // outputs per workgroup
-    hipLaunchKernelGGL(N::reduce_split_kernel, dim3((unsigned)(((int64_t)M * Nn + per - 1) / per)), dim3(256),
-                       0, s, n->part, Z, M, Nn, kind, per, dst);
+    N::RedJob& jb = R.j[R.n];
+    jb.part = part;
+    jb.Z = Z;
+    jb.M = M;
+    jb.N = Nn;
+    jb.kind = kind;
+    jb.per = per;
+    jb.blocks = (int)(((int64_t)M * Nn + per - 1) / per);
+    jb.block0 = block0;
+    jb.dst = dst;
+    R.n += 1;
+}
+
+void run_reductions(const N::RedJobs& R, hipStream_t s) {
+    const N::RedJob& last = R.j[R.n - 1];
+    hipLaunchKernelGGL(N::reduce_split_kernel, dim3(last.block0 + last.blocks), dim3(256), 0, s, R);
 }
 
 // Adds a column-sum job (see colsum_kernel) to J; run_colsums launches them.
@@ -947,6 +987,8 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     transpose(n->dy, B, 32, 32, n->dyt, B, s);
     N::ColJobs cj;
     cj.n = 0;
+    N::RedJobs rj;
+    rj.n = 0;
     // fc3
     N::GemmArgs ga = gemm_args(n->dy, 32, n->pw.w5t, 32, B, N::H2, 32);
     ga.gate = n->h2;
@@ -955,7 +997,7 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     ga.ldcb = N::H2;
     gemm(ga, s);
     transpose(n->h2, B, N::H2, N::H2, n->h2t, B, s);
-    weight_grad(n, n->dyt, n->h2t, N::NOUT, N::H2, B, kFcChunk, 0, g + N::OFF_W5, s);
+    weight_grad(n, rj, n->dyt, n->h2t, N::NOUT, N::H2, B, kFcChunk, 0, g + N::OFF_W5, s);
     add_colsum(cj, n, n->dy, 32, B, N::NOUT, nullptr, g + N::OFF_B5);
     // fc2
     transpose(n->da4, B, N::H2, N::H2, n->da4t, B, s);
@@ -966,7 +1008,7 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     ga.ldcb = N::H1;
     gemm(ga, s);
     transpose(n->h1, B, N::H1, N::H1, n->h1t, B, s);
-    weight_grad(n, n->da4t, n->h1t, N::H2, N::H1, B, kFcChunk, 0, g + N::OFF_W4, s);
+    weight_grad(n, rj, n->da4t, n->h1t, N::H2, N::H1, B, kFcChunk, 0, g + N::OFF_W4, s);
     add_colsum(cj, n, n->da4, N::H2, B, N::H2, nullptr, g + N::OFF_B4);
     // fc1
     transpose(n->da3, B, N::H1, N::H1, n->da3t, B, s);
@@ -977,7 +1019,7 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     ga.ldcb = N::F;
     gemm(ga, s);
     transpose(n->f, B, N::F, N::F, n->ft, B, s);
-    weight_grad(n, n->da3t, n->ft, N::H1, N::F, B, kFcChunk, 0, g + N::OFF_W3, s);
+    weight_grad(n, rj, n->da3t, n->ft, N::H1, N::F, B, kFcChunk, 0, g + N::OFF_W3, s);
     add_colsum(cj, n, n->da3, N::H1, B, N::H1, n->sc, g + N::OFF_WY);
     add_colsum(cj, n, n->da3, N::H1, B, N::H1, nullptr, g + N::OFF_B3);
     // conv2 (da2 viewed as [B*25][32])
@@ -989,13 +1031,14 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
                        n->dA2, n->o1, n->da1, B);
     transpose(n->da2, r2, N::C2, N::C2, n->da2t, r2, s);
     transpose(n->A2, r2, N::K2P, N::K2P, n->A2t, r2, s);
-    weight_grad(n, n->da2t, n->A2t, N::C2, N::K2P, r2, kConvChunk, 2, g + N::OFF_W2, s);
+    weight_grad(n, rj, n->da2t, n->A2t, N::C2, N::K2P, r2, kConvChunk, 2, g + N::OFF_W2, s);
     add_colsum(cj, n, n->da2, N::C2, r2, N::C2, nullptr, g + N::OFF_B2);
     // conv1
     transpose(n->da1, r1, N::C1, N::C1, n->da1t, r1, s);
-    weight_grad(n, n->da1t, n->A1t, N::C1, N::K1P, r1, kConvChunk, 1, g + N::OFF_W1, s);
+    weight_grad(n, rj, n->da1t, n->A1t, N::C1, N::K1P, r1, kConvChunk, 1, g + N::OFF_W1, s);
     add_colsum(cj, n, n->da1, N::C1, r1, N::C1, nullptr, g + N::OFF_B1);
     run_colsums(cj, s);      // every bias gradient, in two launches
+    run_reductions(rj, s);   // every weight gradient's split sums, in one
 
     if (grad_dev) {
         e = hipMemcpyAsync(grad_dev, g, N::N_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, s);
