@@ -279,18 +279,40 @@ __global__ __launch_bounds__(256) void col2im2_kernel(const float* dA2, const bf
     da1[o + 3] = to_bf16(from_bf16(o1[o + 3]) > 0.f ? s.w : 0.f);
 }
 
-// Tiled transpose of a bf16 matrix: dst[c][r] = src[r][c].  A workgroup
-// moves a 64 x 64 tile through LDS; each thread reads two 16-byte runs of a
-// source row and writes two 16-byte runs of a destination row (element by
-// element where a run is cut by the matrix edge or is not 16-byte aligned).
-__global__ __launch_bounds__(256) void transpose_kernel(const bf16* src, int R, int Ccols,
-                                                        int64_t lds, bf16* dst, int64_t ldd) {
+// Tiled transposes of bf16 matrices, dst[c][r] = src[r][c], all of a
+// backward pass's in one launch: job j covers workgroups [block0_j, block0_j
+// + tiles_x_j * tiles_y_j).  A workgroup moves a 64 x 64 tile through LDS;
+// each thread reads two 16-byte runs of a source row and writes two 16-byte
+// runs of a destination row (element by element where a run is cut by the
+// matrix edge or is not 16-byte aligned).
+struct TrJob {
+    const bf16* src;
+    int R, C;
+    int64_t lds;
+    bf16* dst;
+    int64_t ldd;
+    int tiles_x, block0;
+};
+constexpr int kTrJobs = 9;
+struct TrJobs {
+    TrJob j[kTrJobs];
+    int n;
+};
+
+__global__ __launch_bounds__(256) void transpose_kernel(const TrJobs J) {
     typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
     __shared__ uint16_t tile[64][66];
+    int jk = 0;
+    for (int q = 1; q < J.n; ++q)
+        if ((int)blockIdx.x >= J.j[q].block0) jk = q;
+    const TrJob& jb = J.j[jk];
+    const int R = jb.R, Ccols = jb.C;
+    const int64_t lds = jb.lds, ldd = jb.ldd;
+    const int tb = (int)blockIdx.x - jb.block0;
     const int t = threadIdx.x;
-    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
-    const uint16_t* s16 = reinterpret_cast<const uint16_t*>(src);
-    uint16_t* d16 = reinterpret_cast<uint16_t*>(dst);
+    const int r0 = (tb / jb.tiles_x) * 64, c0 = (tb % jb.tiles_x) * 64;
+    const uint16_t* s16 = reinterpret_cast<const uint16_t*>(jb.src);
+    uint16_t* d16 = reinterpret_cast<uint16_t*>(jb.dst);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const int rr = (t >> 3) + 32 * k, cc = (t & 7) * 8;
@@ -648,9 +670,30 @@ N::GemmArgs gemm_args(const bf16* A, int64_t lda, const bf16* B, int64_t ldb, in
     return g;
 }
 
-void transpose(const bf16* src, int R, int C, int64_t lds, bf16* dst, int64_t ldd, hipStream_t s) {
-    dim3 grid((C + 63) / 64, (R + 63) / 64);
-    hipLaunchKernelGGL(N::transpose_kernel, grid, dim3(256), 0, s, src, R, C, lds, dst, ldd);
+// Adds the transpose dst = src^T (src [R][C], row strides lds and ldd) to T;
+// run_transposes launches them.
+void add_transpose(N::TrJobs& T, const bf16* src, int R, int C, int64_t lds, bf16* dst, int64_t ldd) {
+    N::TrJob& jb = T.j[T.n];
+    int block0 = 0;
+    if (T.n > 0) {
+        const N::TrJob& pj = T.j[T.n - 1];
+        block0 = pj.block0 + pj.tiles_x * ((pj.R + 63) / 64);
+    }
+    jb.src = src;
+    jb.R = R;
+    jb.C = C;
+    jb.lds = lds;
+    jb.dst = dst;
+    jb.ldd = ldd;
+    jb.tiles_x = (C + 63) / 64;
+    jb.block0 = block0;
+    T.n += 1;
+}
+
+void run_transposes(const N::TrJobs& T, hipStream_t s) {
+    const N::TrJob& last = T.j[T.n - 1];
+    hipLaunchKernelGGL(N::transpose_kernel, dim3(last.block0 + last.tiles_x * ((last.R + 63) / 64)), dim3(256),
+                       0, s, T);
 }
 
 // Weight gradient dst = A^T-style NT GEMM of [M][K] and [Nn][K] with split-K
@@ -984,11 +1027,7 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
                        n->dy, n->lpart);
     if (loss_dev) hipLaunchKernelGGL(N::finish_loss_kernel, dim3(1), dim3(64), 0, s, n->lpart, lb, B,
                                      loss_dev);
-    transpose(n->dy, B, 32, 32, n->dyt, B, s);
-    N::ColJobs cj;
-    cj.n = 0;
-    N::RedJobs rj;
-    rj.n = 0;
+    // Input gradients, layer by layer, gated by the forward pass's ReLUs.
     // fc3
     N::GemmArgs ga = gemm_args(n->dy, 32, n->pw.w5t, 32, B, N::H2, 32);
     ga.gate = n->h2;
@@ -996,46 +1035,57 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     ga.Cb = n->da4;
     ga.ldcb = N::H2;
     gemm(ga, s);
-    transpose(n->h2, B, N::H2, N::H2, n->h2t, B, s);
-    weight_grad(n, rj, n->dyt, n->h2t, N::NOUT, N::H2, B, kFcChunk, 0, g + N::OFF_W5, s);
-    add_colsum(cj, n, n->dy, 32, B, N::NOUT, nullptr, g + N::OFF_B5);
     // fc2
-    transpose(n->da4, B, N::H2, N::H2, n->da4t, B, s);
     ga = gemm_args(n->da4, N::H2, n->pw.w4t, N::H2, B, N::H1, N::H2);
     ga.gate = n->h1;
     ga.ldg = N::H1;
     ga.Cb = n->da3;
     ga.ldcb = N::H1;
     gemm(ga, s);
-    transpose(n->h1, B, N::H1, N::H1, n->h1t, B, s);
-    weight_grad(n, rj, n->da4t, n->h1t, N::H2, N::H1, B, kFcChunk, 0, g + N::OFF_W4, s);
-    add_colsum(cj, n, n->da4, N::H2, B, N::H2, nullptr, g + N::OFF_B4);
     // fc1
-    transpose(n->da3, B, N::H1, N::H1, n->da3t, B, s);
     ga = gemm_args(n->da3, N::H1, n->pw.w3t, N::H1, B, N::F, N::H1);
     ga.gate = n->f;
     ga.ldg = N::F;
     ga.Cb = n->da2;
     ga.ldcb = N::F;
     gemm(ga, s);
-    transpose(n->f, B, N::F, N::F, n->ft, B, s);
-    weight_grad(n, rj, n->da3t, n->ft, N::H1, N::F, B, kFcChunk, 0, g + N::OFF_W3, s);
-    add_colsum(cj, n, n->da3, N::H1, B, N::H1, n->sc, g + N::OFF_WY);
-    add_colsum(cj, n, n->da3, N::H1, B, N::H1, nullptr, g + N::OFF_B3);
-    // conv2 (da2 viewed as [B*25][32])
+    // conv2 (da2 viewed as [B*25][32]), then conv1's through col2im
     ga = gemm_args(n->da2, N::C2, n->pw.w2t, N::C2, r2, N::K2P, N::C2);
     ga.C = n->dA2;
     ga.ldc = N::K2P;
     gemm(ga, s);
     hipLaunchKernelGGL(N::col2im2_kernel, dim3(blocks_for((int64_t)r1 * (N::C1 / 4))), dim3(256), 0, s,
                        n->dA2, n->o1, n->da1, B);
-    transpose(n->da2, r2, N::C2, N::C2, n->da2t, r2, s);
-    transpose(n->A2, r2, N::K2P, N::K2P, n->A2t, r2, s);
+    // The weight gradients' operands, transposed in one launch (conv1's
+    // im2col was laid out transposed by the forward pass).
+    N::TrJobs tj;
+    tj.n = 0;
+    add_transpose(tj, n->dy, B, 32, 32, n->dyt, B);
+    add_transpose(tj, n->h2, B, N::H2, N::H2, n->h2t, B);
+    add_transpose(tj, n->da4, B, N::H2, N::H2, n->da4t, B);
+    add_transpose(tj, n->h1, B, N::H1, N::H1, n->h1t, B);
+    add_transpose(tj, n->da3, B, N::H1, N::H1, n->da3t, B);
+    add_transpose(tj, n->f, B, N::F, N::F, n->ft, B);
+    add_transpose(tj, n->da2, r2, N::C2, N::C2, n->da2t, r2);
+    add_transpose(tj, n->A2, r2, N::K2P, N::K2P, n->A2t, r2);
+    add_transpose(tj, n->da1, r1, N::C1, N::C1, n->da1t, r1);
+    run_transposes(tj, s);
+    // Weight gradients (split-K products now, their sums below) and bias
+    // gradients.
+    N::RedJobs rj;
+    rj.n = 0;
+    weight_grad(n, rj, n->dyt, n->h2t, N::NOUT, N::H2, B, kFcChunk, 0, g + N::OFF_W5, s);
+    weight_grad(n, rj, n->da4t, n->h1t, N::H2, N::H1, B, kFcChunk, 0, g + N::OFF_W4, s);
+    weight_grad(n, rj, n->da3t, n->ft, N::H1, N::F, B, kFcChunk, 0, g + N::OFF_W3, s);
     weight_grad(n, rj, n->da2t, n->A2t, N::C2, N::K2P, r2, kConvChunk, 2, g + N::OFF_W2, s);
-    add_colsum(cj, n, n->da2, N::C2, r2, N::C2, nullptr, g + N::OFF_B2);
-    // conv1
-    transpose(n->da1, r1, N::C1, N::C1, n->da1t, r1, s);
     weight_grad(n, rj, n->da1t, n->A1t, N::C1, N::K1P, r1, kConvChunk, 1, g + N::OFF_W1, s);
+    N::ColJobs cj;
+    cj.n = 0;
+    add_colsum(cj, n, n->dy, 32, B, N::NOUT, nullptr, g + N::OFF_B5);
+    add_colsum(cj, n, n->da4, N::H2, B, N::H2, nullptr, g + N::OFF_B4);
+    add_colsum(cj, n, n->da3, N::H1, B, N::H1, n->sc, g + N::OFF_WY);
+    add_colsum(cj, n, n->da3, N::H1, B, N::H1, nullptr, g + N::OFF_B3);
+    add_colsum(cj, n, n->da2, N::C2, r2, N::C2, nullptr, g + N::OFF_B2);
     add_colsum(cj, n, n->da1, N::C1, r1, N::C1, nullptr, g + N::OFF_B1);
     run_colsums(cj, s);      // every bias gradient, in two launches
     run_reductions(rj, s);   // every weight gradient's split sums, in one
