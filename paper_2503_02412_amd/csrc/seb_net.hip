@@ -36,11 +36,11 @@ __device__ __forceinline__ float from_bf16(bf16 h) {
 // Operand fragments are loaded straight from global memory: lane l holds
 // row (l % 16) and k-block 8 (l / 16) of its 16 x 32 A and B slices; the
 // accumulator of lane l holds rows 4 (l / 16) + e, column l % 16.
-__global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmArgs g) {
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int bx, int by, int bz) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m0 = blockIdx.x * 64 + (wave >> 1) * 32;
-    const int n0 = blockIdx.y * 64 + (wave & 1) * 32;
-    const int kb = blockIdx.z * g.kchunk;
+    const int m0 = bx * 64 + (wave >> 1) * 32;
+    const int n0 = by * 64 + (wave & 1) * 32;
+    const int kb = bz * g.kchunk;
     const int ke = min(g.K, kb + g.kchunk);
     const int r = lane & 15, kq = (lane >> 4) * 8;
     f32x4 acc[2][2];
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmArgs g) {
                 if (m >= g.M || n >= g.N) continue;
                 float v = acc[i][j][e];
                 if (g.split) {
-                    g.C[blockIdx.z * g.split + (int64_t)m * g.ldc + n] = v;
+                    g.C[bz * g.split + (int64_t)m * g.ldc + n] = v;
                     continue;
                 }
                 if (g.bias) v += g.bias[n];
@@ -106,6 +106,29 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmArgs g) {
                 if (g.C) g.C[(int64_t)m * g.ldc + n] = v;
                 if (g.Cb) g.Cb[(int64_t)m * g.ldcb + n] = to_bf16(v);
             }
+}
+
+__global__ __launch_bounds__(256) void gemm_nt_kernel(const GemmArgs g) {
+    gemm_tile(g, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Several independent products in one launch (the weight gradients of a
+// backward pass): product k covers workgroups [block0_k, block0_k + gx_k gy_k
+// gz_k) of a one-dimensional grid, in gemm_nt_kernel's (x, y, z) order.
+constexpr int kGemmGroup = 5;
+struct GemmGroup {
+    GemmArgs a[kGemmGroup];
+    int block0[kGemmGroup], gx[kGemmGroup], gy[kGemmGroup];
+    int n;
+};
+
+__global__ __launch_bounds__(256) void gemm_group_kernel(const GemmGroup G) {
+    int k = 0;
+    for (int q = 1; q < G.n; ++q)
+        if ((int)blockIdx.x >= G.block0[q]) k = q;
+    const int local = (int)blockIdx.x - G.block0[k];
+    const int gx = G.gx[k], gy = G.gy[k];
+    gemm_tile(G.a[k], local % gx, (local / gx) % gy, local / (gx * gy));
 }
 
 // ------------------------------------------------------ patch-form inputs
@@ -656,6 +679,24 @@ hipError_t gemm(const N::GemmArgs& g, hipStream_t s) {
     return hipGetLastError();
 }
 
+int gemm_zcount(const N::GemmArgs& g) { return g.split ? (g.K + g.kchunk - 1) / g.kchunk : 1; }
+
+// Adds the product g to G; run_group launches them together.
+void add_gemm(N::GemmGroup& G, const N::GemmArgs& g) {
+    const int k = G.n;
+    G.a[k] = g;
+    G.gx[k] = (g.M + 63) / 64;
+    G.gy[k] = (g.N + 63) / 64;
+    G.block0[k] = k == 0 ? 0 : G.block0[k - 1] + G.gx[k - 1] * G.gy[k - 1] * gemm_zcount(G.a[k - 1]);
+    G.n += 1;
+}
+
+void run_group(const N::GemmGroup& G, hipStream_t s) {
+    const int k = G.n - 1;
+    const int blocks = G.block0[k] + G.gx[k] * G.gy[k] * gemm_zcount(G.a[k]);
+    hipLaunchKernelGGL(N::gemm_group_kernel, dim3(blocks), dim3(256), 0, s, G);
+}
+
 N::GemmArgs gemm_args(const bf16* A, int64_t lda, const bf16* B, int64_t ldb, int M, int Nn, int K) {
     N::GemmArgs g;
     std::memset(&g, 0, sizeof(g));
@@ -697,10 +738,10 @@ void run_transposes(const N::TrJobs& T, hipStream_t s) {
 }
 
 // Weight gradient dst = A^T-style NT GEMM of [M][K] and [Nn][K] with split-K
-// into the layer's own region of n->part; its reduction is added to R and
-// runs with the others (run_reductions).
-void weight_grad(seb_net* n, N::RedJobs& R, const bf16* A, const bf16* B, int M, int Nn, int K,
-                 int kchunk, int kind, float* dst, hipStream_t s) {
+// into the layer's own region of n->part: the product is added to G (one
+// launch for every layer, run_group) and its reduction to R (run_reductions).
+void weight_grad(seb_net* n, N::GemmGroup& G, N::RedJobs& R, const bf16* A, const bf16* B, int M, int Nn,
+                 int K, int kchunk, int kind, float* dst) {
     float* part = n->part;
     int block0 = 0;
     if (R.n > 0) {
@@ -713,7 +754,7 @@ void weight_grad(seb_net* n, N::RedJobs& R, const bf16* A, const bf16* B, int M,
     g.split = (int64_t)M * Nn;
     g.C = part;
     g.ldc = Nn;
-    gemm(g, s);
+    add_gemm(G, g);
     const int Z = (K + kchunk - 1) / kchunk;
     const int per = Z >= 64 ? 8 : Z >= 16 ? 16 : 64;      // outputs per workgroup
     N::RedJob& jb = R.j[R.n];
@@ -1072,13 +1113,16 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     run_transposes(tj, s);
     // Weight gradients (split-K products now, their sums below) and bias
     // gradients.
+    N::GemmGroup gg;
+    gg.n = 0;
     N::RedJobs rj;
     rj.n = 0;
-    weight_grad(n, rj, n->dyt, n->h2t, N::NOUT, N::H2, B, kFcChunk, 0, g + N::OFF_W5, s);
-    weight_grad(n, rj, n->da4t, n->h1t, N::H2, N::H1, B, kFcChunk, 0, g + N::OFF_W4, s);
-    weight_grad(n, rj, n->da3t, n->ft, N::H1, N::F, B, kFcChunk, 0, g + N::OFF_W3, s);
-    weight_grad(n, rj, n->da2t, n->A2t, N::C2, N::K2P, r2, kConvChunk, 2, g + N::OFF_W2, s);
-    weight_grad(n, rj, n->da1t, n->A1t, N::C1, N::K1P, r1, kConvChunk, 1, g + N::OFF_W1, s);
+    weight_grad(n, gg, rj, n->dyt, n->h2t, N::NOUT, N::H2, B, kFcChunk, 0, g + N::OFF_W5);
+    weight_grad(n, gg, rj, n->da4t, n->h1t, N::H2, N::H1, B, kFcChunk, 0, g + N::OFF_W4);
+    weight_grad(n, gg, rj, n->da3t, n->ft, N::H1, N::F, B, kFcChunk, 0, g + N::OFF_W3);
+    weight_grad(n, gg, rj, n->da2t, n->A2t, N::C2, N::K2P, r2, kConvChunk, 2, g + N::OFF_W2);
+    weight_grad(n, gg, rj, n->da1t, n->A1t, N::C1, N::K1P, r1, kConvChunk, 1, g + N::OFF_W1);
+    run_group(gg, s);
     N::ColJobs cj;
     cj.n = 0;
     add_colsum(cj, n, n->dy, 32, B, N::NOUT, nullptr, g + N::OFF_B5);
