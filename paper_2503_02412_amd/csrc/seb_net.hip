@@ -303,7 +303,7 @@ __global__ __launch_bounds__(256) void col2im2_kernel(const float* dA2, const bf
 }
 
 // Tiled transposes of bf16 matrices, dst[c][r] = src[r][c], all of a
-// backward pass's in one launch: job j covers workgroups [block0_j, block0_j
+// backward pass's in prep_kernel's launch: job j covers workgroups [block0_j, block0_j
 // + tiles_x_j * tiles_y_j).  A workgroup moves a 64 x 64 tile through LDS;
 // each thread reads two 16-byte runs of a source row and writes two 16-byte
 // runs of a destination row (element by element where a run is cut by the
@@ -322,16 +322,16 @@ struct TrJobs {
     int n;
 };
 
-__global__ __launch_bounds__(256) void transpose_kernel(const TrJobs J) {
+__device__ __forceinline__ void transpose_body(const TrJobs& J, int bid) {
     typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
     __shared__ uint16_t tile[64][66];
     int jk = 0;
     for (int q = 1; q < J.n; ++q)
-        if ((int)blockIdx.x >= J.j[q].block0) jk = q;
+        if (bid >= J.j[q].block0) jk = q;
     const TrJob& jb = J.j[jk];
     const int R = jb.R, Ccols = jb.C;
     const int64_t lds = jb.lds, ldd = jb.ldd;
-    const int tb = (int)blockIdx.x - jb.block0;
+    const int tb = bid - jb.block0;
     const int t = threadIdx.x;
     const int r0 = (tb / jb.tiles_x) * 64, c0 = (tb % jb.tiles_x) * 64;
     const uint16_t* s16 = reinterpret_cast<const uint16_t*>(jb.src);
@@ -401,7 +401,7 @@ __global__ void finish_loss_kernel(const float* partial, int n, int B, float* ou
 // Sums of the split-K partial products part[z][M][N] over z, written to the
 // gradients in the parameter layout (kind 0: [M][N]; 1: conv1's first K1 of
 // K1P columns; 2: conv2's (tap, channel) columns to (channel, tap)), for every
-// weight gradient in one launch at the end of the backward pass.  Job j
+// weight gradient, in finish_kernel's launch.  Job j
 // covers workgroups [block0_j, block0_j + blocks_j); a workgroup adds `per`
 // outputs (64, 16 or 8): thread (o, q) sums z = q, q + L, ... with
 // L = 256 / per lanes (coalesced over o), and the lanes are added in a fixed
@@ -417,15 +417,15 @@ struct RedJobs {
     int n;
 };
 
-__global__ __launch_bounds__(256) void reduce_split_kernel(const RedJobs J) {
+__device__ __forceinline__ void reduce_split_body(const RedJobs& J, int bid) {
     __shared__ float red[256];
     int k = 0;
     for (int q = 1; q < J.n; ++q)
-        if ((int)blockIdx.x >= J.j[q].block0) k = q;
+        if (bid >= J.j[q].block0) k = q;
     const RedJob& jb = J.j[k];
     const int per = jb.per, L = 256 / per, N = jb.N;
     const int o = threadIdx.x % per, q = threadIdx.x / per;
-    const int idx = ((int)blockIdx.x - jb.block0) * per + o;
+    const int idx = (bid - jb.block0) * per + o;
     const int64_t mn = (int64_t)jb.M * N;
     float s = 0.f;
     if (idx < mn)
@@ -447,7 +447,7 @@ __global__ __launch_bounds__(256) void reduce_split_kernel(const RedJobs J) {
 
 // Column sums of the first N columns of bf16 matrices D [M][ld] (N a power
 // of two <= 256), optionally weighted by w[m][0/1]: the bias gradients of
-// every layer in one pair of launches at the end of the backward pass.  Job
+// every layer, in prep_kernel's and finish_kernel's launches.  Job
 // j covers blocks [block0_j, block0_j + blocks_j) of the first pass, and
 // block b of a job sums rows [b * rows, (b + 1) * rows): thread t takes
 // column t % N and every (256 / N)-th row from row t / N on, so 256 / N rows
@@ -470,15 +470,15 @@ struct ColJobs {
     int n;
 };
 
-__global__ __launch_bounds__(256) void colsum_kernel(const ColJobs J) {
+__device__ __forceinline__ void colsum_body(const ColJobs& J, int bid) {
 #pragma clang fp contract(off)
     __shared__ float red[2][256];
     int k = 0;
     for (int q = 1; q < J.n; ++q)
-        if ((int)blockIdx.x >= J.j[q].block0) k = q;
+        if (bid >= J.j[q].block0) k = q;
     const ColJob& jb = J.j[k];
     const int N = jb.N, M = jb.M;
-    const int blk = blockIdx.x - jb.block0;
+    const int blk = bid - jb.block0;
     const int t = threadIdx.x, c = t & (N - 1), lanes = 256 / N;
     const int r0 = blk * jb.rows, r1 = min(M, r0 + jb.rows);
     float s0 = 0.f, s1 = 0.f;
@@ -509,14 +509,14 @@ __global__ __launch_bounds__(256) void colsum_kernel(const ColJobs J) {
     }
 }
 
-__global__ __launch_bounds__(256) void colsum_finish_kernel(const ColJobs J) {
+__device__ __forceinline__ void colsum_finish_body(const ColJobs& J, int bid) {
     __shared__ float red[256];
     int k = 0;
     for (int q = 1; q < J.n; ++q)
-        if ((int)blockIdx.x >= J.j[q].out0) k = q;
+        if (bid >= J.j[q].out0) k = q;
     const ColJob& jb = J.j[k];
     const int cnt = jb.N * (jb.w ? 2 : 1);
-    const int i = blockIdx.x - jb.out0, t = threadIdx.x;       // output i of the job
+    const int i = bid - jb.out0, t = threadIdx.x;       // output i of the job
     float s = 0.f;
     for (int b = t; b < jb.blocks; b += 256) s += jb.part[(int64_t)b * cnt + i];
     red[t] = s;
@@ -526,6 +526,25 @@ __global__ __launch_bounds__(256) void colsum_finish_kernel(const ColJobs J) {
         __syncthreads();
     }
     if (t == 0) jb.dst[i] = red[0];
+}
+
+// The backward pass's two launches after its input gradients and products:
+// prep_kernel runs every transpose (workgroups [0, tr_blocks)) and the first
+// pass of every column sum (the rest); finish_kernel adds every column sum's
+// block partials (workgroups [0, col_outputs)) and every weight gradient's
+// split-K partials (the rest).
+__global__ __launch_bounds__(256) void prep_kernel(const TrJobs T, int tr_blocks, const ColJobs C) {
+    if ((int)blockIdx.x < tr_blocks)
+        transpose_body(T, blockIdx.x);
+    else
+        colsum_body(C, (int)blockIdx.x - tr_blocks);
+}
+
+__global__ __launch_bounds__(256) void finish_kernel(const ColJobs C, int col_outputs, const RedJobs R) {
+    if ((int)blockIdx.x < col_outputs)
+        colsum_finish_body(C, blockIdx.x);
+    else
+        reduce_split_body(R, (int)blockIdx.x - col_outputs);
 }
 
 __global__ __launch_bounds__(256) void adam_kernel(float* theta, float* m, float* v, const float* g,
@@ -711,8 +730,8 @@ N::GemmArgs gemm_args(const bf16* A, int64_t lda, const bf16* B, int64_t ldb, in
     return g;
 }
 
-// Adds the transpose dst = src^T (src [R][C], row strides lds and ldd) to T;
-// run_transposes launches them.
+// Adds the transpose dst = src^T (src [R][C], row strides lds and ldd) to T
+// (run by prep_kernel).
 void add_transpose(N::TrJobs& T, const bf16* src, int R, int C, int64_t lds, bf16* dst, int64_t ldd) {
     N::TrJob& jb = T.j[T.n];
     int block0 = 0;
@@ -731,15 +750,14 @@ void add_transpose(N::TrJobs& T, const bf16* src, int R, int C, int64_t lds, bf1
     T.n += 1;
 }
 
-void run_transposes(const N::TrJobs& T, hipStream_t s) {
+int tr_blocks(const N::TrJobs& T) {
     const N::TrJob& last = T.j[T.n - 1];
-    hipLaunchKernelGGL(N::transpose_kernel, dim3(last.block0 + last.tiles_x * ((last.R + 63) / 64)), dim3(256),
-                       0, s, T);
+    return last.block0 + last.tiles_x * ((last.R + 63) / 64);
 }
 
 // Weight gradient dst = A^T-style NT GEMM of [M][K] and [Nn][K] with split-K
 // into the layer's own region of n->part: the product is added to G (one
-// launch for every layer, run_group) and its reduction to R (run_reductions).
+// launch for every layer, run_group) and its reduction to R (finish_kernel).
 void weight_grad(seb_net* n, N::GemmGroup& G, N::RedJobs& R, const bf16* A, const bf16* B, int M, int Nn,
                  int K, int kchunk, int kind, float* dst) {
     float* part = n->part;
@@ -770,12 +788,13 @@ void weight_grad(seb_net* n, N::GemmGroup& G, N::RedJobs& R, const bf16* A, cons
     R.n += 1;
 }
 
-void run_reductions(const N::RedJobs& R, hipStream_t s) {
+int red_blocks(const N::RedJobs& R) {
     const N::RedJob& last = R.j[R.n - 1];
-    hipLaunchKernelGGL(N::reduce_split_kernel, dim3(last.block0 + last.blocks), dim3(256), 0, s, R);
+    return last.block0 + last.blocks;
 }
 
-// Adds a column-sum job (see colsum_kernel) to J; run_colsums launches them.
+// Adds a column-sum job (see colsum_body) to J (run by prep_kernel and
+// finish_kernel).
 void add_colsum(N::ColJobs& J, seb_net* n, const bf16* D, int64_t ld, int M, int Nn, const float* w,
                 float* dst) {
     // rows per block: kColSteps steps of 256 / Nn rows, more when that would
@@ -808,11 +827,14 @@ void add_colsum(N::ColJobs& J, seb_net* n, const bf16* D, int64_t ld, int M, int
     J.n += 1;
 }
 
-void run_colsums(const N::ColJobs& J, hipStream_t s) {
+int col_blocks(const N::ColJobs& J) {
     const N::ColJob& last = J.j[J.n - 1];
-    hipLaunchKernelGGL(N::colsum_kernel, dim3(last.block0 + last.blocks), dim3(256), 0, s, J);
-    hipLaunchKernelGGL(N::colsum_finish_kernel, dim3(last.out0 + last.N * (last.w ? 2 : 1)), dim3(256), 0,
-                       s, J);
+    return last.block0 + last.blocks;
+}
+
+int col_outputs(const N::ColJobs& J) {
+    const N::ColJob& last = J.j[J.n - 1];
+    return last.out0 + last.N * (last.w ? 2 : 1);
 }
 
 int check_batch(const seb_net* n, const seb_train_batch* b, bool need_labels) {
@@ -1110,9 +1132,18 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     add_transpose(tj, n->da2, r2, N::C2, N::C2, n->da2t, r2);
     add_transpose(tj, n->A2, r2, N::K2P, N::K2P, n->A2t, r2);
     add_transpose(tj, n->da1, r1, N::C1, N::C1, n->da1t, r1);
-    run_transposes(tj, s);
-    // Weight gradients (split-K products now, their sums below) and bias
-    // gradients.
+    N::ColJobs cj;
+    cj.n = 0;
+    add_colsum(cj, n, n->dy, 32, B, N::NOUT, nullptr, g + N::OFF_B5);
+    add_colsum(cj, n, n->da4, N::H2, B, N::H2, nullptr, g + N::OFF_B4);
+    add_colsum(cj, n, n->da3, N::H1, B, N::H1, n->sc, g + N::OFF_WY);
+    add_colsum(cj, n, n->da3, N::H1, B, N::H1, nullptr, g + N::OFF_B3);
+    add_colsum(cj, n, n->da2, N::C2, r2, N::C2, nullptr, g + N::OFF_B2);
+    add_colsum(cj, n, n->da1, N::C1, r1, N::C1, nullptr, g + N::OFF_B1);
+    // every transpose and the bias gradients' first pass, in one launch
+    const int trb = tr_blocks(tj);
+    hipLaunchKernelGGL(N::prep_kernel, dim3(trb + col_blocks(cj)), dim3(256), 0, s, tj, trb, cj);
+    // weight gradients: split-K products, one grouped launch
     N::GemmGroup gg;
     gg.n = 0;
     N::RedJobs rj;
@@ -1123,16 +1154,9 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     weight_grad(n, gg, rj, n->da2t, n->A2t, N::C2, N::K2P, r2, kConvChunk, 2, g + N::OFF_W2);
     weight_grad(n, gg, rj, n->da1t, n->A1t, N::C1, N::K1P, r1, kConvChunk, 1, g + N::OFF_W1);
     run_group(gg, s);
-    N::ColJobs cj;
-    cj.n = 0;
-    add_colsum(cj, n, n->dy, 32, B, N::NOUT, nullptr, g + N::OFF_B5);
-    add_colsum(cj, n, n->da4, N::H2, B, N::H2, nullptr, g + N::OFF_B4);
-    add_colsum(cj, n, n->da3, N::H1, B, N::H1, n->sc, g + N::OFF_WY);
-    add_colsum(cj, n, n->da3, N::H1, B, N::H1, nullptr, g + N::OFF_B3);
-    add_colsum(cj, n, n->da2, N::C2, r2, N::C2, nullptr, g + N::OFF_B2);
-    add_colsum(cj, n, n->da1, N::C1, r1, N::C1, nullptr, g + N::OFF_B1);
-    run_colsums(cj, s);      // every bias gradient, in two launches
-    run_reductions(rj, s);   // every weight gradient's split sums, in one
+    // the bias gradients' block sums and the weight gradients' split sums, in one launch
+    const int co = col_outputs(cj);
+    hipLaunchKernelGGL(N::finish_kernel, dim3(co + red_blocks(rj)), dim3(256), 0, s, cj, co, rj);
 
     if (grad_dev) {
         e = hipMemcpyAsync(grad_dev, g, N::N_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, s);
