@@ -547,18 +547,6 @@ __global__ __launch_bounds__(256) void finish_kernel(const ColJobs C, int col_ou
         reduce_split_body(R, (int)blockIdx.x - col_outputs);
 }
 
-__global__ __launch_bounds__(256) void adam_kernel(float* theta, float* m, float* v, const float* g,
-                                                   int64_t n, float lr, float c1, float c2) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const float gi = g[i];
-    const float mi = 0.9f * m[i] + 0.1f * gi;
-    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    theta[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
-}
-
 // bf16 weight copies in GEMM layouts (see PackedWeights).
 __global__ __launch_bounds__(256) void pack_kernel(const float* th, PackedWeights w) {
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -596,6 +584,49 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* th, PackedWeight
     if (i < H2 * 32) {
         const int c = i / 32, o = i % 32;
         w.w5t[i] = to_bf16(o < NOUT ? th[OFF_W5 + o * H2 + c] : 0.f);
+    }
+}
+
+// Adam step fused with the bf16 refresh: parameter i's new value also goes
+// to its places in the packed GEMM copies, the inverse of pack_kernel's
+// mapping (the copies' padding, written by pack_kernel, never changes).
+__global__ __launch_bounds__(256) void adam_pack_kernel(float* theta, float* m, float* v, const float* g,
+                                                        int64_t n, float lr, float c1, float c2,
+                                                        PackedWeights w) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float th = theta[i] - lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+    theta[i] = th;
+    const bf16 b = to_bf16(th);
+    if (i >= OFF_W1 && i < OFF_W1 + C1 * K1) {
+        const int j = (int)(i - OFF_W1), o = j / K1, c = j % K1;
+        w.w1[o * K1P + c] = b;
+    } else if (i >= OFF_W2 && i < OFF_W2 + C2 * K2) {
+        const int j = (int)(i - OFF_W2), o = j / K2, t = j % K2;
+        const int c = (t % 9) * 16 + t / 9;          // column (tap, channel) of parameter (channel, tap)
+        w.w2[o * K2P + c] = b;
+        w.w2t[c * C2 + o] = b;
+    } else if (i >= OFF_W3 && i < OFF_W3 + (int64_t)H1 * F) {
+        const int j = (int)(i - OFF_W3), o = j / F, c = j % F;
+        w.w3[j] = b;
+        w.w3t[c * H1 + o] = b;
+        const int kk = c / 16, h = (c % 16) / 8, e = c % 8, t = o / 32, l = o % 32 + 32 * h;
+        w.w3f[(((int64_t)kk * 4 + t) * 64 + l) * 8 + e] = b;
+    } else if (i >= OFF_W4 && i < OFF_W4 + H2 * H1) {
+        const int j = (int)(i - OFF_W4), o = j / H1, c = j % H1;
+        w.w4[j] = b;
+        w.w4t[c * H2 + o] = b;
+        w.w4h[j] = (f16)(float)b;
+    } else if (i >= OFF_W5 && i < OFF_W5 + NOUT * H2) {
+        const int j = (int)(i - OFF_W5), o = j / H2, c = j % H2;
+        w.w5[o * H2 + c] = b;
+        w.w5h[o * H2 + c] = (f16)(float)b;
+        w.w5t[c * 32 + o] = b;
     }
 }
 
@@ -1164,9 +1195,8 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
         n->step += 1;
         const double c1 = 1.0 / (1.0 - std::pow(0.9, (double)n->step));
         const double c2 = 1.0 / (1.0 - std::pow(0.999, (double)n->step));
-        hipLaunchKernelGGL(N::adam_kernel, dim3(blocks_for(N::N_PARAMS)), dim3(256), 0, s, n->theta,
-                           n->m, n->v, g, N::N_PARAMS, lr, (float)c1, (float)c2);
-        e = pack(n, s);
+        hipLaunchKernelGGL(N::adam_pack_kernel, dim3(blocks_for(N::N_PARAMS)), dim3(256), 0, s, n->theta,
+                           n->m, n->v, g, N::N_PARAMS, lr, (float)c1, (float)c2, n->pw);
     }
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return net_fail(SEB_ERR_HIP, hipGetErrorString(e));
