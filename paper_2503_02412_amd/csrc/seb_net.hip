@@ -391,11 +391,18 @@ __global__ __launch_bounds__(256) void loss_kernel(const float* y, int64_t ldy, 
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void finish_loss_kernel(const float* partial, int n, int B, float* out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// The loss: the mean over the batch of the loss kernel's per-block sums.
+struct LossJob {
+    const float* partial;
+    int n, B;
+    float* out;                  // null: no loss asked for
+};
+
+__device__ __forceinline__ void finish_loss_body(const LossJob& L) {
+    if (threadIdx.x != 0) return;
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += partial[i];
-    *out = (float)(s / B);
+    for (int i = 0; i < L.n; ++i) s += L.partial[i];
+    *L.out = (float)(s / L.B);
 }
 
 // Sums of the split-K partial products part[z][M][N] over z, written to the
@@ -531,8 +538,8 @@ __device__ __forceinline__ void colsum_finish_body(const ColJobs& J, int bid) {
 // The backward pass's two launches after its input gradients and products:
 // prep_kernel runs every transpose (workgroups [0, tr_blocks)) and the first
 // pass of every column sum (the rest); finish_kernel adds every column sum's
-// block partials (workgroups [0, col_outputs)) and every weight gradient's
-// split-K partials (the rest).
+// block partials (workgroups [0, col_outputs)), every weight gradient's
+// split-K partials (the next red_blocks) and, when asked for, the loss.
 __global__ __launch_bounds__(256) void prep_kernel(const TrJobs T, int tr_blocks, const ColJobs C) {
     if ((int)blockIdx.x < tr_blocks)
         transpose_body(T, blockIdx.x);
@@ -540,11 +547,14 @@ __global__ __launch_bounds__(256) void prep_kernel(const TrJobs T, int tr_blocks
         colsum_body(C, (int)blockIdx.x - tr_blocks);
 }
 
-__global__ __launch_bounds__(256) void finish_kernel(const ColJobs C, int col_outputs, const RedJobs R) {
+__global__ __launch_bounds__(256) void finish_kernel(const ColJobs C, int col_outputs, const RedJobs R,
+                                                     int red_blocks, const LossJob L) {
     if ((int)blockIdx.x < col_outputs)
         colsum_finish_body(C, blockIdx.x);
-    else
+    else if ((int)blockIdx.x < col_outputs + red_blocks)
         reduce_split_body(R, (int)blockIdx.x - col_outputs);
+    else
+        finish_loss_body(L);     // one more workgroup when the loss is asked for
 }
 
 // bf16 weight copies in GEMM layouts (see PackedWeights).
@@ -1119,8 +1129,11 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     const int lb = (B + 255) / 256;
     hipLaunchKernelGGL(N::loss_kernel, dim3(lb), dim3(256), 0, s, n->y, (int64_t)N::NOUT, n->tgt, B,
                        n->dy, n->lpart);
-    if (loss_dev) hipLaunchKernelGGL(N::finish_loss_kernel, dim3(1), dim3(64), 0, s, n->lpart, lb, B,
-                                     loss_dev);
+    N::LossJob lj;             // finished in the backward pass's last launch
+    lj.partial = n->lpart;
+    lj.n = lb;
+    lj.B = B;
+    lj.out = loss_dev;
     // Input gradients, layer by layer, gated by the forward pass's ReLUs.
     // fc3
     N::GemmArgs ga = gemm_args(n->dy, 32, n->pw.w5t, 32, B, N::H2, 32);
@@ -1187,7 +1200,9 @@ int seb_net_train_step(seb_net* n, const seb_train_batch* bt, float lr, float* l
     run_group(gg, s);
     // the bias gradients' block sums and the weight gradients' split sums, in one launch
     const int co = col_outputs(cj);
-    hipLaunchKernelGGL(N::finish_kernel, dim3(co + red_blocks(rj)), dim3(256), 0, s, cj, co, rj);
+    const int rb = red_blocks(rj);
+    hipLaunchKernelGGL(N::finish_kernel, dim3(co + rb + (loss_dev ? 1 : 0)), dim3(256), 0, s, cj, co, rj, rb,
+                       lj);
 
     if (grad_dev) {
         e = hipMemcpyAsync(grad_dev, g, N::N_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, s);
