@@ -309,8 +309,9 @@ def bench_surrogate(torch, seb, train_steps: int = 3000, eval_maps: int = 4, p=N
                     f"{p.fp_length}x{p.fp_width} m on {p.fp_nl}x{p.fp_nw} samples",
         "train_steps": train_steps, "train_batch": 4096,
         "train_samples_per_s": train_steps * 4096 / t_train, "label_seconds": t_data,
-        # algorithmic MFMA work of a training sample: forward + two backward
-        # products per layer, minus conv1's unneeded data gradient
+        # algorithmic work of a training sample's products: forward + two
+        # backward products per layer, minus conv1's unneeded data gradient
+        # (all on MFMA but conv1's forward, 11% of it, on the vector ALU)
         "train_mfma_tflops": train_steps * 4096 / t_train * TRAIN_FLOP_PER_SAMPLE / 1e12,
         "train_mfma_frac_of_bf16_peak":
             train_steps * 4096 / t_train * TRAIN_FLOP_PER_SAMPLE / 1e12 / VENDOR_BF16_PEAK_TFLOPS,

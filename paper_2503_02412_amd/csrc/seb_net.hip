@@ -176,19 +176,24 @@ __device__ __forceinline__ bool ref_height(const BatchArgs& a, int mi, int cy, i
     return n > 0.f;
 }
 
-// conv1 im2col: A1[(b*121 + a*11 + bb)][c*16 + i*4 + j]; yaw features and targets.
-// One thread per row (sample b, conv1 position (a, bb)): the 5 x 5 cells
-// under its 4 x 4 window and the next row and column (for the slopes) are
-// read once, and the row's 64 entries leave as eight 16-byte stores (and,
-// when A1t is given, as the row's column of the transpose, where a wave's
-// lanes write 64 consecutive entries of each row of A1t).  Input
-// channels at cell (y, x), with k the known flag and h the height (0 where
-// unknown): x-slope k(y,x) k(y,x+1) (h(y,x+1) - h(y,x)) / res, y-slope the
-// same with (y+1, x), and k(y,x).
-__global__ __launch_bounds__(256) void im2col1_kernel(const BatchArgs a, bf16* A1, bf16* A1t, float* sc,
-                                                      float* tgt) {
+// conv1 on its im2col rows, row (b*121 + a*11 + bb) column c*16 + i*4 + j;
+// yaw features and targets.  One thread per row (sample b, conv1 position
+// (a, bb)): the 5 x 5 cells under its 4 x 4 window and the next row and
+// column (for the slopes) are read once, the row's 48 inputs are rounded to
+// bf16, and the 16 outputs ReLU(b1 + W1 . row) go out as two 16-byte stores
+// of bf16 (with FP32 products and sums, as the MFMA products of the other
+// layers); in training the row is also written as a column of the transposed
+// im2col A1t (a wave's lanes write 64 consecutive entries of each of its
+// rows), for conv1's weight gradient.  Input channels at cell (y, x), with k
+// the known flag and h the height (0 where unknown): x-slope k(y,x) k(y,x+1)
+// (h(y,x+1) - h(y,x)) / res, y-slope the same with (y+1, x), and k(y,x).
+__global__ __launch_bounds__(256) void im2col1_kernel(const BatchArgs a, const bf16* w1, const float* b1,
+                                                      bf16* o1, bf16* A1t, float* sc, float* tgt) {
+    __shared__ float ws[C1][K1];             // conv1's weights (their bf16 values)
+    for (int i = threadIdx.x; i < C1 * K1; i += 256) ws[i / K1][i % K1] = from_bf16(w1[(i / K1) * K1P + i % K1]);
+    __syncthreads();
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    static_assert(K1 == 48 && K1P % 8 == 0, "three channels of 4 x 4, padded to 16-byte groups");
+    static_assert(K1 == 48 && K1P % 8 == 0 && C1 == 16, "three channels of 4 x 4; 16 outputs");
     if (idx < (int64_t)a.B * P1 * P1) {
         const int pos = (int)(idx % (P1 * P1));
         const int b = (int)(idx / (P1 * P1));
@@ -199,29 +204,37 @@ __global__ __launch_bounds__(256) void im2col1_kernel(const BatchArgs a, bf16* A
         for (int i = 0; i < 5; ++i)
 #pragma unroll
             for (int j = 0; j < 5; ++j) h[i][j] = map_at(a, mi, y0 + i, x0 + j, &v[i][j]);
-        bf16x8* dst = reinterpret_cast<bf16x8*>(A1 + idx * K1P);
+        float in[K1];                          // the row's inputs, rounded to bf16
 #pragma unroll
-        for (int g = 0; g < K1P / 8; ++g) {
-            bf16x8 o;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int col = 8 * g + e;
-                const int c = col / 16, i = (col / 4) % 4, j = col % 4;
-                float val = 0.f;
-                if (c == 0)
-                    val = v[i][j] * v[i][j + 1] * (h[i][j + 1] - h[i][j]) * a.inv_res;
-                else if (c == 1)
-                    val = v[i][j] * v[i + 1][j] * (h[i + 1][j] - h[i][j]) * a.inv_res;
-                else if (c == 2)
-                    val = v[i][j];
-                o[e] = to_bf16(val);
-            }
-            dst[g] = o;
-            if (A1t) {                          // training: the transpose too, A1t[col][row]
-#pragma unroll
-                for (int e = 0; e < 8; ++e) A1t[(int64_t)(8 * g + e) * ((int64_t)a.B * P1 * P1) + idx] = o[e];
-            }
+        for (int col = 0; col < K1; ++col) {
+            const int c = col / 16, i = (col / 4) % 4, j = col % 4;
+            float val;
+            if (c == 0)
+                val = v[i][j] * v[i][j + 1] * (h[i][j + 1] - h[i][j]) * a.inv_res;
+            else if (c == 1)
+                val = v[i][j] * v[i + 1][j] * (h[i + 1][j] - h[i][j]) * a.inv_res;
+            else
+                val = v[i][j];
+            in[col] = from_bf16(to_bf16(val));
         }
+        if (A1t) {                             // training: the transposed im2col, A1t[col][row]
+            const int64_t rows = (int64_t)a.B * P1 * P1;
+#pragma unroll
+            for (int col = 0; col < K1P; ++col)
+                A1t[(int64_t)col * rows + idx] = to_bf16(col < K1 ? in[col] : 0.f);
+        }
+        // conv1: o1[row][o] = bf16(ReLU(b1[o] + sum_col W1[o][col] in[col]))
+        bf16x8 out[2];
+#pragma unroll
+        for (int o = 0; o < C1; ++o) {
+            float acc = 0.f;
+#pragma unroll
+            for (int col = 0; col < K1; ++col) acc = fmaf(ws[o][col], in[col], acc);
+            out[o / 8][o % 8] = to_bf16(fmaxf(acc + b1[o], 0.f));
+        }
+        bf16x8* dst = reinterpret_cast<bf16x8*>(o1 + idx * C1);
+        dst[0] = out[0];
+        dst[1] = out[1];
     }
     if (idx < a.B) {
         const int b = (int)idx;
@@ -690,7 +703,7 @@ struct seb_net {
     float* grad = nullptr;
     N::PackedWeights pw{};
     // workspace (max_batch rows)
-    bf16 *A1 = nullptr, *A1t = nullptr, *o1 = nullptr, *da1 = nullptr, *da1t = nullptr;
+    bf16 *A1t = nullptr, *o1 = nullptr, *da1 = nullptr, *da1t = nullptr;
     bf16 *A2 = nullptr, *A2t = nullptr, *f = nullptr, *ft = nullptr, *da2 = nullptr, *da2t = nullptr;
     bf16 *h1 = nullptr, *h1t = nullptr, *da3 = nullptr, *da3t = nullptr;
     bf16 *h2 = nullptr, *h2t = nullptr, *da4 = nullptr, *da4t = nullptr;
@@ -914,17 +927,11 @@ hipError_t forward_pass(seb_net* n, const seb_train_batch* bt, float* out, bool 
     const int B = bt->batch;
     const N::BatchArgs ba = batch_args(bt);
     const int64_t r1 = (int64_t)B * N::P1 * N::P1, r2 = (int64_t)B * N::P2 * N::P2;
-    hipLaunchKernelGGL(N::im2col1_kernel, dim3(blocks_for(r1)), dim3(256), 0, s, ba, n->A1,
-                       train ? n->A1t : nullptr, n->sc, n->tgt);
-    N::GemmArgs g = gemm_args(n->A1, N::K1P, n->pw.w1, N::K1P, (int)r1, N::C1, N::K1P);
-    g.bias = n->theta + N::OFF_B1;
-    g.relu = 1;
-    g.Cb = n->o1;
-    g.ldcb = N::C1;
-    gemm(g, s);
+    hipLaunchKernelGGL(N::im2col1_kernel, dim3(blocks_for(r1)), dim3(256), 0, s, ba, n->pw.w1,
+                       n->theta + N::OFF_B1, n->o1, train ? n->A1t : nullptr, n->sc, n->tgt);
     hipLaunchKernelGGL(N::im2col2_kernel, dim3(blocks_for(r2 * (N::K2P / 16))), dim3(256), 0, s, n->o1,
                        n->A2, B);
-    g = gemm_args(n->A2, N::K2P, n->pw.w2, N::K2P, (int)r2, N::C2, N::K2P);
+    N::GemmArgs g = gemm_args(n->A2, N::K2P, n->pw.w2, N::K2P, (int)r2, N::C2, N::K2P);
     g.bias = n->theta + N::OFF_B2;
     g.relu = 1;
     g.Cb = n->f;
@@ -998,8 +1005,7 @@ int seb_net_create(uint64_t seed, int32_t max_batch, seb_net** out) {
               dalloc(n, &n->pw.w3t, N::F * N::H1) && dalloc(n, &n->pw.w4t, N::H1 * N::H2) &&
               dalloc(n, &n->pw.w5t, N::H2 * 32) && dalloc(n, &n->pw.w4h, N::H2 * N::H1) &&
               dalloc(n, &n->pw.w3f, N::H1 * N::F) &&
-              dalloc(n, &n->pw.w5h, 16 * N::H2) && dalloc(n, &n->A1, r1 * N::K1P) &&
-              dalloc(n, &n->A1t, r1 * N::K1P) && dalloc(n, &n->o1, r1 * N::C1) &&
+              dalloc(n, &n->pw.w5h, 16 * N::H2) && dalloc(n, &n->A1t, r1 * N::K1P) && dalloc(n, &n->o1, r1 * N::C1) &&
               dalloc(n, &n->da1, r1 * N::C1) && dalloc(n, &n->da1t, r1 * N::C1) &&
               dalloc(n, &n->A2, r2 * N::K2P) && dalloc(n, &n->A2t, r2 * N::K2P) &&
               dalloc(n, &n->dA2, r2 * N::K2P) && dalloc(n, &n->f, Bm * N::F) &&
